@@ -1,0 +1,244 @@
+"""Pins for the FP64 SPME oracle (O1-O10) against what mathematics fixes.
+
+The method is the paper's long-range pipeline (section III.A): spread, FFT,
+Green's-function multiply, inverse FFT, interpolate.  Nothing in the paper
+prints a worked example, so the oracle is pinned by:
+  * brute-force Ewald reciprocal sums (the quantity SPME converges to),
+  * published lattice constants (NaCl Madelung, simple-cubic Wigner),
+  * finite differences of its own energy (forces, virial, beta-derivative),
+  * exact invariants (charge sum, Parseval, symmetry, translations).
+A dropped term, wrong sign, wrong index offset or transposed axis in any of
+O1-O10 breaks at least one of these.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_12617_amd import inputs
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "constants.json")))
+
+
+def small_system(seed=3, n=8, L=10.0):
+    return inputs.random_neutral(n, L, seed)
+
+
+def three_waters(seed=11, L=9.0):
+    pos, q, box = inputs.water_box(3, L, seed)
+    return pos, q, box
+
+
+def test_charge_sum_and_unit_charge_grid(orc):
+    pos, q, box = small_system()
+    r = orc.spme(pos, q, box, 16, 4, 0.35, want_grids=True)
+    assert r["Q"].sum() == pytest.approx(q.sum(), abs=1e-13 * np.abs(q).sum())
+    # a unit charge sitting on grid point (5,7,9): weights 1/6, 2/3, 1/6 on the
+    # three points below it along each axis, tensor product over axes
+    L = 16.0
+    r = orc.spme(np.array([[5.0, 7.0, 9.0]]), np.array([1.0]), np.diag([L] * 3), 16, 4, 0.35,
+                 want_grids=True)
+    w = {2: 1.0 / 6.0, 3: 2.0 / 3.0, 4: 1.0 / 6.0}
+    expect = np.zeros((16, 16, 16))
+    for dz, wz in w.items():
+        for dy, wy in w.items():
+            for dx, wx in w.items():
+                expect[9 - 5 + dz, 7 - 5 + dy, 5 - 5 + dx] = wz * wy * wx
+    np.testing.assert_allclose(r["Q"], expect, atol=1e-15)
+
+
+def test_permutation_invariance(orc):
+    pos, q, box = small_system(n=12)
+    perm = np.random.default_rng(0).permutation(len(q))
+    a = orc.spme(pos, q, box, 16, 4, 0.35, want_grids=True)
+    b = orc.spme(pos[perm], q[perm], box, 16, 4, 0.35, want_grids=True)
+    np.testing.assert_allclose(a["Q"], b["Q"], atol=1e-14)
+    np.testing.assert_allclose(a["forces"][perm], b["forces"], rtol=1e-11, atol=1e-14)
+    assert a["E"] == pytest.approx(b["E"], rel=1e-13)
+
+
+def test_energy_equals_half_Q_phi_and_scales_quadratically(orc):
+    pos, q, box = three_waters()
+    r = orc.spme(pos, q, box, 16, 6, 0.4, want_grids=True)
+    assert 0.5 * np.sum(r["Q"] * r["phi"]) == pytest.approx(r["E"], rel=1e-12)
+    r2 = orc.spme(pos, 2.5 * q, box, 16, 6, 0.4)
+    assert r2["E"] == pytest.approx(6.25 * r["E"], rel=1e-13)
+    np.testing.assert_allclose(r2["forces"], 6.25 * r["forces"], rtol=1e-12, atol=1e-15)
+    # the Coulomb constant is a pure prefactor
+    r3 = orc.spme(pos, q, box, 16, 6, 0.4, coulomb=332.0637)
+    assert r3["E"] == pytest.approx(332.0637 * r["E"], rel=1e-13)
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_forces_are_minus_gradient(orc, p):
+    pos, q, box = small_system(n=6)
+    K, beta, h = 16, 0.35, 1e-5
+    F = orc.spme(pos, q, box, K, p, beta)["forces"]
+    for i in (0, 3, 5):
+        for c in range(3):
+            pp = pos.copy()
+            pp[i, c] += h
+            pm = pos.copy()
+            pm[i, c] -= h
+            fd = -(orc.spme(pp, q, box, K, p, beta)["E"] - orc.spme(pm, q, box, K, p, beta)["E"]) / (2 * h)
+            assert F[i, c] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_net_force_is_minus_translation_derivative(orc):
+    # SPME is not exactly translation invariant; the net force equals minus
+    # the derivative of E under a rigid translation (not zero).
+    pos, q, box = three_waters()
+    K, p, beta, h = 12, 4, 0.35, 1e-5
+    F = orc.spme(pos, q, box, K, p, beta)["forces"]
+    for c in range(3):
+        d = np.zeros(3)
+        d[c] = h
+        fd = -(orc.spme(pos + d, q, box, K, p, beta)["E"] - orc.spme(pos - d, q, box, K, p, beta)["E"]) / (2 * h)
+        assert F[:, c].sum() == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+def _strained(pos, box, a, b, h):
+    eps = np.zeros((3, 3))
+    eps[a, b] = h
+    T = np.eye(3) + eps
+    return pos @ T.T, box @ T.T
+
+
+@pytest.mark.parametrize("ab", [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)])
+def test_virial_is_minus_strain_derivative(orc, ab):
+    pos, q, box = three_waters()
+    box = np.diag([9.0, 10.0, 11.0])
+    K, p, beta, h = 16, 4, 0.4, 1e-6
+    r = orc.spme(pos, q, box, K, p, beta)
+    idx = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}[ab]
+    pp, bp = _strained(pos, box, ab[0], ab[1], h)
+    pm, bm = _strained(pos, box, ab[0], ab[1], -h)
+    fd = -(orc.spme(pp, q, bp, K, p, beta)["E"] - orc.spme(pm, q, bm, K, p, beta)["E"]) / (2 * h)
+    assert r["virial"][idx] == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(r["E"]))
+    # the transposed shear gives the same (symmetric tensor)
+    if ab[0] != ab[1]:
+        pp, bp = _strained(pos, box, ab[1], ab[0], h)
+        pm, bm = _strained(pos, box, ab[1], ab[0], -h)
+        fd2 = -(orc.spme(pp, q, bp, K, p, beta)["E"] - orc.spme(pm, q, bm, K, p, beta)["E"]) / (2 * h)
+        assert fd2 == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(r["E"]))
+
+
+def test_virial_trace_identity(orc):
+    # trace P = E - beta dE/dbeta (at fixed grid), an exact identity of O7/O8
+    pos, q, box = small_system(n=10)
+    K, p, beta, h = 16, 4, 0.35, 1e-6
+    r = orc.spme(pos, q, box, K, p, beta)
+    dEdb = (orc.spme(pos, q, box, K, p, beta + h)["E"] - orc.spme(pos, q, box, K, p, beta - h)["E"]) / (2 * h)
+    assert r["virial"][:3].sum() == pytest.approx(r["E"] - beta * dEdb, rel=1e-7)
+
+
+def test_triclinic_matches_strained_orthorhombic_energy(orc):
+    # in a sheared cell the same fractional configuration gives a different E;
+    # check O1/O6 handle a general cell by comparing against exact Ewald
+    pos, q, box = small_system(n=6)
+    T = np.array([[1.0, 0.0, 0.0], [0.2, 1.0, 0.0], [-0.1, 0.15, 1.0]])
+    tb = box @ T.T
+    tp = pos @ T.T
+    spme = orc.spme(tp, q, tb, 48, 8, 0.4)
+    ex = orc.ewald_recip(tp, q, tb, 0.4, 14)
+    assert spme["E"] == pytest.approx(ex["E"], rel=1e-8)
+    np.testing.assert_allclose(spme["forces"], ex["forces"], atol=1e-8 * np.abs(ex["forces"]).max())
+    np.testing.assert_allclose(spme["virial"], ex["virial"], atol=1e-8 * abs(ex["E"]))
+
+
+def test_periodic_image_and_grid_translation(orc):
+    pos, q, box = small_system(n=8, L=16.0)
+    K, p, beta = 16, 4, 0.35
+    a = orc.spme(pos, q, box, K, p, beta)
+    shifted = pos.copy()
+    shifted[2] += np.array([16.0, -32.0, 48.0])
+    b = orc.spme(shifted, q, box, K, p, beta)
+    assert b["E"] == pytest.approx(a["E"], rel=1e-12)
+    np.testing.assert_allclose(b["forces"], a["forces"], rtol=1e-10, atol=1e-13)
+    # a rigid translation by one whole grid spacing only relabels grid points
+    c = orc.spme(pos + np.array([1.0, 0.0, 2.0]), q, box, K, p, beta)
+    assert c["E"] == pytest.approx(a["E"], rel=1e-12)
+    np.testing.assert_allclose(c["forces"], a["forces"], rtol=1e-10, atol=1e-13)
+
+
+def test_rock_salt_forces_vanish(orc):
+    pos, q, box = inputs.rock_salt(4, 2.0)
+    r = orc.spme(pos, q, box, 16, 4, 0.6)
+    assert np.abs(r["forces"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("system", ["pair", "waters", "ions"])
+def test_converges_to_exact_ewald(orc, system):
+    if system == "pair":
+        pos = np.array([[1.0, 2.0, 3.0], [4.5, 2.5, 6.0]])
+        q = np.array([1.0, -1.0])
+        box = np.diag([10.0] * 3)
+    elif system == "waters":
+        pos, q, box = three_waters()
+    else:
+        pos, q, box = small_system(n=8)
+    beta = 0.35
+    ex = orc.ewald_recip(pos, q, box, beta, 14)
+    errs = []
+    for K, p in [(16, 4), (32, 4), (32, 6), (64, 8)]:
+        r = orc.spme(pos, q, box, K, p, beta)
+        errs.append((abs(r["E"] - ex["E"]) / abs(ex["E"]),
+                     np.linalg.norm(r["forces"] - ex["forces"]) / np.linalg.norm(ex["forces"])))
+    # monotone in grid size and order, and the finest setting is essentially exact
+    assert errs[0][0] > errs[1][0] > errs[3][0]
+    assert errs[0][1] > errs[1][1] > errs[2][1] > errs[3][1]
+    assert errs[3][0] < 1e-10 and errs[3][1] < 1e-9
+    r = orc.spme(pos, q, box, 64, 8, beta)
+    np.testing.assert_allclose(r["virial"], ex["virial"], atol=1e-9 * abs(ex["E"]))
+
+
+def test_exact_ewald_harness_is_self_consistent(orc):
+    pos, q, box = small_system(n=5)
+    beta, h = 0.4, 1e-5
+    ex = orc.ewald_recip(pos, q, box, beta, 12)
+    rs = orc.ewald_real(pos, q, box, beta, nimg=2)
+    for i, c in [(0, 0), (2, 1), (4, 2)]:
+        pp = pos.copy()
+        pp[i, c] += h
+        pm = pos.copy()
+        pm[i, c] -= h
+        fd = -(orc.ewald_recip(pp, q, box, beta, 12)["E"] - orc.ewald_recip(pm, q, box, beta, 12)["E"]) / (2 * h)
+        assert ex["forces"][i, c] == pytest.approx(fd, rel=1e-6, abs=1e-10)
+        fdr = -(orc.ewald_real(pp, q, box, beta, nimg=2)["E_real"] - orc.ewald_real(pm, q, box, beta, nimg=2)["E_real"]) / (2 * h)
+        assert rs["forces"][i, c] == pytest.approx(fdr, rel=1e-6, abs=1e-10)
+
+
+def test_total_ewald_energy_is_beta_independent(orc):
+    pos, q, box = small_system(n=8)
+    tot = []
+    for beta in (0.3, 0.45):
+        rec = orc.ewald_recip(pos, q, box, beta, 14)["E"]
+        rs = orc.ewald_real(pos, q, box, beta, nimg=2)
+        tot.append(rec + rs["E_real"] + rs["E_self"])
+    assert tot[0] == pytest.approx(tot[1], rel=1e-10)
+
+
+@pytest.mark.parametrize("offset", [(0.0, 0.0, 0.0), (0.37, 1.13, 2.71)])
+def test_nacl_madelung_constant(orc, offset):
+    M, r0, beta = 4, 2.8, 0.5
+    pos, q, box = inputs.rock_salt(M, r0, offset)
+    rec = orc.spme(pos, q, box, 64, 8, beta)["E"]
+    rs = orc.ewald_real(pos, q, box, beta, nimg=1)
+    E = rec + rs["E_real"] + rs["E_self"]
+    madelung = -2.0 * E * r0 / len(q)
+    g = GOLD["madelung_nacl"]
+    assert abs(madelung - g["value"]) <= g["tolerance"]
+
+
+def test_wigner_simple_cubic_constant(orc):
+    L, beta = 10.0, 0.5
+    pos = np.array([[1.3, 4.2, 7.7]])
+    q = np.array([1.0])
+    box = np.diag([L] * 3)
+    rec = orc.spme(pos, q, box, 64, 8, beta)["E"]
+    rs = orc.ewald_real(pos, q, box, beta, nimg=2)
+    background = -np.pi * q.sum() ** 2 / (2.0 * L ** 3 * beta ** 2)
+    xi = 2.0 * L * (rec + rs["E_real"] + rs["E_self"] + background)
+    g = GOLD["wigner_simple_cubic"]
+    assert abs(xi - g["value"]) <= g["tolerance"]
