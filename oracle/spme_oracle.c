@@ -19,6 +19,8 @@
  *   O4  B-spline moduli |b(m)|^2
  *   O5  F(m) = sum_k Q(k) exp(+2 pi i m.k/K)             (unnormalised)
  *   O6  G(m) = c B(m) exp(-pi^2 |m|^2/beta^2) / (pi V |m|^2),  G(0) = 0
+ *       (m = sum_a mt_a a*_a with mt_a = m_a or m_a - K_a, |mt_a| <= K_a/2;
+ *       a Nyquist index K_a/2 counts half as +K_a/2 and half as -K_a/2)
  *   O7  E = 1/2 sum_m G(m) |F(m)|^2
  *   O8  virial P_ab = 1/2 sum_m G|F|^2 (delta_ab - 2 (1 + pi^2|m|^2/beta^2)
  *                                        m_a m_b / |m|^2)
@@ -293,7 +295,12 @@ int orc_spme(const double *pos, const double *q, int N, const double box[9],
   orc_fft3d(K1, K2, K3, re, im, +1);
   double t2s = now_s();
 
-  /* O4 + O6..O8: influence function, energy and virial; F <- G F. */
+  /* O4 + O6..O8: influence function, energy and virial; F <- G F.
+   * A Nyquist index m_a = K_a/2 (K_a even) aliases +K_a/2 and -K_a/2 equally;
+   * its mode is split half and half between the two wave vectors, so G,
+   * the energy and the virial of that mode are averages over the sign
+   * choices (this keeps the off-diagonal virial symmetric under reflection;
+   * in an orthorhombic cell only off-diagonal virial terms are affected). */
   double *bsq[3];
   for (int a = 0; a < 3; ++a) {
     bsq[a] = (double *)malloc(sizeof(double) * (size_t)K[a]);
@@ -301,30 +308,47 @@ int orc_spme(const double *pos, const double *q, int N, const double box[9],
   }
   double E = 0.0, P[6] = {0, 0, 0, 0, 0, 0};
   for (int m3 = 0; m3 < K3; ++m3) {
-    int t3 = (m3 <= K3 / 2) ? m3 : m3 - K3;
     for (int m2 = 0; m2 < K2; ++m2) {
-      int t2 = (m2 <= K2 / 2) ? m2 : m2 - K2;
       for (int m1 = 0; m1 < K1; ++m1) {
-        int tt1 = (m1 <= K1 / 2) ? m1 : m1 - K1;
         long idx = ((long)m3 * K2 + m2) * K1 + m1;
-        double mv[3];
-        for (int c = 0; c < 3; ++c)
-          mv[c] = tt1 * rec[0 + c] + t2 * rec[3 + c] + t3 * rec[6 + c];
-        double msq = dot3(mv, mv);
+        int m[3] = {m1, m2, m3};
+        int mt[3], nyq[3], nq = 0;
+        for (int a = 0; a < 3; ++a) {
+          mt[a] = (m[a] <= K[a] / 2) ? m[a] : m[a] - K[a];
+          nyq[a] = (K[a] % 2 == 0 && 2 * m[a] == K[a]);
+          nq += nyq[a];
+        }
         double G = 0.0;
         if (m1 != 0 || m2 != 0 || m3 != 0) {
           double B = bsq[0][m1] * bsq[1][m2] * bsq[2][m3];
-          G = coulomb * B * exp(-ORC_PI * ORC_PI * msq / (beta * beta)) / (ORC_PI * V * msq);
           double f2 = re[idx] * re[idx] + im[idx] * im[idx];
-          double e = 0.5 * G * f2;
-          double fac = 2.0 * (1.0 + ORC_PI * ORC_PI * msq / (beta * beta)) / msq;
-          E += e;
-          P[0] += e * (1.0 - fac * mv[0] * mv[0]);
-          P[1] += e * (1.0 - fac * mv[1] * mv[1]);
-          P[2] += e * (1.0 - fac * mv[2] * mv[2]);
-          P[3] += e * (0.0 - fac * mv[0] * mv[1]);
-          P[4] += e * (0.0 - fac * mv[0] * mv[2]);
-          P[5] += e * (0.0 - fac * mv[1] * mv[2]);
+          int nvar = 1 << nq;
+          for (int v = 0; v < nvar; ++v) {
+            double ms[3];
+            for (int a = 0, bit = 0; a < 3; ++a) {
+              ms[a] = mt[a];
+              if (nyq[a]) {
+                if ((v >> bit) & 1) ms[a] = -ms[a];
+                ++bit;
+              }
+            }
+            double mv[3];
+            for (int c = 0; c < 3; ++c)
+              mv[c] = ms[0] * rec[0 + c] + ms[1] * rec[3 + c] + ms[2] * rec[6 + c];
+            double msq = dot3(mv, mv);
+            double Gv = coulomb * B * exp(-ORC_PI * ORC_PI * msq / (beta * beta)) /
+                        (ORC_PI * V * msq) / nvar;
+            double e = 0.5 * Gv * f2;
+            double fac = 2.0 * (1.0 + ORC_PI * ORC_PI * msq / (beta * beta)) / msq;
+            G += Gv;
+            E += e;
+            P[0] += e * (1.0 - fac * mv[0] * mv[0]);
+            P[1] += e * (1.0 - fac * mv[1] * mv[1]);
+            P[2] += e * (1.0 - fac * mv[2] * mv[2]);
+            P[3] += e * (0.0 - fac * mv[0] * mv[1]);
+            P[4] += e * (0.0 - fac * mv[0] * mv[2]);
+            P[5] += e * (0.0 - fac * mv[1] * mv[2]);
+          }
         }
         re[idx] *= G;
         im[idx] *= G;

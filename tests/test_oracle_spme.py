@@ -124,6 +124,21 @@ def test_virial_is_minus_strain_derivative(orc, ab):
         assert fd2 == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(r["E"]))
 
 
+def test_virial_reflection_antisymmetry(orc):
+    # mirroring the system through a plane x = const flips the sign of the
+    # xy and xz virial components and leaves the rest; this holds exactly only
+    # if a Nyquist mode counts +K/2 and -K/2 alike
+    pos, q, box = small_system(n=9)
+    K, p, beta = 16, 4, 0.5
+    a = orc.spme(pos, q, box, K, p, beta)
+    m = pos.copy()
+    m[:, 0] = 10.0 - m[:, 0]
+    b = orc.spme(m, q, box, K, p, beta)
+    sgn = np.array([1, 1, 1, -1, -1, 1])
+    np.testing.assert_allclose(b["virial"], sgn * a["virial"], rtol=0, atol=1e-12 * abs(a["E"]))
+    assert abs(a["virial"][3]) > 1e-6 * abs(a["E"])
+
+
 def test_virial_trace_identity(orc):
     # trace P = E - beta dE/dbeta (at fixed grid), an exact identity of O7/O8
     pos, q, box = small_system(n=10)
