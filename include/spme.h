@@ -1,0 +1,176 @@
+/*
+ * spme.h -- C ABI of the MI355X smooth particle-mesh Ewald (SPME)
+ * reciprocal-space step.
+ *
+ * One step takes atom positions and charges and returns the long-range
+ * electrostatic force on every atom, as the paper's long-range pipeline does
+ * each timestep (§III.A): charge spreading with order-p cardinal B-splines
+ * (§III.A.1), forward 3D FFT, multiplication by the Green's function
+ * (influence function) with energy and virial, inverse 3D FFT (§III.A.2),
+ * and force interpolation with B-spline derivatives (§III.A.3).  The
+ * equations are those of the SPME method the paper builds on (Essmann et
+ * al., J. Chem. Phys. 103:8577, 1995):
+ *   Q(k)   = sum_i q_i prod_a M_p(u_ia - k_a)           (charge grid)
+ *   F(m)   = sum_k Q(k) exp(2 pi i m.k/K)               (3D FFT)
+ *   G(m)   = c B(m) exp(-pi^2 |m|^2/beta^2) / (pi V |m|^2),  G(0) = 0
+ *   E      = 1/2 sum_m G(m) |F(m)|^2
+ *   P_ab   = 1/2 sum_m G|F|^2 (delta_ab - 2(1 + pi^2|m|^2/beta^2) m_a m_b/|m|^2)
+ *   phi(k) = sum_m G(m) F(m) exp(-2 pi i m.k/K)         (inverse 3D FFT)
+ *   F_i    = -q_i sum_k phi(k) grad_i prod_a M_p(u_ia - k_a)
+ * with B(m) the product of the squared B-spline moduli along the three axes.
+ *
+ * Units: positions and box in Angstrom, charges in e, energies and forces in
+ * c e^2/A and c e^2/A^2 where c is the Coulomb constant passed at creation
+ * (1.0 by default; 332.0637 gives kcal/mol).
+ *
+ * Memory: the library never allocates device memory.  The caller owns every
+ * device buffer: positions, charges, forces, the energy/virial vector and one
+ * workspace of pme_workspace_bytes() bytes.  Device pointers are plain
+ * addresses (e.g. torch tensor data_ptr()).  A plan is host memory owned by
+ * the library between pme_create and pme_destroy; it is not thread safe and
+ * enqueues all work on the stream given at creation (or pme_set_stream), in
+ * stream order, without host synchronisation except where noted.
+ *
+ * Errors: every call returns a pme_status.  Argument errors are detected on
+ * the host before anything is enqueued.  Conditions only the device can see
+ * (a non-finite coordinate or charge, fixed-point headroom exceeded) raise
+ * sticky flags read by pme_check().  Nothing aborts and no exception crosses
+ * the ABI.
+ *
+ * Supported on the GPU: cubic grids K1 = K2 = K3 = K with
+ * K in {16, 24, 32, 48, 64, 96, 128}, spline order p in {4, 6}, orthorhombic
+ * cells.  Anything else returns PME_EUNSUPPORTED.
+ */
+#ifndef SPME_H
+#define SPME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pme_plan pme_plan;
+
+/* Arithmetic of the step.
+ * PME_FP32_FIXED: B-spline weights, FFTs and the convolution in FP32; the
+ *   charge grid accumulated in 64-bit two's-complement fixed point with
+ *   frac_bits fraction bits (order-free, so bit-identical run to run);
+ *   B-spline moduli, influence function, energy and virial in FP64.
+ * PME_FP64: every stage in FP64 (charge grid accumulated in FP64). */
+typedef enum { PME_FP64 = 0, PME_FP32_FIXED = 1 } pme_precision;
+
+typedef enum {
+  PME_OK = 0,
+  PME_EINVAL = 1,        /* bad argument (null pointer, N out of range, beta <= 0, ...) */
+  PME_EUNSUPPORTED = 2,  /* valid SPME parameters this build does not run (grid, order, cell) */
+  PME_EWORKSPACE = 3,    /* workspace missing, misaligned or smaller than pme_workspace_bytes */
+  PME_EOVERFLOW = 4,     /* fixed-point headroom exceeded (sum |q| 2^F >= 2^52) */
+  PME_EDEVICE = 5,       /* a HIP runtime call failed */
+  PME_ENONFINITE = 6,    /* a position or charge was NaN or infinite */
+  PME_ESTATE = 7         /* call out of order (e.g. pme_solve before pme_spread) */
+} pme_status;
+
+/* Sticky device flags reported by pme_check. */
+#define PME_FLAG_NONFINITE 1u
+#define PME_FLAG_OVERFLOW 2u
+
+/* Bytes of device workspace a plan with these parameters needs (0 when the
+ * parameters are unsupported).  Host only; no device is touched. */
+size_t pme_workspace_bytes(int K1, int K2, int K3, int order, int max_atoms, int precision);
+
+/* Create a plan.
+ *   K1, K2, K3  grid points per axis (§III.A.2: the FFT input volume)
+ *   order       B-spline order p (the paper spreads over 4x4x4 points, p = 4)
+ *   beta        Ewald splitting parameter in 1/A (> 0)
+ *   max_atoms   largest N any later call will pass (>= 0)
+ *   precision   pme_precision
+ *   frac_bits   fixed-point fraction bits F for PME_FP32_FIXED (0 selects 32;
+ *               otherwise 16..40); ignored for PME_FP64
+ *   coulomb     Coulomb constant c (0 selects 1.0)
+ *   workspace   device pointer, 256-byte aligned, >= pme_workspace_bytes();
+ *               owned by the caller, must outlive the plan, must not be used
+ *               by anyone else while the plan exists
+ *   stream      hipStream_t (NULL = the default stream)
+ * Uploads the plan tables (moduli, twiddles) and synchronises the stream
+ * once.  On failure *out is NULL. */
+int pme_create(pme_plan **out, int K1, int K2, int K3, int order, double beta, int max_atoms,
+               int precision, int frac_bits, double coulomb, void *workspace,
+               size_t workspace_bytes, void *stream);
+
+/* Release the host plan.  Does not free the workspace and does not wait for
+ * enqueued work. */
+int pme_destroy(pme_plan *plan);
+
+/* Change the stream subsequent calls enqueue on. */
+int pme_set_stream(pme_plan *plan, void *stream);
+
+/* Charge spreading and the first FFT passes (§III.A.1, first half of
+ * §III.A.2): bins the atoms, spreads them into the fixed-point (or FP64) grid
+ * and transforms it along x (real-to-complex) and y.
+ *   pos  device [N][3] doubles (Angstrom, any image; wrapped internally)
+ *   q    device [N] doubles
+ *   N    0 <= N <= max_atoms
+ *   box  HOST [9] doubles, rows a1, a2, a3; must be diagonal (orthorhombic)
+ * pos and q must stay valid until pme_gather of the same step has been
+ * enqueued (it reads q again). */
+int pme_spread(pme_plan *plan, const double *pos, const double *q, int N, const double box[9]);
+
+/* Green's-function convolution (§III.A.2: the z transform, multiply,
+ * inverse z transform), energy and virial.
+ *   ev   device [7] doubles: E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz (overwritten),
+ *        or NULL to skip writing them. */
+int pme_solve(pme_plan *plan, double *ev);
+
+/* Inverse y and x transforms and force interpolation (§III.A.2 second
+ * corner turn, §III.A.3).
+ *   forces      device [N][3] doubles in the caller's atom order
+ *   accumulate  0 overwrites, 1 adds to the existing values */
+int pme_gather(pme_plan *plan, double *forces, int accumulate);
+
+/* The whole step: pme_spread + pme_solve + pme_gather. */
+int pme_step(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
+             double *forces, int accumulate, double *ev);
+
+/* Keep a copy of the charge grid at each spread (costs K1 K2 K3 x 8 bytes
+ * of extra writes; off by default). */
+int pme_set_debug(pme_plan *plan, int keep_charge_grid);
+
+/* Copy an intermediate grid (enqueued on the plan's stream) to device dst:
+ *   which 0: charge grid [K3][K2][K1], int64 (FP32_FIXED, raw fixed point with
+ *            frac_bits fraction bits) or double (FP64); needs pme_set_debug(1)
+ *            before the spread
+ *   which 1: the half spectrum [K3][K2][K1/2+1] complex (float2 / double2):
+ *            after pme_spread the forward transform of the charge grid along
+ *            x and y; after pme_solve G F transformed back along z
+ *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED) or double */
+int pme_debug_grid(pme_plan *plan, int which, void *dst);
+
+/* Size in bytes of pme_debug_grid(which)'s output (0 for a bad which). */
+size_t pme_debug_grid_bytes(pme_plan *plan, int which);
+
+/* Synchronise the plan's stream, return the sticky device flags
+ * (PME_FLAG_*) in *flags and clear them.  Returns PME_ENONFINITE or
+ * PME_EOVERFLOW when the matching flag was set, else PME_OK. */
+int pme_check(pme_plan *plan, unsigned *flags);
+
+/* Per-kernel timing with HIP events on the plan's stream (off by default).
+ * While enabled every launch is bracketed by events; pme_kernel_times
+ * synchronises, adds the elapsed times of all completed launches into
+ * ms[0..n-1] (kernel order: bin, spread+xy, z-convolution, inverse xy,
+ * gather) and returns the number of steps accumulated in *steps. */
+int pme_kernel_timing(pme_plan *plan, int enable);
+int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
+
+/* Human-readable text for a pme_status. */
+const char *pme_strerror(int code);
+
+/* ABI version (major * 100 + minor). */
+int pme_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPME_H */

@@ -1,0 +1,88 @@
+"""ctypes declarations of libspme.so (the C ABI in include/spme.h).
+
+Argument marshalling only: every step of the SPME path runs in the HIP
+library.  Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspme.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "spme.h")
+
+PME_FP64 = 0
+PME_FP32_FIXED = 1
+PME_FLAG_NONFINITE = 1
+PME_FLAG_OVERFLOW = 2
+
+STATUS = {0: "PME_OK", 1: "PME_EINVAL", 2: "PME_EUNSUPPORTED", 3: "PME_EWORKSPACE",
+          4: "PME_EOVERFLOW", 5: "PME_EDEVICE", 6: "PME_ENONFINITE", 7: "PME_ESTATE"}
+
+_lib = None
+
+
+class SpmeError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        msg = _lib.pme_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({msg})")
+
+
+def declared_functions():
+    """Names of the functions include/spme.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pme_[a-z_]+)\s*\(", text)))
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2009_12617_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.pme_version.restype = i
+    lib.pme_version.argtypes = []
+    lib.pme_strerror.restype = ctypes.c_char_p
+    lib.pme_strerror.argtypes = [i]
+    lib.pme_workspace_bytes.restype = sz
+    lib.pme_workspace_bytes.argtypes = [i, i, i, i, i, i]
+    lib.pme_create.restype = i
+    lib.pme_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, d, i, i, i, d, vp, sz, vp]
+    lib.pme_destroy.restype = i
+    lib.pme_destroy.argtypes = [vp]
+    lib.pme_set_stream.restype = i
+    lib.pme_set_stream.argtypes = [vp, vp]
+    lib.pme_spread.restype = i
+    lib.pme_spread.argtypes = [vp, vp, vp, i, dp]
+    lib.pme_solve.restype = i
+    lib.pme_solve.argtypes = [vp, vp]
+    lib.pme_gather.restype = i
+    lib.pme_gather.argtypes = [vp, vp, i]
+    lib.pme_step.restype = i
+    lib.pme_step.argtypes = [vp, vp, vp, i, dp, vp, i, vp]
+    lib.pme_set_debug.restype = i
+    lib.pme_set_debug.argtypes = [vp, i]
+    lib.pme_debug_grid.restype = i
+    lib.pme_debug_grid.argtypes = [vp, i, vp]
+    lib.pme_debug_grid_bytes.restype = sz
+    lib.pme_debug_grid_bytes.argtypes = [vp, i]
+    lib.pme_check.restype = i
+    lib.pme_check.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
+    lib.pme_kernel_timing.restype = i
+    lib.pme_kernel_timing.argtypes = [vp, i]
+    lib.pme_kernel_times.restype = i
+    lib.pme_kernel_times.argtypes = [vp, dp, i, ctypes.POINTER(ctypes.c_int)]
+    _lib = lib
+    return lib
+
+
+def check(code, what):
+    if code != 0:
+        raise SpmeError(code, what)

@@ -1,0 +1,371 @@
+// C ABI of the SPME step: argument validation, workspace layout, plan tables
+// and launch sequencing.  All device work is enqueued on the plan's stream;
+// the library allocates no device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/spme.h"
+#include "spme_internal.h"
+
+using spme::Args;
+using spme::Layout;
+
+namespace {
+
+constexpr int kMaxAtoms = 1 << 26;
+
+struct TimedLaunch {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
+enum State { kCreated = 0, kSpread = 1, kSolved = 2 };
+
+}  // namespace
+
+struct pme_plan {
+  int K = 0, order = 0, precision = 0, frac_bits = 32, max_atoms = 0;
+  double beta = 0.0, coulomb = 1.0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  Layout lay{};
+  Args cur{};
+  int state = kCreated;
+  int keep_grid = 0;
+  int grid_kept = 0;
+  // host copies of the uploaded tables
+  std::vector<double> bsq;
+  std::vector<double> tw64;
+  std::vector<float> tw32;
+  // per-kernel timing
+  int timing = 0;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_next = 0;
+  std::vector<TimedLaunch> pending;
+  int timed_steps = 0;
+};
+
+namespace {
+
+// Cardinal B-spline M_n at integer arguments 1..n-1 by the order recursion
+// M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x - 1)] / (n - 1).
+double bspline_at(int n, double x) {
+  if (n == 2) return (x >= 0.0 && x <= 2.0) ? 1.0 - std::fabs(x - 1.0) : 0.0;
+  return (x * bspline_at(n - 1, x) + (n - x) * bspline_at(n - 1, x - 1.0)) / (n - 1);
+}
+
+// |b(m)|^2 = 1 / |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2 (even p: no zeros).
+void moduli(int p, int K, double* out) {
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < K; ++m) {
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k <= p - 2; ++k) {
+      const double c = bspline_at(p, k + 1.0);
+      const double ang = 2.0 * pi * (double)((long)m * k % K) / (double)K;
+      re += c * std::cos(ang);
+      im += c * std::sin(ang);
+    }
+    out[m] = 1.0 / (re * re + im * im);
+  }
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int device_error(hipError_t e) { return e == hipSuccess ? PME_OK : PME_EDEVICE; }
+
+hipEvent_t next_event(pme_plan* p) {
+  if (p->event_next == p->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->event_pool.push_back(e);
+  }
+  return p->event_pool[p->event_next++];
+}
+
+template <class F>
+int timed(pme_plan* p, int kernel, F&& launch) {
+  if (!p->timing) return device_error(launch());
+  hipEvent_t a = next_event(p), b = next_event(p);
+  if (!a || !b) return PME_EDEVICE;
+  if (hipEventRecord(a, p->stream) != hipSuccess) return PME_EDEVICE;
+  hipError_t e = launch();
+  if (e != hipSuccess) return PME_EDEVICE;
+  if (hipEventRecord(b, p->stream) != hipSuccess) return PME_EDEVICE;
+  p->pending.push_back({kernel, a, b});
+  return PME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pme_version(void) { return 100; }
+
+const char* pme_strerror(int code) {
+  switch (code) {
+    case PME_OK: return "ok";
+    case PME_EINVAL: return "invalid argument";
+    case PME_EUNSUPPORTED: return "unsupported parameters (grid, spline order or cell shape)";
+    case PME_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case PME_EOVERFLOW: return "fixed-point headroom exceeded (sum |q| 2^F >= 2^52)";
+    case PME_EDEVICE: return "HIP runtime error";
+    case PME_ENONFINITE: return "non-finite position or charge";
+    case PME_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+size_t pme_workspace_bytes(int K1, int K2, int K3, int order, int max_atoms, int precision) {
+  if (K1 != K2 || K2 != K3 || max_atoms < 0 || max_atoms > kMaxAtoms) return 0;
+  Layout L;
+  if (!spme::layout_for(K1, order, max_atoms, precision, &L)) return 0;
+  return L.total;
+}
+
+int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, int max_atoms,
+               int precision, int frac_bits, double coulomb, void* workspace,
+               size_t workspace_bytes, void* stream) {
+  if (out == nullptr) return PME_EINVAL;
+  *out = nullptr;
+  if (K1 < 2 || K2 < 2 || K3 < 2 || order < 3 || !(beta > 0.0) || !is_fin(beta) ||
+      max_atoms < 0 || (precision != PME_FP64 && precision != PME_FP32_FIXED) ||
+      !is_fin(coulomb))
+    return PME_EINVAL;
+  if (frac_bits == 0) frac_bits = 32;
+  if (frac_bits < 16 || frac_bits > 40) return PME_EINVAL;
+  if (coulomb == 0.0) coulomb = 1.0;
+  if (K1 != K2 || K2 != K3 || !spme::grid_supported(K1) || (order != 4 && order != 6) ||
+      max_atoms > kMaxAtoms)
+    return PME_EUNSUPPORTED;
+  Layout L;
+  if (!spme::layout_for(K1, order, max_atoms, precision, &L)) return PME_EUNSUPPORTED;
+  if (workspace == nullptr || workspace_bytes < L.total ||
+      (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
+    return PME_EWORKSPACE;
+
+  pme_plan* p = new (std::nothrow) pme_plan();
+  if (p == nullptr) return PME_EDEVICE;
+  p->K = K1;
+  p->order = order;
+  p->precision = precision;
+  p->frac_bits = frac_bits;
+  p->max_atoms = max_atoms;
+  p->beta = beta;
+  p->coulomb = coulomb;
+  p->ws = static_cast<char*>(workspace);
+  p->ws_bytes = workspace_bytes;
+  p->stream = static_cast<hipStream_t>(stream);
+  p->lay = L;
+
+  // Tables: moduli for the three axes (cubic grid: the same K), twiddles
+  // exp(-2 pi i k / K) rounded once from FP64.
+  const int K = K1;
+  p->bsq.resize(3 * (size_t)K);
+  moduli(order, K, p->bsq.data());
+  std::memcpy(p->bsq.data() + K, p->bsq.data(), sizeof(double) * K);
+  std::memcpy(p->bsq.data() + 2 * K, p->bsq.data(), sizeof(double) * K);
+  const double pi = 3.14159265358979323846;
+  p->tw64.resize(2 * (size_t)K);
+  for (int k = 0; k < K; ++k) {
+    const double ang = 2.0 * pi * (double)k / (double)K;
+    p->tw64[2 * k] = std::cos(ang);
+    p->tw64[2 * k + 1] = -std::sin(ang);
+  }
+  p->tw32.resize(2 * (size_t)K);
+  for (int i = 0; i < 2 * K; ++i) p->tw32[i] = (float)p->tw64[i];
+
+  hipError_t e = spme::prepare_kernels(K, order, precision);
+  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ctrl, 0, 64 * sizeof(unsigned), p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * 3 * K,
+                       hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) {
+    if (precision == PME_FP32_FIXED)
+      e = hipMemcpyAsync(p->ws + L.tw, p->tw32.data(), sizeof(float) * 2 * K,
+                         hipMemcpyHostToDevice, p->stream);
+    else
+      e = hipMemcpyAsync(p->ws + L.tw, p->tw64.data(), sizeof(double) * 2 * K,
+                         hipMemcpyHostToDevice, p->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return PME_EDEVICE;
+  }
+  Args& a = p->cur;
+  a.K = K;
+  a.order = order;
+  a.precision = precision;
+  a.frac_bits = frac_bits;
+  a.beta = beta;
+  a.coulomb = coulomb;
+  a.ws = p->ws;
+  a.lay = L;
+  *out = p;
+  return PME_OK;
+}
+
+int pme_destroy(pme_plan* p) {
+  if (p == nullptr) return PME_EINVAL;
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+  delete p;
+  return PME_OK;
+}
+
+int pme_set_stream(pme_plan* p, void* stream) {
+  if (p == nullptr) return PME_EINVAL;
+  p->stream = static_cast<hipStream_t>(stream);
+  return PME_OK;
+}
+
+int pme_set_debug(pme_plan* p, int keep_charge_grid) {
+  if (p == nullptr) return PME_EINVAL;
+  p->keep_grid = keep_charge_grid ? 1 : 0;
+  return PME_OK;
+}
+
+int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const double box[9]) {
+  if (p == nullptr || box == nullptr || N < 0 || N > p->max_atoms) return PME_EINVAL;
+  if (N > 0 && (pos == nullptr || q == nullptr)) return PME_EINVAL;
+  for (int i = 0; i < 9; ++i)
+    if (!is_fin(box[i])) return PME_EINVAL;
+  if (box[1] != 0.0 || box[2] != 0.0 || box[3] != 0.0 || box[5] != 0.0 || box[6] != 0.0 ||
+      box[7] != 0.0)
+    return PME_EUNSUPPORTED;  // triclinic cells are not supported on the GPU
+  if (!(box[0] > 0.0 && box[4] > 0.0 && box[8] > 0.0)) return PME_EINVAL;
+  Args& a = p->cur;
+  a.N = N;
+  a.n_chunks = (N + spme::kChunk - 1) / spme::kChunk;
+  a.pos = pos;
+  a.q = q;
+  a.L[0] = box[0];
+  a.L[1] = box[4];
+  a.L[2] = box[8];
+  for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
+  a.volume = a.L[0] * a.L[1] * a.L[2];
+  a.keep_grid = p->keep_grid;
+  a.forces = nullptr;
+  a.ev = nullptr;
+  int rc = timed(p, 0, [&] { return spme::launch_bin(a, p->stream); });
+  if (rc == PME_OK) rc = timed(p, 1, [&] { return spme::launch_spread_fwd(a, p->stream); });
+  if (rc != PME_OK) return rc;
+  p->grid_kept = p->keep_grid;
+  p->state = kSpread;
+  return PME_OK;
+}
+
+int pme_solve(pme_plan* p, double* ev) {
+  if (p == nullptr) return PME_EINVAL;
+  if (p->state < kSpread) return PME_ESTATE;
+  Args& a = p->cur;
+  a.ev = ev;
+  int rc = timed(p, 2, [&] { return spme::launch_pencil(a, p->stream); });
+  if (rc != PME_OK) return rc;
+  p->state = kSolved;
+  return PME_OK;
+}
+
+int pme_gather(pme_plan* p, double* forces, int accumulate) {
+  if (p == nullptr) return PME_EINVAL;
+  if (p->state < kSolved) return PME_ESTATE;
+  Args& a = p->cur;
+  if (a.N > 0 && forces == nullptr) return PME_EINVAL;
+  a.forces = forces;
+  a.accumulate = accumulate ? 1 : 0;
+  int rc = timed(p, 3, [&] { return spme::launch_inv(a, p->stream); });
+  if (rc == PME_OK) rc = timed(p, 4, [&] { return spme::launch_gather(a, p->stream); });
+  if (rc == PME_OK && p->timing) p->timed_steps++;
+  return rc;
+}
+
+int pme_step(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
+             double* forces, int accumulate, double* ev) {
+  if (p == nullptr) return PME_EINVAL;
+  if (N > 0 && forces == nullptr) return PME_EINVAL;
+  int rc = pme_spread(p, pos, q, N, box);
+  if (rc == PME_OK) rc = pme_solve(p, ev);
+  if (rc == PME_OK) rc = pme_gather(p, forces, accumulate);
+  return rc;
+}
+
+size_t pme_debug_grid_bytes(pme_plan* p, int which) {
+  if (p == nullptr) return 0;
+  const size_t K = p->K, kh = K / 2 + 1;
+  const size_t real = p->precision == PME_FP32_FIXED ? 4 : 8;
+  switch (which) {
+    case 0: return K * K * K * 8;
+    case 1: return K * K * kh * 2 * real;
+    case 2: return K * K * K * real;
+    default: return 0;
+  }
+}
+
+int pme_debug_grid(pme_plan* p, int which, void* dst) {
+  if (p == nullptr || dst == nullptr) return PME_EINVAL;
+  const size_t bytes = pme_debug_grid_bytes(p, which);
+  if (bytes == 0) return PME_EINVAL;
+  const size_t K = p->K;
+  const size_t real = p->precision == PME_FP32_FIXED ? 4 : 8;
+  hipError_t e;
+  switch (which) {
+    case 0:
+      if (p->state < kSpread || !p->grid_kept) return PME_ESTATE;
+      e = hipMemcpyAsync(dst, p->ws + p->lay.dbg, bytes, hipMemcpyDeviceToDevice, p->stream);
+      break;
+    case 1:
+      if (p->state < kSpread) return PME_ESTATE;
+      e = hipMemcpyAsync(dst, p->ws + p->lay.spec, bytes, hipMemcpyDeviceToDevice, p->stream);
+      break;
+    default:
+      if (p->state < kSolved) return PME_ESTATE;
+      e = hipMemcpy2DAsync(dst, K * real, p->ws + p->lay.phi + (p->order - 1) * real,
+                           (size_t)p->lay.phi_pitch * real, K * real, K * K,
+                           hipMemcpyDeviceToDevice, p->stream);
+      break;
+  }
+  return device_error(e);
+}
+
+int pme_check(pme_plan* p, unsigned* flags) {
+  if (p == nullptr || flags == nullptr) return PME_EINVAL;
+  unsigned f = 0;
+  hipError_t e = hipMemcpyAsync(&f, p->ws + p->lay.ctrl, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess) e = spme::launch_clear_flags(p->cur, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return PME_EDEVICE;
+  *flags = f;
+  if (f & PME_FLAG_NONFINITE) return PME_ENONFINITE;
+  if (f & PME_FLAG_OVERFLOW) return PME_EOVERFLOW;
+  return PME_OK;
+}
+
+int pme_kernel_timing(pme_plan* p, int enable) {
+  if (p == nullptr) return PME_EINVAL;
+  p->timing = enable ? 1 : 0;
+  return PME_OK;
+}
+
+int pme_kernel_times(pme_plan* p, double* ms, int n, int* steps) {
+  if (p == nullptr || (n > 0 && ms == nullptr)) return PME_EINVAL;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return PME_EDEVICE;
+  for (const TimedLaunch& t : p->pending) {
+    float el = 0.0f;
+    if (hipEventElapsedTime(&el, t.start, t.stop) != hipSuccess) return PME_EDEVICE;
+    if (t.kernel < n) ms[t.kernel] += el;
+  }
+  p->pending.clear();
+  p->event_next = 0;
+  if (steps) *steps = p->timed_steps;
+  p->timed_steps = 0;
+  return PME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the C ABI (spme_api.cpp) and the kernels
+// (spme_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace spme {
+
+constexpr int kChunk = 1024;        // atoms per binning workgroup (one sorted chunk)
+constexpr int kBinThreads = 256;    // 4 atoms per thread
+constexpr int kPlaneThreads = 512;  // one z-plane per workgroup
+constexpr int kPencilThreads = 256; // z-pencils of one (y, x-range) per workgroup
+constexpr int kGatherThreads = 256; // one atom per thread
+constexpr int kNumKernels = 5;      // bin, spread+xy, z-convolution, inverse xy, gather
+
+// Sorted atom record of the FP32/fixed path (32 bytes): packed base grid
+// index (x | y << 10 | z << 20), single-precision fractional offsets and
+// charge, index of the atom in the caller's order.
+struct RecF {
+  int g;
+  float w[3];
+  float q;
+  int idx;
+  int pad[2];
+};
+// FP64 path (48 bytes).
+struct RecD {
+  int g;
+  int idx;
+  double w[3];
+  double q;
+  double pad;
+};
+
+// Byte offsets of the workspace regions (each 256-byte aligned).
+struct Layout {
+  size_t ctrl;     // unsigned[64]: [0] sticky flags, [1] ticket of the z-convolution reduction
+  size_t bsq;      // double[3][K]: squared B-spline moduli per axis
+  size_t tw;       // complex[K]: exp(-2 pi i k/K), float2 or double2
+  size_t cnt;      // int[n_chunks][K]: atoms of chunk c whose base z index is b
+  size_t off;      // int[n_chunks][K]: exclusive prefix of cnt within the chunk
+  size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
+  size_t rec;      // records [n_chunks * kChunk]
+  size_t spec;     // complex[K][K][K/2+1] half spectrum
+  size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
+  size_t partial;  // double[pencil_blocks][8]: energy/virial partial sums
+  size_t dbg;      // int64 or double [K][K][K]: charge-grid copy (debug)
+  size_t total;
+  int n_chunks_max;
+  int pencil_blocks;
+  int xsplit;
+  int phi_pitch;
+};
+
+struct Args {
+  int K, order, precision, frac_bits;
+  int N, n_chunks;
+  int accumulate, keep_grid;
+  double L[3], invL[3];
+  double beta, coulomb, volume;
+  const double* pos;
+  const double* q;
+  double* forces;
+  double* ev;
+  char* ws;
+  Layout lay;
+};
+
+bool grid_supported(int K);
+bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay);
+
+// Raise dynamic-LDS limits of the kernels a plan will launch.
+hipError_t prepare_kernels(int K, int order, int precision);
+
+hipError_t launch_bin(const Args& a, hipStream_t s);
+hipError_t launch_spread_fwd(const Args& a, hipStream_t s);
+hipError_t launch_pencil(const Args& a, hipStream_t s);
+hipError_t launch_inv(const Args& a, hipStream_t s);
+hipError_t launch_gather(const Args& a, hipStream_t s);
+hipError_t launch_clear_flags(const Args& a, hipStream_t s);
+
+}  // namespace spme

@@ -1,0 +1,172 @@
+"""Python binding of the SPME step: torch tensors in, the C ABI underneath.
+
+PyTorch supplies device memory and the stream; every step of the SPME path
+runs in libspme.so's HIP kernels.  There is no CPU fallback: without the
+built library or a GPU, construction raises.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PME_FP32_FIXED, PME_FP64, check
+
+KERNEL_NAMES = ("bin", "spread_xy", "convolve_z", "inverse_xy", "gather")
+PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64}
+
+
+def _box9(box):
+    b = np.asarray(box, dtype=np.float64)
+    if b.shape == (3,):
+        b = np.diag(b)
+    b = np.ascontiguousarray(b.reshape(9))
+    return (ctypes.c_double * 9)(*b.tolist())
+
+
+def _dev_f64(t, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """One SPME reciprocal-space solver for a cubic K^3 grid.
+
+    precision: "fp32_fixed" (FP32 splines/FFT/convolution, 64-bit fixed-point
+    charge grid, FP64 moduli/energy/virial) or "fp64".
+    """
+
+    def __init__(self, K, order=4, beta=0.34, max_atoms=0, precision="fp32_fixed",
+                 frac_bits=32, coulomb=1.0, device=None, stream=None):
+        lib = _lib.load()
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.K, self.order, self.beta = int(K), int(order), float(beta)
+        self.max_atoms, self.precision = int(max_atoms), precision
+        self.frac_bits = int(frac_bits)
+        self.coulomb = float(coulomb)
+        prec = PRECISIONS[precision]
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.type != "cuda":
+            raise ValueError("the SPME step runs on a GPU device")
+        nbytes = lib.pme_workspace_bytes(self.K, self.K, self.K, self.order, self.max_atoms, prec)
+        if nbytes == 0:
+            raise _lib.SpmeError(2, f"pme_workspace_bytes(K={K}, order={order})")
+        self.workspace_bytes = nbytes
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self._ws.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib.pme_create(ctypes.byref(h), self.K, self.K, self.K, self.order, self.beta,
+                             self.max_atoms, prec, self.frac_bits, self.coulomb, base, nbytes,
+                             ctypes.c_void_p(self.stream.cuda_stream)), "pme_create")
+        self._h = h
+        self._lib = lib
+        self._keep = ()
+        self._n = 0
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pme_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        check(self._lib.pme_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "pme_set_stream")
+
+    # -- the step -----------------------------------------------------------
+    def spread(self, pos, q, box):
+        n = int(q.shape[0])
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
+        self._keep = (pos, q)
+        self._n = n
+        check(self._lib.pme_spread(self._h, pos.data_ptr(), q.data_ptr(), n, _box9(box)),
+              "pme_spread")
+
+    def solve(self, ev=None):
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=self.device)
+        _dev_f64(ev, (7,), "ev")
+        check(self._lib.pme_solve(self._h, ev.data_ptr()), "pme_solve")
+        return ev
+
+    def gather(self, forces=None, accumulate=False):
+        if forces is None:
+            forces = torch.empty((self._n, 3), dtype=torch.float64, device=self.device)
+        _dev_f64(forces, (self._n, 3), "forces")
+        check(self._lib.pme_gather(self._h, forces.data_ptr(), int(bool(accumulate))),
+              "pme_gather")
+        return forces
+
+    def step(self, pos, q, box, forces=None, accumulate=False, ev=None):
+        """Forces [N,3] and ev = [E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz] (device float64)."""
+        n = int(q.shape[0])
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=self.device)
+        _dev_f64(forces, (n, 3), "forces")
+        _dev_f64(ev, (7,), "ev")
+        self._keep = (pos, q)
+        self._n = n
+        check(self._lib.pme_step(self._h, pos.data_ptr(), q.data_ptr(), n, _box9(box),
+                                 forces.data_ptr(), int(bool(accumulate)), ev.data_ptr()),
+              "pme_step")
+        return forces, ev
+
+    # -- inspection -----------------------------------------------------------
+    def set_debug(self, keep_charge_grid=True):
+        check(self._lib.pme_set_debug(self._h, int(bool(keep_charge_grid))), "pme_set_debug")
+
+    def debug_grid(self, which):
+        """0: charge grid (int64 fixed point or float64), 1: half spectrum
+        (complex), 2: potential phi; shaped [K, K, K] / [K, K, K/2+1]."""
+        K, kh = self.K, self.K // 2 + 1
+        fx = self.precision == "fp32_fixed"
+        if which == 0:
+            out = torch.empty((K, K, K), dtype=torch.int64 if fx else torch.float64, device=self.device)
+        elif which == 1:
+            out = torch.empty((K, K, kh), dtype=torch.complex64 if fx else torch.complex128, device=self.device)
+        elif which == 2:
+            out = torch.empty((K, K, K), dtype=torch.float32 if fx else torch.float64, device=self.device)
+        else:
+            raise ValueError("which must be 0, 1 or 2")
+        assert out.numel() * out.element_size() == self._lib.pme_debug_grid_bytes(self._h, which)
+        check(self._lib.pme_debug_grid(self._h, int(which), out.data_ptr()), "pme_debug_grid")
+        return out
+
+    def check(self):
+        """Synchronise; return the sticky flags and clear them (raises on none)."""
+        flags = ctypes.c_uint(0)
+        rc = self._lib.pme_check(self._h, ctypes.byref(flags))
+        if rc not in (0, 4, 6):
+            check(rc, "pme_check")
+        return int(flags.value)
+
+    def kernel_timing(self, enable=True):
+        check(self._lib.pme_kernel_timing(self._h, int(bool(enable))), "pme_kernel_timing")
+
+    def kernel_times(self):
+        """Accumulated per-kernel milliseconds since the last call, and the step count."""
+        ms = (ctypes.c_double * len(KERNEL_NAMES))()
+        steps = ctypes.c_int(0)
+        check(self._lib.pme_kernel_times(self._h, ms, len(KERNEL_NAMES), ctypes.byref(steps)),
+              "pme_kernel_times")
+        return dict(zip(KERNEL_NAMES, list(ms))), int(steps.value)

@@ -1,0 +1,250 @@
+"""GPU parity of the HIP SPME path against the CPU oracle (through the C ABI).
+
+Bars:
+  * the 64-bit fixed-point charge grid is bit-identical to the oracle's
+    quantised mirror (and run to run);
+  * FP32/fixed path: force relative RMS <= 1e-5, energy relative error
+    <= 1e-6, every virial component within 1e-6 |E| of the FP64 oracle;
+  * FP64 path: force relative RMS <= 1e-10, energy relative error <= 1e-11.
+Sizes span several plane/pencil tiles and ragged atom chunks; the full
+benchmark-size systems are compared over every atom.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2009_12617_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+F32_FORCE, F32_ENERGY, F32_VIRIAL = 1e-5, 1e-6, 1e-6
+F64_FORCE, F64_ENERGY = 1e-10, 1e-11
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2009_12617_amd as pkg
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# (name, waters, box edge, K, order, beta): several tiles each, atom counts not
+# multiples of the 1024-atom chunk
+SMALL = [
+    ("k16_p4", 150, 14.0, 16, 4, 0.40),
+    ("k24_p6", 400, 18.0, 24, 6, 0.38),
+    ("k32_p4", 1365, 32.0, 32, 4, 0.35),
+    ("k48_p4", 2000, 40.0, 48, 4, 0.34),
+    ("k64_p6", 1700, 38.0, 64, 6, 0.34),
+    ("k96_p4", 3000, 60.0, 96, 4, 0.34),
+    ("k128_p6", 1000, 50.0, 128, 6, 0.34),
+]
+
+
+def system(name, nw, L, seed=17):
+    return I.water_box(nw, L, seed + sum(map(ord, name)))
+
+
+def compare(res, ref, ftol, etol, vtol):
+    forces, ev = res
+    f = forces.cpu().numpy()
+    e = ev.cpu().numpy()
+    fr = rel_rms(f, ref["forces"])
+    er = abs(e[0] - ref["E"]) / abs(ref["E"])
+    vr = float(np.abs(e[1:] - ref["virial"]).max() / abs(ref["E"]))
+    print(f"force_rel_rms={fr:.3e} energy_rel={er:.3e} virial_rel={vr:.3e}", flush=True)
+    assert fr <= ftol
+    assert er <= etol
+    assert vr <= vtol
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_fixed_point_grid_bit_exact(P, case):
+    name, nw, L, K, p, beta = case
+    pos, q, box = system(name, nw, L)
+    # atoms outside the primary cell on both sides exercise the wrap
+    pos[::7] += L * np.array([1.0, -2.0, 3.0])
+    plan = P.Plan(K, p, beta, max_atoms=len(q))
+    plan.set_debug(True)
+    plan.spread(dev(pos), dev(q), box)
+    got = plan.debug_grid(0).cpu().numpy()
+    ref, ref32 = oracle.mirror_grid(pos, q, box, K, p)
+    assert np.array_equal(got, ref), f"{int((got != ref).sum())} grid points differ"
+    # first FFT passes (x real-to-complex, then y) of the quantised grid
+    spec = plan.debug_grid(1).cpu().numpy().astype(np.complex128)
+    want = np.fft.fft(np.fft.rfft(ref32.astype(np.float64), axis=2), axis=1)
+    err = np.abs(spec - want).max() / np.abs(want).max()
+    print(f"xy-pass max rel err {err:.2e}", flush=True)
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_step_fp32_fixed(P, case):
+    name, nw, L, K, p, beta = case
+    pos, q, box = system(name, nw, L)
+    plan = P.Plan(K, p, beta, max_atoms=len(q))
+    res = plan.step(dev(pos), dev(q), box)
+    ref = oracle.spme(pos, q, box, K, p, beta, want_grids=True)
+    compare(res, ref, F32_FORCE, F32_ENERGY, F32_VIRIAL)
+    phi = plan.debug_grid(2).cpu().numpy()
+    assert rel_rms(phi, ref["phi"]) <= 1e-5
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_step_fp64(P, case):
+    name, nw, L, K, p, beta = case
+    pos, q, box = system(name, nw, L)
+    plan = P.Plan(K, p, beta, max_atoms=len(q), precision="fp64")
+    plan.set_debug(True)
+    res = plan.step(dev(pos), dev(q), box)
+    ref = oracle.spme(pos, q, box, K, p, beta, want_grids=True)
+    compare(res, ref, F64_FORCE, F64_ENERGY, 1e-11)
+    grid = plan.debug_grid(0).cpu().numpy()
+    assert np.abs(grid - ref["Q"]).max() < 1e-13
+
+
+WORKLOADS = [I.SMALL_32, I.HEADLINE_64, I.LARGE_128_P4, I.LARGE_128_P6]
+
+
+@pytest.mark.parametrize("w", WORKLOADS, ids=[w.name for w in WORKLOADS])
+def test_full_size_fp32_fixed(P, w):
+    pos, q, box = w.make()
+    plan = P.Plan(w.K, w.order, w.beta, max_atoms=len(q))
+    plan.set_debug(True)
+    res = plan.step(dev(pos), dev(q), box)
+    grid = plan.debug_grid(0).cpu().numpy()
+    ref_grid, _ = oracle.mirror_grid(pos, q, box, w.K, w.order)
+    assert np.array_equal(grid, ref_grid)
+    ref = oracle.spme(pos, q, box, w.K, w.order, w.beta)
+    compare(res, ref, F32_FORCE, F32_ENERGY, F32_VIRIAL)
+
+
+@pytest.mark.parametrize("w", [I.SMALL_32, I.HEADLINE_64], ids=["water_4095_k32", "water_65535_k64"])
+def test_full_size_fp64(P, w):
+    pos, q, box = w.make()
+    plan = P.Plan(w.K, w.order, w.beta, max_atoms=len(q), precision="fp64")
+    res = plan.step(dev(pos), dev(q), box)
+    ref = oracle.spme(pos, q, box, w.K, w.order, w.beta)
+    compare(res, ref, F64_FORCE, F64_ENERGY, 1e-11)
+
+
+def test_jittered_frames_reuse_plan(P):
+    w = I.HEADLINE_64
+    pos0, q, box = w.make()
+    frames = I.jitter_stream(pos0, 12, I.HEADLINE_JITTER_SIGMA, I.HEADLINE_JITTER_SEED)
+    plan = P.Plan(w.K, w.order, w.beta, max_atoms=len(q))
+    qd = dev(q)
+    dframes = dev(frames)
+    forces = torch.empty((len(q), 3), dtype=torch.float64, device="cuda")
+    ev = torch.empty(7, dtype=torch.float64, device="cuda")
+    for t in range(12):
+        plan.step(dframes[t], qd, box, forces=forces, ev=ev)
+        if t in (5, 11):
+            ref = oracle.spme(frames[t], q, box, w.K, w.order, w.beta)
+            compare((forces, ev), ref, F32_FORCE, F32_ENERGY, F32_VIRIAL)
+
+
+def test_run_to_run_bit_identical(P):
+    w = I.HEADLINE_64
+    pos, q, box = w.make()
+    plan = P.Plan(w.K, w.order, w.beta, max_atoms=len(q))
+    plan.set_debug(True)
+    dp, dq = dev(pos), dev(q)
+    f0, e0 = (t.clone() for t in plan.step(dp, dq, box))
+    g0 = plan.debug_grid(0).clone()
+    for _ in range(20):
+        f, e = plan.step(dp, dq, box)
+        assert torch.equal(f, f0)
+        assert torch.equal(e, e0)
+        assert torch.equal(plan.debug_grid(0), g0)
+
+
+def test_split_calls_match_step(P):
+    pos, q, box = system("split", 900, 26.0)
+    plan = P.Plan(32, 4, 0.35, max_atoms=len(q))
+    dp, dq = dev(pos), dev(q)
+    f0, e0 = (t.clone() for t in plan.step(dp, dq, box))
+    plan.spread(dp, dq, box)
+    e1 = plan.solve()
+    f1 = plan.gather()
+    assert torch.equal(f1, f0) and torch.equal(e1, e0)
+    # accumulate adds onto existing forces
+    f2 = torch.ones_like(f0)
+    plan.gather(f2, accumulate=True)
+    assert torch.allclose(f2, f0 + 1.0, rtol=0, atol=1e-12)
+
+
+def test_edge_cases(P):
+    box = np.diag([20.0] * 3)
+    plan = P.Plan(32, 4, 0.35, max_atoms=5000)
+    # no atoms: zero energy and virial
+    f, e = plan.step(dev(np.zeros((0, 3))), dev(np.zeros(0)), box)
+    assert f.shape == (0, 3) and torch.count_nonzero(e) == 0
+    # one (non-neutral) charge: its SPME self-force is grid aliasing, ~1e-3 of a
+    # unit-pair force, so it is compared in absolute terms
+    pos, q = np.array([[3.3, 7.1, 19.99]]), np.array([1.0])
+    f, e = plan.step(dev(pos), dev(q), box)
+    ref = oracle.spme(pos, q, box, 32, 4, 0.35)
+    assert np.abs(f.cpu().numpy() - ref["forces"]).max() < 1e-6
+    assert abs(e[0].item() - ref["E"]) <= F32_ENERGY * abs(ref["E"])
+    # atom counts one past a 1024-atom chunk boundary
+    for n in (1025, 2049):
+        pos, q, _ = I.random_neutral(n, 20.0, n)
+        res = plan.step(dev(pos), dev(q), box)
+        ref = oracle.spme(pos, q, box, 32, 4, 0.35)
+        compare(res, ref, F32_FORCE, F32_ENERGY, F32_VIRIAL)
+    # atoms exactly on cell faces and grid points
+    pos = np.array([[0.0, 0.0, 0.0], [20.0, 10.0, 5.0], [-20.0, 19.375, 0.625], [10.0, 10.0, 10.0]])
+    q = np.array([1.0, -1.0, 0.5, -0.5])
+    plan.set_debug(True)
+    plan.spread(dev(pos), dev(q), box)
+    assert np.array_equal(plan.debug_grid(0).cpu().numpy(), oracle.mirror_grid(pos, q, box, 32, 4)[0])
+    plan.set_debug(False)
+
+
+def test_sticky_flags(P):
+    box = np.diag([20.0] * 3)
+    pos, q, _ = I.random_neutral(300, 20.0, 5)
+    plan = P.Plan(32, 4, 0.35, max_atoms=300)
+    plan.step(dev(pos), dev(q), box)
+    assert plan.check() == 0
+    bad = pos.copy()
+    bad[17, 2] = np.nan
+    plan.set_debug(True)
+    plan.spread(dev(bad), dev(q), box)
+    grid = plan.debug_grid(0).cpu().numpy()
+    assert plan.check() & 1
+    assert plan.check() == 0  # cleared
+    ref, _ = oracle.mirror_grid(bad, q, box, 32, 4, allow_nonfinite=True)
+    assert np.array_equal(grid, ref)
+    # fixed-point headroom: sum |q| 2^F >= 2^52 raises the overflow flag
+    plan2 = P.Plan(32, 4, 0.35, max_atoms=300, frac_bits=40)
+    plan2.step(dev(pos), dev(q * 200.0), box)
+    assert plan2.check() & 2
+
+
+def test_call_order_and_arguments(P):
+    from paper_2009_12617_amd._lib import SpmeError
+    plan = P.Plan(32, 4, 0.35, max_atoms=10)
+    with pytest.raises(SpmeError) as ei:
+        plan.solve()
+    assert ei.value.code == 7
+    pos, q, box = I.random_neutral(11, 20.0, 1)
+    with pytest.raises(SpmeError) as ei:
+        plan.step(dev(pos), dev(q), box)
+    assert ei.value.code == 1
+    tric = box.copy()
+    tric[1, 0] = 1.0
+    with pytest.raises(SpmeError) as ei:
+        plan.spread(dev(pos[:10]), dev(q[:10]), tric)
+    assert ei.value.code == 2
