@@ -31,13 +31,14 @@ def algorithmic_bytes(N, K, kernel, fp64=False):
     atoms 32 B read by spreading, 32 B read + 24 B written by interpolation;
     the charge grid (8 B/point) written and read; the half spectrum
     (8 or 16 B/point) across the two corner turns; the potential written and
-    read."""
+    read.  Each term is charged to the kernel that performs that step."""
     kh = K // 2 + 1
     cs = 16 if fp64 else 8       # complex bytes
     rs = 8 if fp64 else 4        # potential bytes
     return {
         "bin": 32 * N,
-        "spread_xy": 8 * K ** 3 + 8 * K ** 3 + cs * K * K * kh,
+        "spread_x": 8 * K ** 3,
+        "fft_y": 8 * K ** 3 + cs * K * K * kh,
         "convolve_z": 2 * cs * K * K * kh,
         "inverse_xy": cs * K * K * kh + rs * K ** 3,
         "gather": 56 * N + rs * K ** 3,
@@ -46,7 +47,7 @@ def algorithmic_bytes(N, K, kernel, fp64=False):
 
 def step_bytes(N, K, fp64=False):
     return sum(algorithmic_bytes(N, K, k, fp64) for k in
-               ("bin", "spread_xy", "convolve_z", "inverse_xy", "gather"))
+               ("bin", "spread_x", "fft_y", "convolve_z", "inverse_xy", "gather"))
 
 
 def source_digest():
@@ -108,6 +109,7 @@ def main():
           file=sys.stderr, flush=True)
 
     def run(plan, steps, warmup, per_step=False):
+        """Host-launched steps; device time per step from events around them."""
         forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
         ev = torch.empty(7, dtype=torch.float64, device=dev)
         stream = torch.cuda.current_stream(dev)
@@ -133,16 +135,93 @@ def main():
         wall = time.perf_counter() - t0
         return start.elapsed_time(stop) / steps, wall / steps * 1e3
 
+    def capture(plan, first, steps, forces, ev):
+        """One HIP graph holding `steps` consecutive steps (frames first, first+1, ...)."""
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream(device=dev)
+        with torch.cuda.graph(g, stream=cs):
+            plan.set_stream(torch.cuda.current_stream(dev))
+            for t in range(steps):
+                plan.step(d_frames[(first + t) % F], d_q, box, forces=forces, ev=ev)
+        plan.set_stream(torch.cuda.current_stream(dev))
+        return g
+
+    def run_graph(plan, steps, warmup, exact=True):
+        """The timed region replays one captured graph of `steps` stream-ordered
+        steps; replays are checked against host-launched steps (bit for bit on
+        the fixed-point path; the FP64 path accumulates its grid with FP64
+        atomics, whose order, and so last-bit rounding, varies run to run)."""
+        forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        ev = torch.empty(7, dtype=torch.float64, device=dev)
+        for t in range(warmup):
+            plan.step(d_frames[t % F], d_q, box, forces=forces, ev=ev)
+        torch.cuda.synchronize()
+        g = capture(plan, warmup, steps, forces, ev)
+        g.replay()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record(stream)
+        g.replay()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop) / steps
+        # the replay's last step against a host-launched step on the same frame,
+        # twice, with eager work in between
+        last = (warmup + steps - 1) % F
+        ok = True
+        for _ in range(2):
+            fg, eg = forces.clone(), ev.clone()
+            fe, ee = plan.step(d_frames[last], d_q, box)
+            torch.cuda.synchronize()
+            if exact:
+                ok &= bool(torch.equal(fg, fe)) and bool(torch.equal(eg, ee))
+            else:
+                ok &= bool(torch.allclose(fg, fe, rtol=1e-11, atol=1e-14))
+                ok &= bool(torch.allclose(eg, ee, rtol=1e-11, atol=1e-14))
+            g.replay()
+            torch.cuda.synchronize()
+        del g
+        return ms, wall / steps * 1e3, ok
+
+    def graph_latency(plan, steps):
+        """Per-step latency of single-step graph launches (one frame each)."""
+        forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        ev = torch.empty(7, dtype=torch.float64, device=dev)
+        gs = [capture(plan, t, 1, forces, ev) for t in range(min(steps, F, 200))]
+        stream = torch.cuda.current_stream(dev)
+        for g in gs[:5]:
+            g.replay()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        evs[0].record(stream)
+        for t in range(steps):
+            gs[t % len(gs)].replay()
+            evs[t + 1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+
     plan = Plan(K, w.order, w.beta, max_atoms=N, precision="fp32_fixed", device=dev)
-    ms_step, wall_ms = run(plan, args.steps, args.warmup)
-    print(f"# fp32_fixed: {ms_step * 1e3:.2f} us/step (device events), {wall_ms * 1e3:.2f} us/step (host wall)",
+    ms_eager, wall_eager = run(plan, args.steps, args.warmup)
+    print(f"# fp32_fixed host-launched: {ms_eager * 1e3:.2f} us/step (device events), "
+          f"{wall_eager * 1e3:.2f} us/step (host wall)", file=sys.stderr, flush=True)
+    ms_step, wall_ms, graph_ok = run_graph(plan, args.steps, args.warmup)
+    print(f"# fp32_fixed graph replay: {ms_step * 1e3:.2f} us/step, replay == eager: {graph_ok}",
           file=sys.stderr, flush=True)
+    if not graph_ok:
+        print("bench.py: graph replay differs from host-launched steps", file=sys.stderr)
+        sys.exit(1)
     if args.profile:
         print(json.dumps({"metric": "us/PME step (65,535 atoms, 64^3)", "value": ms_step * 1e3,
-                          "unit": "us/step", "mode": "profile"}))
+                          "unit": "us/step", "mode": "profile",
+                          "host_launched_us_per_step": ms_eager * 1e3}))
         return
 
-    lat = run(plan, min(args.steps, 1000), 5, per_step=True) * 1e3
+    lat = graph_latency(plan, min(args.steps, 1000)) * 1e3
+    lat_eager = run(plan, min(args.steps, 1000), 5, per_step=True) * 1e3
     plan.kernel_timing(True)
     run(plan, min(args.steps, 500), 0)
     kms, ksteps = plan.kernel_times()
@@ -158,7 +237,10 @@ def main():
     fp64 = None
     if not args.no_fp64:
         plan64 = Plan(K, w.order, w.beta, max_atoms=N, precision="fp64", device=dev)
-        ms64, _ = run(plan64, args.steps, args.warmup)
+        ms64, _, ok64 = run_graph(plan64, args.steps, args.warmup, exact=False)
+        if not ok64:
+            print("bench.py: FP64 graph replay differs from host-launched steps", file=sys.stderr)
+            sys.exit(1)
         fp64 = {"us_per_step": ms64 * 1e3, "speedup_fp32_fixed": ms64 / ms_step,
                 "step_roofline_frac": step_bytes(N, K, True) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"# fp64: {ms64 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
@@ -208,8 +290,12 @@ def main():
                    "box_A": float(box[0, 0]), "frames": F, "jitter_A": I.HEADLINE_JITTER_SIGMA,
                    "precision": "fp32 splines/FFT/convolution, int64 fixed-point charge grid, fp64 energy/virial"},
         "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean()), "steps": int(len(lat))},
-        "host_wall_us_per_step": wall_ms * 1e3,
+                       "mean": float(lat.mean()), "steps": int(len(lat)),
+                       "what": "one step per single-step graph launch, stream-ordered"},
+        "host_launched": {"us_per_step": ms_eager * 1e3, "host_wall_us_per_step": wall_eager * 1e3,
+                          "latency_p50_us": float(np.percentile(lat_eager, 50)),
+                          "latency_p99_us": float(np.percentile(lat_eager, 99))},
+        "timed_region": "one HIP graph replay of all timed steps (captured pme_step calls)",
         "kernels_us": kavg_us,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

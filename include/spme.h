@@ -66,7 +66,7 @@ typedef enum {
   PME_EINVAL = 1,        /* bad argument (null pointer, N out of range, beta <= 0, ...) */
   PME_EUNSUPPORTED = 2,  /* valid SPME parameters this build does not run (grid, order, cell) */
   PME_EWORKSPACE = 3,    /* workspace missing, misaligned or smaller than pme_workspace_bytes */
-  PME_EOVERFLOW = 4,     /* fixed-point headroom exceeded (sum |q| 2^F >= 2^52) */
+  PME_EOVERFLOW = 4,     /* fixed-point headroom exceeded (sum |q| 2^F >= 2^51) */
   PME_EDEVICE = 5,       /* a HIP runtime call failed */
   PME_ENONFINITE = 6,    /* a position or charge was NaN or infinite */
   PME_ESTATE = 7         /* call out of order (e.g. pme_solve before pme_spread) */
@@ -108,7 +108,8 @@ int pme_set_stream(pme_plan *plan, void *stream);
 
 /* Charge spreading and the first FFT passes (§III.A.1, first half of
  * §III.A.2): bins the atoms, spreads them into the fixed-point (or FP64) grid
- * and transforms it along x (real-to-complex) and y.
+ * and transforms it along x (real-to-complex) and y.  With the FP32/fixed
+ * path the plan raises PME_FLAG_OVERFLOW when sum |q| 2^F >= 2^51.
  *   pos  device [N][3] doubles (Angstrom, any image; wrapped internally)
  *   q    device [N] doubles
  *   N    0 <= N <= max_atoms
@@ -156,10 +157,13 @@ size_t pme_debug_grid_bytes(pme_plan *plan, int which);
 int pme_check(pme_plan *plan, unsigned *flags);
 
 /* Per-kernel timing with HIP events on the plan's stream (off by default).
- * While enabled every launch is bracketed by events; pme_kernel_times
+ * While enabled every launch carries a start and a stop event attached to
+ * the dispatch itself (hipExtLaunchKernel), so the elapsed time is the
+ * kernel's own execution; pme_kernel_times
  * synchronises, adds the elapsed times of all completed launches into
- * ms[0..n-1] (kernel order: bin, spread+xy, z-convolution, inverse xy,
- * gather) and returns the number of steps accumulated in *steps. */
+ * ms[0..n-1] (kernel order: bin, spread + x FFT, y FFT, z-convolution,
+ * inverse y/x FFT, gather) and returns the number of steps accumulated in
+ * *steps. */
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
 

@@ -88,16 +88,17 @@ hipEvent_t next_event(pme_plan* p) {
   return p->event_pool[p->event_next++];
 }
 
+// Run one launch; with timing on, events are attached to the dispatch and
+// queued for pme_kernel_times.
 template <class F>
 int timed(pme_plan* p, int kernel, F&& launch) {
-  if (!p->timing) return device_error(launch());
-  hipEvent_t a = next_event(p), b = next_event(p);
-  if (!a || !b) return PME_EDEVICE;
-  if (hipEventRecord(a, p->stream) != hipSuccess) return PME_EDEVICE;
-  hipError_t e = launch();
-  if (e != hipSuccess) return PME_EDEVICE;
-  if (hipEventRecord(b, p->stream) != hipSuccess) return PME_EDEVICE;
-  p->pending.push_back({kernel, a, b});
+  if (!p->timing) return device_error(launch(spme::Timing()));
+  spme::Timing t;
+  t.start = next_event(p);
+  t.stop = next_event(p);
+  if (!t.start || !t.stop) return PME_EDEVICE;
+  if (launch(t) != hipSuccess) return PME_EDEVICE;
+  p->pending.push_back({kernel, t.start, t.stop});
   return PME_OK;
 }
 
@@ -113,7 +114,7 @@ const char* pme_strerror(int code) {
     case PME_EINVAL: return "invalid argument";
     case PME_EUNSUPPORTED: return "unsupported parameters (grid, spline order or cell shape)";
     case PME_EWORKSPACE: return "workspace missing, misaligned or too small";
-    case PME_EOVERFLOW: return "fixed-point headroom exceeded (sum |q| 2^F >= 2^52)";
+    case PME_EOVERFLOW: return "fixed-point headroom exceeded (sum |q| 2^F >= 2^51)";
     case PME_EDEVICE: return "HIP runtime error";
     case PME_ENONFINITE: return "non-finite position or charge";
     case PME_ESTATE: return "call out of order";
@@ -252,36 +253,65 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
   a.keep_grid = p->keep_grid;
   a.forces = nullptr;
   a.ev = nullptr;
-  int rc = timed(p, 0, [&] { return spme::launch_bin(a, p->stream); });
-  if (rc == PME_OK) rc = timed(p, 1, [&] { return spme::launch_spread_fwd(a, p->stream); });
+  a.reduce_ev = 0;
+  int rc = timed(p, 0, [&](const spme::Timing& t) { return spme::launch_bin(a, p->stream, t); });
+  if (rc == PME_OK)
+    rc = timed(p, 1, [&](const spme::Timing& t) { return spme::launch_spread_x(a, p->stream, t); });
+  if (rc == PME_OK)
+    rc = timed(p, 2, [&](const spme::Timing& t) { return spme::launch_fft_y(a, p->stream, t); });
   if (rc != PME_OK) return rc;
   p->grid_kept = p->keep_grid;
   p->state = kSpread;
   return PME_OK;
 }
 
-int pme_solve(pme_plan* p, double* ev) {
-  if (p == nullptr) return PME_EINVAL;
+namespace {
+
+// The z-convolution writes one energy/virial row per workgroup; the rows are
+// summed either by the next kernel of the step (fused = true) or by a
+// one-workgroup kernel right away.
+int solve_impl(pme_plan* p, double* ev, bool fused) {
   if (p->state < kSpread) return PME_ESTATE;
   Args& a = p->cur;
   a.ev = ev;
-  int rc = timed(p, 2, [&] { return spme::launch_pencil(a, p->stream); });
+  a.reduce_ev = 0;
+  int rc = timed(p, 3, [&](const spme::Timing& t) { return spme::launch_pencil(a, p->stream, t); });
+  if (rc != PME_OK) return rc;
+  if (ev != nullptr) {
+    if (fused)
+      a.reduce_ev = 1;
+    else
+      rc = device_error(spme::launch_reduce_ev(a, p->stream));
+  }
   if (rc != PME_OK) return rc;
   p->state = kSolved;
   return PME_OK;
 }
 
-int pme_gather(pme_plan* p, double* forces, int accumulate) {
-  if (p == nullptr) return PME_EINVAL;
+int gather_impl(pme_plan* p, double* forces, int accumulate) {
   if (p->state < kSolved) return PME_ESTATE;
   Args& a = p->cur;
   if (a.N > 0 && forces == nullptr) return PME_EINVAL;
   a.forces = forces;
   a.accumulate = accumulate ? 1 : 0;
-  int rc = timed(p, 3, [&] { return spme::launch_inv(a, p->stream); });
-  if (rc == PME_OK) rc = timed(p, 4, [&] { return spme::launch_gather(a, p->stream); });
+  int rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_inv(a, p->stream, t); });
+  a.reduce_ev = 0;  // the energy/virial rows are summed once
+  if (rc == PME_OK)
+    rc = timed(p, 5, [&](const spme::Timing& t) { return spme::launch_gather(a, p->stream, t); });
   if (rc == PME_OK && p->timing) p->timed_steps++;
   return rc;
+}
+
+}  // namespace
+
+int pme_solve(pme_plan* p, double* ev) {
+  if (p == nullptr) return PME_EINVAL;
+  return solve_impl(p, ev, false);
+}
+
+int pme_gather(pme_plan* p, double* forces, int accumulate) {
+  if (p == nullptr) return PME_EINVAL;
+  return gather_impl(p, forces, accumulate);
 }
 
 int pme_step(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
@@ -289,8 +319,8 @@ int pme_step(pme_plan* p, const double* pos, const double* q, int N, const doubl
   if (p == nullptr) return PME_EINVAL;
   if (N > 0 && forces == nullptr) return PME_EINVAL;
   int rc = pme_spread(p, pos, q, N, box);
-  if (rc == PME_OK) rc = pme_solve(p, ev);
-  if (rc == PME_OK) rc = pme_gather(p, forces, accumulate);
+  if (rc == PME_OK) rc = solve_impl(p, ev, true);
+  if (rc == PME_OK) rc = gather_impl(p, forces, accumulate);
   return rc;
 }
 

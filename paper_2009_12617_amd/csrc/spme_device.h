@@ -359,10 +359,15 @@ __device__ __forceinline__ bool grid_coord(double x, double invL, int K, int* g,
   return ok;
 }
 
-// 64-bit fixed-point contribution: round-half-even of c 2^F.
+// 64-bit fixed-point contribution: round-half-even of c 2^F.  c 2^F is exact
+// in FP64; adding 1.5 2^52 in one fused operation rounds it to an integer in
+// the default round-to-nearest-even mode, and the integer is the difference
+// of the two bit patterns (valid for |c 2^F| < 2^51, which the plan's
+// headroom check guarantees).
 __device__ __forceinline__ long long to_fixed(float c, double scale) {
-#pragma clang fp contract(off)
-  return (long long)rint((double)c * scale);
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  const double d = __fma_rn((double)c, scale, magic);
+  return __double_as_longlong(d) - __double_as_longlong(magic);
 }
 
 }  // namespace spme

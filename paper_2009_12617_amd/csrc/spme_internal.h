@@ -7,12 +7,23 @@
 
 namespace spme {
 
-constexpr int kChunk = 1024;        // atoms per binning workgroup (one sorted chunk)
-constexpr int kBinThreads = 256;    // 4 atoms per thread
-constexpr int kPlaneThreads = 512;  // one z-plane per workgroup
-constexpr int kPencilThreads = 256; // z-pencils of one (y, x-range) per workgroup
-constexpr int kGatherThreads = 256; // one atom per thread
-constexpr int kNumKernels = 5;      // bin, spread+xy, z-convolution, inverse xy, gather
+constexpr int kChunk = 1024;         // atoms per binning workgroup (one sorted chunk)
+constexpr int kBinThreads = 1024;    // one atom per thread
+constexpr int kMaxBins = 1024;       // (z, y slice, head/body) bins per chunk: 2 K nq <= 1024
+constexpr int kItemMap = 4096;       // items per window of the spreading item map
+constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
+constexpr int kPlaneThreads = 512;   // one z-plane per workgroup
+constexpr int kPencilThreads = 256;  // z-pencils of one (y, x-range) per workgroup
+constexpr int kGatherThreads = 256;  // one atom per thread
+constexpr int kNumKernels = 6;       // bin, spread+x, y, z-convolution, inverse xy, gather
+
+// y slices per z-plane in the spreading pass (rows per slice >= 8 > p - 1,
+// so an atom's support reaches at most one slice below its own).
+__host__ __device__ constexpr int nq_of(int K) { return K >= 32 ? 4 : K / 8; }
+__host__ __device__ constexpr int pencil_xsplit(int K) { return K >= 32 ? 2 : 1; }
+__host__ __device__ constexpr int phi_pitch_of(int K, int order) {
+  return (K + order - 1 + 3) / 4 * 4;
+}
 
 // Sorted atom record of the FP32/fixed path (32 bytes): packed base grid
 // index (x | y << 10 | z << 20), single-precision fractional offsets and
@@ -35,13 +46,13 @@ struct RecD {
 
 // Byte offsets of the workspace regions (each 256-byte aligned).
 struct Layout {
-  size_t ctrl;     // unsigned[64]: [0] sticky flags, [1] ticket of the z-convolution reduction
+  size_t ctrl;     // unsigned[64]: [0] sticky flags
   size_t bsq;      // double[3][K]: squared B-spline moduli per axis
   size_t tw;       // complex[K]: exp(-2 pi i k/K), float2 or double2
-  size_t cnt;      // int[n_chunks][K]: atoms of chunk c whose base z index is b
-  size_t off;      // int[n_chunks][K]: exclusive prefix of cnt within the chunk
+  size_t cnt;      // int[n_chunks][2 K nq]: atoms of chunk c in bin (z, y slice, head/body)
+  size_t off;      // int[n_chunks][2 K nq]: exclusive prefix of cnt within the chunk
   size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
-  size_t rec;      // records [n_chunks * kChunk]
+  size_t rec;      // records [n_chunks * kChunk] (RecF or RecD)
   size_t spec;     // complex[K][K][K/2+1] half spectrum
   size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
   size_t partial;  // double[pencil_blocks][8]: energy/virial partial sums
@@ -57,6 +68,7 @@ struct Args {
   int K, order, precision, frac_bits;
   int N, n_chunks;
   int accumulate, keep_grid;
+  int reduce_ev;  // k_inv_xy's first workgroup adds the energy/virial rows
   double L[3], invL[3];
   double beta, coulomb, volume;
   const double* pos;
@@ -67,17 +79,24 @@ struct Args {
   Layout lay;
 };
 
+// Optional events attached to one kernel dispatch (both null: untimed).
+struct Timing {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 bool grid_supported(int K);
 bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay);
 
 // Raise dynamic-LDS limits of the kernels a plan will launch.
 hipError_t prepare_kernels(int K, int order, int precision);
 
-hipError_t launch_bin(const Args& a, hipStream_t s);
-hipError_t launch_spread_fwd(const Args& a, hipStream_t s);
-hipError_t launch_pencil(const Args& a, hipStream_t s);
-hipError_t launch_inv(const Args& a, hipStream_t s);
-hipError_t launch_gather(const Args& a, hipStream_t s);
+hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_reduce_ev(const Args& a, hipStream_t s);
+hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t = Timing());
 hipError_t launch_clear_flags(const Args& a, hipStream_t s);
 
 }  // namespace spme

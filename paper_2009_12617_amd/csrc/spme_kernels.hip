@@ -1,31 +1,33 @@
 // HIP kernels of the SPME reciprocal-space step for gfx950 (CDNA4).
 //
-// One step is five launches on one stream:
-//   k_bin        fractional coordinates, base grid index and offsets of each
-//                atom; per-chunk counting sort of the atoms by the z index of
-//                their base point (the GPU counterpart of the paper's atom
-//                reordering for hazard suppression, §III.A.1 / §V.C)
-//   k_spread_fwd one z-plane per workgroup: every atom whose B-spline support
-//                covers the plane adds its p x p contributions into an LDS
-//                plane (64-bit fixed point: integer adds commute, so the grid
-//                is bit-identical whatever the order), then the plane is
-//                transformed along x (real-to-complex) and y in LDS and
-//                written out as half-spectrum rows (§III.A.2: "each slab runs
-//                independently to compute X and Y transforms")
-//   k_pencil     one y row (or half of it) per workgroup: z transforms,
-//                multiplication by the influence function with FP64 energy
-//                and virial partials, inverse z transforms (§III.A.2: "Z
-//                direction transforms, multiply by Green's function data,
-//                compute Z^-1 transforms"); the last workgroup reduces the
-//                partials in a fixed order
-//   k_inv_xy     one z-plane per workgroup: inverse y and complex-to-real x
-//                transforms, potential rows written with a (p-1)-point wrap
-//                halo so interpolation reads contiguous runs
-//   k_gather     one atom per thread: B-spline weights and derivatives, p^3
-//                potential reads, forces scattered back to the caller's atom
-//                order (§III.A.3)
+// One step is six launches on one stream:
+//   k_bin       fractional coordinates, base grid index and offsets of each
+//               atom; a per-chunk counting sort of the atoms by (base z,
+//               y slice) -- the GPU counterpart of the
+//               paper's atom reordering for hazard suppression (§III.A.1, §V.C)
+//   k_spread_x  one y slice of one z-plane per workgroup: every atom whose
+//               support covers the slice adds its contributions into an LDS
+//               tile in 64-bit fixed point (integer adds commute, so the grid
+//               is bit-identical whatever the order); the finished rows are
+//               converted to FP32 and transformed along x (real-to-complex)
+//   k_fft_y     one z-plane per workgroup: y transforms (§III.A.2: "each
+//               slab runs independently to compute X and Y transforms")
+//   k_pencil    one y row (or half of it) per workgroup: z transforms,
+//               multiplication by the influence function with FP64 energy and
+//               virial partials, inverse z transforms (§III.A.2: "Z direction
+//               transforms, multiply by Green's function data, compute Z^-1
+//               transforms")
+//   k_inv_xy    one z-plane per workgroup: inverse y and complex-to-real x
+//               transforms; potential rows written with a (p-1)-point wrap
+//               halo so interpolation reads contiguous runs; one extra
+//               workgroup adds the energy/virial partial rows
+//   k_gather    one atom per thread: B-spline weights and derivatives, p^3
+//               potential reads, forces scattered back to the caller's atom
+//               order (§III.A.3)
 // The paper's two all-to-all corner turns become the HBM round trips between
 // plane and pencil passes.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "spme_device.h"
@@ -33,6 +35,23 @@
 #include "../../include/spme.h"
 
 namespace spme {
+
+// Optional phase trace (build with -DSPME_TRACE): thread 0 of each workgroup
+// stamps the 100 MHz wall clock at phase boundaries into
+// trace[kernel][workgroup][phase]; kernels 0..5 in launch order, phase 0 at
+// entry and 15 at exit.
+#ifdef SPME_TRACE
+__device__ unsigned long long* g_trace;
+#define TRACE(kernel, phase)                                                         \
+  do {                                                                               \
+    if (threadIdx.x == 0 && g_trace != nullptr && blockIdx.x < 1024)                 \
+      g_trace[((size_t)(kernel) * 1024 + blockIdx.x) * 16 + (phase)] = wall_clock64(); \
+  } while (0)
+#else
+#define TRACE(kernel, phase) \
+  do {                       \
+  } while (0)
+#endif
 
 struct PFixed {
   using real = float;
@@ -47,18 +66,16 @@ struct PDouble {
   static constexpr bool fixed = false;
 };
 
-// Row pitch of the LDS plane in 8-byte units.  Fixed point: K int64 values
-// per row (the half spectrum of K/2+1 float2 fits in place).  FP64: room for
-// K/2+1 double2.  One extra unit of padding skews rows across LDS banks.
+// Row pitch of an LDS grid tile in 8-byte units.  Fixed point: K int64
+// values per row (the half spectrum of K/2+1 float2 fits in place).  FP64:
+// room for K/2+1 double2.  The extra unit skews rows across LDS banks.
 template <class P>
-__host__ __device__ constexpr int plane_pitch(int K) { return P::fixed ? K + 1 : K + 4; }
-__host__ __device__ constexpr int pencil_xsplit(int K) { return K >= 32 ? 2 : 1; }
-__host__ __device__ constexpr int phi_pitch_of(int K, int order) { return (K + order - 1 + 3) / 4 * 4; }
+__host__ __device__ constexpr int tile_pitch(int K) { return P::fixed ? K + 1 : K + 4; }
 
-// a[i] for a register array and a lane-varying i, written as a masked sum
-// (a[i] + exact zeros) so the array stays in registers.
 template <int P, typename T>
 __device__ __forceinline__ T pick(const T* a, int i) {
+  // a[i] for a register array and a lane-varying i, written as a masked sum
+  // (a[i] plus exact zeros) so that the array stays in registers
   T v = T(0);
 #pragma unroll
   for (int k = 0; k < P; ++k) v += a[k] * T(i == k ? 1 : 0);
@@ -91,17 +108,34 @@ __device__ int block_exclusive_scan(int v, int* wsum, int* total) {
   return (wave > 0 ? wsum[16 + wave - 1] : 0) + x - v;
 }
 
-// Sum of one double over the block in a fixed order (wave shuffles, then the
-// wave partials in order).  red needs blockDim/64 doubles.
-__device__ double block_sum(double v, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// Sums of V doubles over the block in a fixed order: every thread stores its
+// values, 16 threads per value add consecutive runs of blockDim/16 entries,
+// then thread c < V adds the 16 run sums of value c in order and returns it
+// (other threads return 0).  red needs block_sum_doubles(V, blockDim)
+// doubles; the caller synchronises before reusing red.
+__host__ __device__ constexpr int block_sum_doubles(int V, int threads) { return V * (threads + 16); }
+
+template <int V>
+__device__ double block_sums(const double* v, double* red) {
+  const int n = blockDim.x, tid = threadIdx.x;
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+  for (int c = 0; c < V; ++c) red[c * n + tid] = v[c];
   __syncthreads();
-  if (lane == 0) red[wave] = v;
+  double* part = red + V * n;
+  const int run = n / 16;
+  if (tid < V * 16) {
+    const int c = tid / 16, k = tid - c * 16;
+    const double* src = red + c * n + k * run;
+    double s = 0.0;
+    for (int i = 0; i < run; ++i) s += src[i];
+    part[tid] = s;
+  }
   __syncthreads();
   double s = 0.0;
-  for (int w = 0; w < nw; ++w) s += red[w];
+  if (tid < V) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += part[tid * 16 + k];
+  }
   return s;
 }
 
@@ -112,221 +146,241 @@ template <class P>
 __global__ __launch_bounds__(kBinThreads) void k_bin(Args a) {
   using Rec = typename P::rec;
   using T = typename P::real;
-  __shared__ int hist[128];
-  __shared__ int base[128];
-  __shared__ double red[kBinThreads / 64];
-  const int K = a.K;
+  __shared__ int hist[kMaxBins];
+  __shared__ int wsum[32];
+  __shared__ double red[block_sum_doubles(1, kBinThreads)];
+  TRACE(0, 0);
+  const int K = a.K, nq = nq_of(a.K), rows = K / nq, nbins = 2 * K * nq;
   const int c = blockIdx.x, tid = threadIdx.x;
-  int* cnt = reinterpret_cast<int*>(a.ws + a.lay.cnt) + (size_t)c * K;
-  int* off = reinterpret_cast<int*>(a.ws + a.lay.off) + (size_t)c * K;
+  int* cnt = reinterpret_cast<int*>(a.ws + a.lay.cnt) + (size_t)c * nbins;
+  int* off = reinterpret_cast<int*>(a.ws + a.lay.off) + (size_t)c * nbins;
   Rec* rec = reinterpret_cast<Rec*>(a.ws + a.lay.rec) + (size_t)c * kChunk;
   unsigned* flags = reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl);
-  for (int b = tid; b < K; b += kBinThreads) hist[b] = 0;
+  for (int b = tid; b < nbins; b += kBinThreads) hist[b] = 0;
   __syncthreads();
+  TRACE(0, 1);
 
-  constexpr int APT = kChunk / kBinThreads;
-  Rec r[APT];
-  int bin[APT], rank[APT];
-  double sabs = 0.0;
-  bool bad = false;
+  // one atom per thread
+  const int i = c * kChunk + tid;
+  Rec r;
+  int bin = -1, rank = 0;
+  double v[1] = {0.0};
+  if (i < a.N) {
+    int g[3];
+    double w[3];
+    bool ok = true;
 #pragma unroll
-  for (int t = 0; t < APT; ++t) {
-    const int i = c * kChunk + t * kBinThreads + tid;
-    bin[t] = -1;
-    if (i < a.N) {
-      int g[3];
-      double w[3];
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= grid_coord(a.pos[3 * (size_t)i + d], a.invL[d], K, &g[d], &w[d]);
-      double qi = a.q[i];
-      ok &= (qi - qi == 0.0);  // finite
-      if (!ok) {
-        qi = 0.0;  // contributes nothing; reported through the sticky flag
-        bad = true;
-      }
-      sabs += fabs(qi);
-      r[t].g = g[0] | (g[1] << 10) | (g[2] << 20);
-      r[t].w[0] = (T)w[0];
-      r[t].w[1] = (T)w[1];
-      r[t].w[2] = (T)w[2];
-      r[t].q = (T)qi;
-      r[t].idx = i;
-      bin[t] = g[2];
-      rank[t] = atomicAdd(&hist[g[2]], 1);
+    for (int d = 0; d < 3; ++d) ok &= grid_coord(a.pos[3 * (size_t)i + d], a.invL[d], K, &g[d], &w[d]);
+    double qi = a.q[i];
+    ok &= (qi - qi == 0.0);  // finite
+    if (!ok) {
+      qi = 0.0;  // contributes nothing; reported through the sticky flag
+      atomicOr(flags, PME_FLAG_NONFINITE);
     }
+    v[0] = fabs(qi);
+    r.g = g[0] | (g[1] << 10) | (g[2] << 20);
+    r.w[0] = (T)w[0];
+    r.w[1] = (T)w[1];
+    r.w[2] = (T)w[2];
+    r.q = (T)qi;
+    r.idx = i;
+    // bin (z, y slice, head/body): the head holds the atoms whose support
+    // also reaches the slice below (g_y mod rows < p - 1)
+    const int sl = g[1] / rows;
+    bin = (g[2] * nq + sl) * 2 + ((g[1] - sl * rows) >= a.order - 1 ? 1 : 0);
+    rank = atomicAdd(&hist[bin], 1);
   }
-  if (bad) atomicOr(flags, PME_FLAG_NONFINITE);
+  // sum |q| of the chunk (fixed-point headroom), before any global store so
+  // that the barriers below do not wait on outstanding writes
+  const double qsum = block_sums<1>(v, red);
+  TRACE(0, 2);
+  // exclusive scan of the bin counts, one bin per thread
+  const int h = (tid < nbins) ? hist[tid] : 0;
+  int total;
+  const int ex = block_exclusive_scan(h, wsum, &total);
+  if (tid < nbins) hist[tid] = ex;  // own slot: read above by this thread only
   __syncthreads();
-  {
-    // K <= 128 bins: waves 0 and 1 scan 64 bins each; wave 1 adds wave 0's total
-    __shared__ int wave0_total;
-    const int lane = tid & 63, wave = tid >> 6;
-    int h = 0, x = 0;
-    if (wave < 2) {
-      h = (tid < K) ? hist[tid] : 0;
-      x = h;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-      }
-      if (wave == 0 && lane == 63) wave0_total = x;
-    }
-    __syncthreads();
-    if (wave < 2 && tid < K) {
-      const int ex = x - h + (wave == 1 ? wave0_total : 0);
-      base[tid] = ex;
-      cnt[tid] = h;
-      off[tid] = ex;
-    }
+  TRACE(0, 3);
+  if (bin >= 0) rec[hist[bin] + rank] = r;
+  if (tid < nbins) {
+    cnt[tid] = h;
+    off[tid] = ex;
   }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < APT; ++t)
-    if (bin[t] >= 0) rec[base[bin[t]] + rank[t]] = r[t];
-  const double tot = block_sum(sabs, red);
-  if (tid == 0) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = tot;
+  if (tid == 0) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = qsum;
+  TRACE(0, 15);
 }
 
 // ---------------------------------------------------------------------------
-// k_spread_fwd: charge spreading of one z-plane, then x (R2C) and y FFTs.
+// k_spread_x: charge spreading of one y slice of one z-plane, then the x
+// real-to-complex FFT of its rows.
 // ---------------------------------------------------------------------------
 template <class P, int K>
 __host__ __device__ constexpr size_t spread_lds_bytes() {
-  return (size_t)K * plane_pitch<P>(K) * 8 + (size_t)K * sizeof(cplx<typename P::real>) +
-         (size_t)(2 * kPlaneThreads + 1 + 32) * sizeof(int) + 16 * sizeof(double);
+  return (size_t)(K / nq_of(K)) * tile_pitch<P>(K) * 8 +
+         (size_t)K * sizeof(cplx<typename P::real>) +
+         block_sum_doubles(1, kSpreadThreads) * sizeof(double) +
+         (size_t)(2 * kSpreadThreads + 2 + 32) * sizeof(int) + kItemMap * sizeof(unsigned short);
 }
 
 template <class P, int K, int ORDER>
-__global__ __launch_bounds__(kPlaneThreads) void k_spread_fwd(Args a) {
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   using T = typename P::real;
   using Acc = typename P::acc;
   using Rec = typename P::rec;
   constexpr int M = K / 2, KH = K / 2 + 1;
-  constexpr int PITCH = plane_pitch<P>(K);
-  constexpr int PC = P::fixed ? PITCH : PITCH / 2;
+  constexpr int NQ = nq_of(K), R = K / NQ;
+  constexpr int PITCH = tile_pitch<P>(K);
   extern __shared__ __align__(16) unsigned char smem[];
-  Acc* plane = reinterpret_cast<Acc*>(smem);
-  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + (size_t)K * PITCH * 8);
+  Acc* tile = reinterpret_cast<Acc*>(smem);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + (size_t)R * PITCH * 8);
   double* red = reinterpret_cast<double*>(tw + K);
-  int* segpre = reinterpret_cast<int*>(red + 16);
-  int* segbeg = segpre + kPlaneThreads + 1;
-  int* wsum = segbeg + kPlaneThreads;
+  int* segpre = reinterpret_cast<int*>(red + block_sum_doubles(1, kSpreadThreads));
+  int* segbeg = segpre + kSpreadThreads + 2;
+  int* wsum = segbeg + kSpreadThreads;
+  unsigned short* imap = reinterpret_cast<unsigned short*>(wsum + 32);
 
-  const int z = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  TRACE(1, 0);
+  const int z = blockIdx.x / NQ, qs = blockIdx.x - z * NQ, y0 = qs * R;
+  const int tid = threadIdx.x;
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
-  for (int i = tid; i < K * PITCH; i += kPlaneThreads) plane[i] = Acc(0);
+  for (int i = tid; i < K; i += kSpreadThreads) tw[i] = twg[i];
+  for (int i = tid; i < R * PITCH; i += kSpreadThreads) tile[i] = Acc(0);
   const int* cnt = reinterpret_cast<const int*>(a.ws + a.lay.cnt);
   const int* off = reinterpret_cast<const int*>(a.ws + a.lay.off);
   const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
   const double scale = ldexp(1.0, a.frac_bits);
   __syncthreads();
+  TRACE(1, 1);
 
-  // --- spreading.  Plane z receives the atoms whose base z index b lies in
-  // z .. z+p-1 (mod K); for b = z + j the plane is support point jz = p-1-j.
-  // A segment is the run of such atoms inside one sorted chunk; segments are
-  // taken kPlaneThreads at a time.  Each thread owns kItems (atom, plane)
-  // items per pass and adds all p x p contributions of each; the items'
-  // lookups and record loads are issued together so their latencies overlap.
+  // --- spreading.  The tile (rows y0 .. y0+R-1 of plane z) receives the
+  // atoms whose base z index b lies in z .. z+p-1 (mod K) -- for b = z + j
+  // the plane is support point jz = p-1-j -- and whose base y index lies in
+  // this slice, or in the head (first p-1 rows) of the next slice: an atom
+  // touches rows g_y-p+1 .. g_y.  A segment is the run of one such bin
+  // (z, slice, head/body) inside one sorted chunk; segments are taken
+  // kSpreadThreads at a time and their items are numbered consecutively.  An
+  // LDS map gives each item's segment; each thread then owns kItems items per
+  // pass so that their record loads overlap.
   constexpr int kItems = 4;
-  const int nseg = a.n_chunks * ORDER;
-  for (int s0 = 0; s0 < nseg; s0 += kPlaneThreads) {
-    const int ns = min(kPlaneThreads, nseg - s0);
-    int len = 0;
+  constexpr int NB = 2 * K * NQ;
+  constexpr int SPJ = 3;  // segments per (chunk, j): own head, own body, next head
+  const int nseg = a.n_chunks * ORDER * SPJ;
+  for (int s0 = 0; s0 < nseg; s0 += kSpreadThreads) {
+    const int ns = min(kSpreadThreads, nseg - s0);
+    int len = 0, beg = 0;
     if (tid < ns) {
       const int seg = s0 + tid;
-      const int c = seg / ORDER, j = seg - c * ORDER;
-      int b = z + j;
-      if (b >= K) b -= K;
-      len = cnt[(size_t)c * K + b];
-      segbeg[tid] = c * kChunk + off[(size_t)c * K + b];
+      const int c = seg / (SPJ * ORDER), rem = seg - c * SPJ * ORDER;
+      const int j = rem / SPJ, d = rem - j * SPJ;
+      int bz = z + j;
+      if (bz >= K) bz -= K;
+      int by = qs + (d == 2 ? 1 : 0);
+      if (by >= NQ) by -= NQ;
+      const int b = (bz * NQ + by) * 2 + (d == 1 ? 1 : 0);
+      len = cnt[(size_t)c * NB + b];
+      beg = c * kChunk + off[(size_t)c * NB + b];
     }
     int total;
     const int ex = block_exclusive_scan(len, wsum, &total);
-    if (tid < ns) segpre[tid] = ex;
-    if (tid == 0) segpre[ns] = total;
-    __syncthreads();
-    for (int it = 0; it < total; it += kItems * kPlaneThreads) {
-      Rec r[kItems];
-      int jz[kItems];
-#pragma unroll
-      for (int u = 0; u < kItems; ++u) {
-        const int t = it + u * kPlaneThreads + tid;
-        jz[u] = -1;
-        if (t < total) {
-          int lo = 0, hi = ns;  // segpre[lo] <= t < segpre[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (segpre[mid] <= t) lo = mid;
-            else hi = mid;
-          }
-          r[u] = rec[segbeg[lo] + (t - segpre[lo])];
-          jz[u] = ORDER - 1 - (s0 + lo) % ORDER;
-        }
+    if (tid < ns) {
+      segpre[tid] = ex;
+      segbeg[tid] = beg;
+    }
+    for (int w0 = 0; w0 < total; w0 += kItemMap) {
+      const int wn = min(kItemMap, total - w0);
+      // map the items of this window to their segments
+      if (tid < ns) {
+        const int lo = max(ex, w0), hi = min(ex + len, w0 + wn);
+        for (int t = lo; t < hi; ++t) imap[t - w0] = (unsigned short)tid;
       }
+      __syncthreads();
+      for (int it = 0; it < wn; it += kItems * kSpreadThreads) {
+        int idx[kItems], jz[kItems];
 #pragma unroll
-      for (int u = 0; u < kItems; ++u) {
-        if (jz[u] < 0) continue;
-        const int gx = r[u].g & 1023, gy = (r[u].g >> 10) & 1023;
-        T thx[ORDER], thy[ORDER], thz[ORDER];
-        bspline<ORDER>(r[u].w[0], thx, (T*)nullptr);
-        bspline<ORDER>(r[u].w[1], thy, (T*)nullptr);
-        bspline<ORDER>(r[u].w[2], thz, (T*)nullptr);
-        const T tz = pick<ORDER>(thz, jz[u]);
-        int xs[ORDER];
-#pragma unroll
-        for (int jx = 0; jx < ORDER; ++jx) {
-          int x = gx - ORDER + 1 + jx;
-          xs[jx] = x < 0 ? x + K : x;
+        for (int u = 0; u < kItems; ++u) {
+          const int t = it + u * kSpreadThreads + tid;
+          jz[u] = -1;
+          idx[u] = 0;
+          if (t < wn) {
+            const int sg = imap[t];
+            idx[u] = segbeg[sg] + (w0 + t - segpre[sg]);
+            jz[u] = ORDER - 1 - ((s0 + sg) % (SPJ * ORDER)) / SPJ;
+          }
         }
+        Rec r[kItems];
 #pragma unroll
-        for (int jy = 0; jy < ORDER; ++jy) {
-          int y = gy - ORDER + 1 + jy;
-          if (y < 0) y += K;
-          Acc* row = plane + y * PITCH;
+        for (int u = 0; u < kItems; ++u)
+          if (jz[u] >= 0) r[u] = rec[idx[u]];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+          if (jz[u] < 0) continue;
+          const int gx = r[u].g & 1023, gy = (r[u].g >> 10) & 1023;
+          T tx[ORDER], ty[ORDER], tz[ORDER];
+          bspline<ORDER>(r[u].w[0], tx, (T*)nullptr);
+          bspline<ORDER>(r[u].w[1], ty, (T*)nullptr);
+          bspline<ORDER>(r[u].w[2], tz, (T*)nullptr);
+          int xs[ORDER];
+#pragma unroll
+          for (int jx = 0; jx < ORDER; ++jx) {
+            const int x = gx - ORDER + 1 + jx;
+            xs[jx] = x < 0 ? x + K : x;
+          }
           if constexpr (P::fixed) {
 #pragma clang fp contract(off)
-            const float cy = (r[u].q * tz) * thy[jy];  // product order z, y, x
+            const float cz = r[u].q * pick<ORDER>(tz, jz[u]);  // product order z, y, x
 #pragma unroll
-            for (int jx = 0; jx < ORDER; ++jx) {
-              const float cq = cy * thx[jx];
-              atomicAdd(&row[xs[jx]], (unsigned long long)to_fixed(cq, scale));
+            for (int jy = 0; jy < ORDER; ++jy) {
+              int dy = gy - ORDER + 1 + jy - y0;
+              if (dy < 0) dy += K;
+              if (dy >= R) continue;
+              Acc* row = tile + dy * PITCH;
+              const float cy = cz * ty[jy];
+#pragma unroll
+              for (int jx = 0; jx < ORDER; ++jx)
+                atomicAdd(&row[xs[jx]], (unsigned long long)to_fixed(cy * tx[jx], scale));
             }
           } else {
-            const T cy = r[u].q * tz * thy[jy];
+            const double cz = r[u].q * pick<ORDER>(tz, jz[u]);
 #pragma unroll
-            for (int jx = 0; jx < ORDER; ++jx) atomicAdd(&row[xs[jx]], cy * thx[jx]);
+            for (int jy = 0; jy < ORDER; ++jy) {
+              int dy = gy - ORDER + 1 + jy - y0;
+              if (dy < 0) dy += K;
+              if (dy >= R) continue;
+              Acc* row = tile + dy * PITCH;
+              const double cy = cz * ty[jy];
+#pragma unroll
+              for (int jx = 0; jx < ORDER; ++jx) atomicAdd(&row[xs[jx]], cy * tx[jx]);
+            }
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
+  TRACE(1, 2);
 
-  // --- fixed-point headroom: sum |q| 2^F must stay below 2^52 so that every
-  // grid value and its conversion to FP64 are exact.
-  if (P::fixed && z == 0) {
+  // --- fixed-point headroom: sum |q| 2^F must stay below 2^51 so that every
+  // contribution and grid value is exact in FP64 and the rounding of
+  // to_fixed holds.
+  if (P::fixed && blockIdx.x == 0) {
     const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
-    double s = 0.0;
-    for (int c = tid; c < a.n_chunks; c += kPlaneThreads) s += absq[c];
-    s = block_sum(s, red);
-    if (tid == 0 && s * scale >= 4503599627370496.0)
+    double v[1] = {0.0};
+    for (int c = tid; c < a.n_chunks; c += kSpreadThreads) v[0] += absq[c];
+    const double qsum = block_sums<1>(v, red);
+    if (tid == 0 && qsum * scale >= 2251799813685248.0)
       atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
   }
   if (a.keep_grid) {
-    Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + (size_t)z * K * K;
-    for (int i = tid; i < K * K; i += kPlaneThreads) dbg[i] = plane[(i / K) * PITCH + (i % K)];
+    Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + ((size_t)z * K + y0) * K;
+    for (int i = tid; i < R * K; i += kSpreadThreads) dbg[i] = tile[(i / K) * PITCH + (i % K)];
+    __syncthreads();  // the x transform below overwrites the tile in place
   }
-  __syncthreads();
 
   // --- x: real-to-complex, one row per group of fft_lanes(M) lanes.
   constexpr int TM = fft_lanes(M);
-  for (int task = tid; task < K * TM; task += kPlaneThreads) {
+  for (int task = tid; task < R * TM; task += kSpreadThreads) {
     const int y = task / TM, l = task - y * TM;
-    cplx<T>* row = reinterpret_cast<cplx<T>*>(plane + y * PITCH);
+    cplx<T>* row = reinterpret_cast<cplx<T>*>(tile + y * PITCH);
     if constexpr (P::fixed) {
       // int64 -> float in place: x_j at float slot j, so the row reads as the
       // packed complex sequence z_n = x_{2n} + i x_{2n+1}
@@ -335,7 +389,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_spread_fwd(Args a) {
       float v[PER];
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        const long long iv = (long long)plane[y * PITCH + l + i * TM];
+        const long long iv = (long long)tile[y * PITCH + l + i * TM];
         v[i] = (float)((double)iv * inv_scale);
       }
       lds_order();
@@ -347,21 +401,64 @@ __global__ __launch_bounds__(kPlaneThreads) void k_spread_fwd(Args a) {
     r2c_post<T, K>(row, l, tw);
   }
   __syncthreads();
+  TRACE(1, 3);
 
-  // --- y: complex FFT down each of the K/2+1 columns.
-  constexpr int TK = fft_lanes(K);
-  cplx<T>* pc = reinterpret_cast<cplx<T>*>(plane);
-  for (int task = tid; task < KH * TK; task += kPlaneThreads) {
-    const int x = task / TK, l = task - x * TK;
-    fft_pencil<T, K, -1>(pc + x, PC, l, tw, 1);
+  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + ((size_t)z * K + y0) * KH;
+  constexpr int PC = P::fixed ? PITCH : PITCH / 2;
+  const cplx<T>* tc = reinterpret_cast<const cplx<T>*>(tile);
+  for (int i = tid; i < R * KH; i += kSpreadThreads) {
+    const int y = i / KH, x = i - y * KH;
+    spec[i] = tc[y * PC + x];
   }
-  __syncthreads();
+  TRACE(1, 15);
+}
 
+// ---------------------------------------------------------------------------
+// k_fft_y: forward y FFT of one z-plane of the half spectrum.
+// ---------------------------------------------------------------------------
+template <class P, int K>
+__host__ __device__ constexpr size_t plane_lds_bytes() {
+  return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
+         (size_t)K * sizeof(cplx<typename P::real>);
+}
+// k_inv_xy also hosts the energy/virial reduction workgroup.
+template <class P, int K>
+__host__ __device__ constexpr size_t inv_lds_bytes() {
+  return plane_lds_bytes<P, K>() > block_sum_doubles(7, kPlaneThreads) * sizeof(double)
+             ? plane_lds_bytes<P, K>()
+             : block_sum_doubles(7, kPlaneThreads) * sizeof(double);
+}
+
+template <class P, int K>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a) {
+  using T = typename P::real;
+  constexpr int KH = K / 2 + 1, PC = KH + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = pl + K * PC;
+  TRACE(2, 0);
+  const int z = blockIdx.x, tid = threadIdx.x;
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
   for (int i = tid; i < K * KH; i += kPlaneThreads) {
     const int y = i / KH, x = i - y * KH;
-    spec[i] = pc[y * PC + x];
+    pl[y * PC + x] = spec[i];
   }
+  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
+  __syncthreads();
+  TRACE(2, 1);
+  constexpr int TK = fft_lanes(K);
+  for (int task = tid; task < KH * TK; task += kPlaneThreads) {
+    const int x = task / TK, l = task - x * TK;
+    fft_pencil<T, K, -1>(pl + x, PC, l, tw, 1);
+  }
+  __syncthreads();
+  TRACE(2, 2);
+  for (int i = tid; i < K * KH; i += kPlaneThreads) {
+    const int y = i / KH, x = i - y * KH;
+    spec[i] = pl[y * PC + x];
+  }
+  TRACE(2, 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,7 +469,7 @@ __host__ __device__ constexpr size_t pencil_lds_bytes() {
   constexpr int KH = K / 2 + 1, XW = (KH + pencil_xsplit(K) - 1) / pencil_xsplit(K);
   return (size_t)K * (XW + 1) * sizeof(cplx<typename P::real>) +
          (size_t)K * sizeof(cplx<typename P::real>) + 3 * (size_t)K * sizeof(double) +
-         8 * (kPencilThreads / 64) * sizeof(double) + 16;
+         block_sum_doubles(7, kPencilThreads) * sizeof(double);
 }
 
 template <class P, int K>
@@ -388,8 +485,8 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
   cplx<T>* tw = buf + K * PW;
   double* bs = reinterpret_cast<double*>(tw + K);
   double* red = bs + 3 * K;
-  __shared__ int is_last;
 
+  TRACE(3, 0);
   const int tid = threadIdx.x;
   const int y = blockIdx.x / XS;
   const int x0 = (blockIdx.x - y * XS) * XW;
@@ -397,13 +494,23 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec);
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
-  for (int i = tid; i < K; i += kPencilThreads) tw[i] = twg[i];
-  for (int i = tid; i < 3 * K; i += kPencilThreads) bs[i] = bsg[i];
   for (int i = tid; i < K * XW; i += kPencilThreads) {
     const int zz = i / XW, xx = i - zz * XW;
     if (xx < xw) buf[zz * PW + xx] = spec[((size_t)zz * K + y) * KH + x0 + xx];
   }
+  for (int i = tid; i < K; i += kPencilThreads) tw[i] = twg[i];
+  {
+    // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
+    const double fac = PI * PI / (a.beta * a.beta);
+    for (int i = tid; i < 3 * K; i += kPencilThreads) {
+      const int ax = i / K, m = i - ax * K;
+      const int mt = (m <= K / 2) ? m : m - K;
+      const double u = mt * a.invL[ax];
+      bs[i] = bsg[i] * exp(-fac * u * u);
+    }
+  }
   __syncthreads();
+  TRACE(3, 1);
 
   constexpr int TK = fft_lanes(K);
   for (int task = tid; task < XW * TK; task += kPencilThreads) {
@@ -411,15 +518,18 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
     if (xx < xw) fft_pencil<T, K, -1>(buf + xx, PW, l, tw, 1);
   }
   __syncthreads();
+  TRACE(3, 2);
 
-  // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2); the half spectrum
-  // counts every m1 = 1 .. K/2-1 twice (its Hermitian partner), m1 = 0 and
-  // m1 = K/2 once.
+  // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2).  In an
+  // orthorhombic cell B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3).
+  // The half spectrum counts every m1 = 1 .. K/2-1 twice (its Hermitian
+  // partner), m1 = 0 and m1 = K/2 once.
   const double pref = a.coulomb / (PI * a.volume);
   const double fac = PI * PI / (a.beta * a.beta);
   const int my = (y <= K / 2) ? y : y - K;
   const double mvy = my * a.invL[1];
   const double ny = (2 * y == K) ? 0.0 : mvy;
+  const double Ty = bs[K + y];
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int i = tid; i < K * XW; i += kPencilThreads) {
     const int zz = i / XW, xx = i - zz * XW;
@@ -432,8 +542,9 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
     const double msq = mvx * mvx + mvy * mvy + mvz * mvz;
     double G = 0.0, t = 0.0;
     if (m1 != 0 || y != 0 || zz != 0) {
-      G = pref * bs[m1] * bs[K + y] * bs[2 * K + zz] * exp(-fac * msq) / msq;
-      t = 2.0 * (1.0 + fac * msq) / msq;
+      const double inv = 1.0 / msq;
+      G = pref * bs[m1] * Ty * bs[2 * K + zz] * inv;
+      t = 2.0 * (inv + fac);
     }
     cplx<T> f = buf[zz * PW + xx];
     const double f2 = (double)f.x * (double)f.x + (double)f.y * (double)f.y;
@@ -448,67 +559,48 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
     const T g = (T)G;
     buf[zz * PW + xx] = {f.x * g, f.y * g};
   }
-  __syncthreads();
+  // Energy/virial: fixed-order block sums, one partial row per workgroup,
+  // added in workgroup order by the next kernel on the stream.  (Done before
+  // the final stores: a barrier after global stores waits for them.)
+  const double tot = block_sums<7>(acc, red);
+  if (tid < 7) reinterpret_cast<double*>(a.ws + a.lay.partial)[blockIdx.x * 8 + tid] = tot;
+  TRACE(3, 3);
 
   for (int task = tid; task < XW * TK; task += kPencilThreads) {
     const int xx = task / TK, l = task - xx * TK;
     if (xx < xw) fft_pencil<T, K, 1>(buf + xx, PW, l, tw, 1);
   }
   __syncthreads();
+  TRACE(3, 4);
   for (int i = tid; i < K * XW; i += kPencilThreads) {
     const int zz = i / XW, xx = i - zz * XW;
     if (xx < xw) spec[((size_t)zz * K + y) * KH + x0 + xx] = buf[zz * PW + xx];
   }
+  TRACE(3, 15);
+}
 
-  // Energy/virial: fixed-order block sums, one partial row per workgroup;
-  // the last workgroup to finish adds the rows in workgroup order.
-  double* partial = reinterpret_cast<double*>(a.ws + a.lay.partial);
-  double tot[7];
+// Sum of the energy/virial partial rows in row order by one workgroup.
+__device__ void reduce_ev(const Args& a, double* red) {
+  const double* partial = reinterpret_cast<const double*>(a.ws + a.lay.partial);
+  const int rows = a.lay.pencil_blocks;
+  double r[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < rows; b += blockDim.x) {
 #pragma unroll
-  for (int c = 0; c < 7; ++c) tot[c] = block_sum(acc[c], red);
-  if (tid == 0) {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) partial[blockIdx.x * 8 + c] = tot[c];
-    __threadfence();
-    unsigned* ticket = reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl) + 1;
-    const unsigned prev =
-        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == gridDim.x - 1);
+    for (int c = 0; c < 7; ++c) r[c] += partial[b * 8 + c];
   }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    // every thread loads whole partial rows (in parallel), then the same
-    // fixed-order block sum as above
-    double r[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (unsigned b = tid; b < gridDim.x; b += kPencilThreads) {
-#pragma unroll
-      for (int c = 0; c < 7; ++c)
-        r[c] += __hip_atomic_load(&partial[b * 8 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    double sum[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) sum[c] = block_sum(r[c], red);
-    if (tid == 0) {
-      if (a.ev != nullptr) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) a.ev[c] = sum[c];
-      }
-      unsigned* ticket = reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl) + 1;
-      __hip_atomic_store(ticket, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  const double tot = block_sums<7>(r, red);
+  if (threadIdx.x < 7) a.ev[threadIdx.x] = tot;
+}
+
+// (same block size as k_inv_xy's reduction workgroup: identical sum order)
+__global__ __launch_bounds__(kPlaneThreads) void k_reduce_ev(Args a) {
+  __shared__ double red[block_sum_doubles(7, kPlaneThreads)];
+  reduce_ev(a, red);
 }
 
 // ---------------------------------------------------------------------------
 // k_inv_xy: inverse y FFT and complex-to-real x FFT of one z-plane.
 // ---------------------------------------------------------------------------
-template <class P, int K>
-__host__ __device__ constexpr size_t inv_lds_bytes() {
-  return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
-         (size_t)K * sizeof(cplx<typename P::real>);
-}
-
 template <class P, int K, int ORDER>
 __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
   using T = typename P::real;
@@ -517,15 +609,22 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K * PC;
+  TRACE(4, 0);
   const int z = blockIdx.x, tid = threadIdx.x;
-  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
+  if (z == K) {
+    // the extra workgroup: energy and virial
+    reduce_ev(a, reinterpret_cast<double*>(smem));
+    return;
+  }
   const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
   for (int i = tid; i < K * KH; i += kPlaneThreads) {
     const int y = i / KH, x = i - y * KH;
     pl[y * PC + x] = spec[i];
   }
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
   __syncthreads();
+  TRACE(4, 1);
 
   constexpr int TK = fft_lanes(K);
   for (int task = tid; task < KH * TK; task += kPlaneThreads) {
@@ -533,6 +632,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
     fft_pencil<T, K, 1>(pl + x, PC, l, tw, 1);
   }
   __syncthreads();
+  TRACE(4, 2);
 
   constexpr int TM = fft_lanes(M);
   for (int task = tid; task < K * TM; task += kPlaneThreads) {
@@ -542,6 +642,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
     fft_pencil<T, M, 1>(row, 1, l, tw, 2);
   }
   __syncthreads();
+  TRACE(4, 3);
 
   T* phi = reinterpret_cast<T*>(a.ws + a.lay.phi) + (size_t)z * K * PP;
   for (int i = tid; i < K * PP; i += kPlaneThreads) {
@@ -551,6 +652,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
     if (x >= K) x -= K;
     phi[i] = reinterpret_cast<const T*>(pl + y * PC)[x];
   }
+  TRACE(4, 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,6 +663,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Args a) {
   using T = typename P::real;
   using Rec = typename P::rec;
   constexpr int PP = phi_pitch_of(K, ORDER);
+  TRACE(5, 0);
   const int t = blockIdx.x * kGatherThreads + threadIdx.x;
   if (t >= a.N) return;
   const Rec r = reinterpret_cast<const Rec*>(a.ws + a.lay.rec)[t];
@@ -607,6 +710,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Args a) {
     out[1] = f[1];
     out[2] = f[2];
   }
+  TRACE(5, 15);
 }
 
 __global__ void k_clear_flags(unsigned* ctrl) {
@@ -618,6 +722,25 @@ __global__ void k_clear_flags(unsigned* ctrl) {
 // ---------------------------------------------------------------------------
 template <int V>
 using ic = std::integral_constant<int, V>;
+
+// Launch with optional timing events attached to the dispatch itself (the
+// kernel's own start and end), or plainly.
+template <typename Kern>
+hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, const Timing& t,
+                  const Args& a) {
+  if (t.start != nullptr)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t.start, t.stop, 0u, a);
+  else
+    kernel<<<grid, block, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+// A launch that is skipped still closes its timing window.
+static hipError_t skip(hipStream_t s, const Timing& t) {
+  if (t.start == nullptr) return hipSuccess;
+  hipError_t e = hipEventRecord(t.start, s);
+  return e == hipSuccess ? hipEventRecord(t.stop, s) : e;
+}
 
 template <class F>
 hipError_t with_prec(int prec, F&& f) {
@@ -660,13 +783,14 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   const size_t real = fx ? 4 : 8, cpx = 2 * real;
   const size_t kh = (size_t)K / 2 + 1;
   const int nch = (max_atoms + kChunk - 1) / kChunk;
+  const size_t nbins = 2 * (size_t)K * nq_of(K);
   Layout L{};
   size_t o = 0;
   L.ctrl = o;      o = align256(o + 64 * sizeof(unsigned));
   L.bsq = o;       o = align256(o + 3 * (size_t)K * sizeof(double));
   L.tw = o;        o = align256(o + (size_t)K * cpx);
-  L.cnt = o;       o = align256(o + (size_t)nch * K * sizeof(int));
-  L.off = o;       o = align256(o + (size_t)nch * K * sizeof(int));
+  L.cnt = o;       o = align256(o + (size_t)nch * nbins * sizeof(int));
+  L.off = o;       o = align256(o + (size_t)nch * nbins * sizeof(int));
   L.absq = o;      o = align256(o + (size_t)nch * sizeof(double));
   L.rec = o;       o = align256(o + (size_t)nch * kChunk * (fx ? sizeof(RecF) : sizeof(RecD)));
   L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
@@ -689,75 +813,89 @@ hipError_t prepare_kernels(int K, int order, int precision) {
       constexpr int KK = decltype(kc)::value;
       return with_order(order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        hipError_t e = hipFuncSetAttribute((const void*)k_spread_fwd<P, KK, O>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+        const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+        hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O>, attr,
                                            (int)spread_lds_bytes<P, KK>());
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)inv_lds_bytes<P, KK>());
-        if (e != hipSuccess) return e;
-        return hipFuncSetAttribute((const void*)k_pencil<P, KK>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)pencil_lds_bytes<P, KK>());
+        if (e == hipSuccess)
+          e = hipFuncSetAttribute((const void*)k_fft_y<P, KK>, attr, (int)plane_lds_bytes<P, KK>());
+        if (e == hipSuccess)
+          e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O>, attr,
+                                  (int)inv_lds_bytes<P, KK>());
+        if (e == hipSuccess)
+          e = hipFuncSetAttribute((const void*)k_pencil<P, KK>, attr,
+                                  (int)pencil_lds_bytes<P, KK>());
+        return e;
       });
     });
   });
 }
 
-hipError_t launch_bin(const Args& a, hipStream_t s) {
-  if (a.n_chunks == 0) return hipSuccess;
+hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t) {
+  if (a.n_chunks == 0) return skip(s, t);
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    k_bin<P><<<dim3(a.n_chunks), dim3(kBinThreads), 0, s>>>(a);
-    return hipGetLastError();
+    return launch(k_bin<P>, dim3(a.n_chunks), dim3(kBinThreads), 0, s, t, a);
   });
 }
 
-hipError_t launch_spread_fwd(const Args& a, hipStream_t s) {
+hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        constexpr size_t lds = spread_lds_bytes<P, KK>();
-        k_spread_fwd<P, KK, O><<<dim3(KK), dim3(kPlaneThreads), lds, s>>>(a);
-        return hipGetLastError();
+        return launch(k_spread_x<P, KK, O>, dim3(KK * nq_of(KK)), dim3(kSpreadThreads),
+                      spread_lds_bytes<P, KK>(), s, t, a);
       });
     });
   });
 }
 
-hipError_t launch_pencil(const Args& a, hipStream_t s) {
+hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
-      constexpr size_t lds = pencil_lds_bytes<P, KK>();
-      k_pencil<P, KK><<<dim3(KK * pencil_xsplit(KK)), dim3(kPencilThreads), lds, s>>>(a);
-      return hipGetLastError();
+      return launch(k_fft_y<P, KK>, dim3(KK), dim3(kPlaneThreads), plane_lds_bytes<P, KK>(), s, t,
+                    a);
     });
   });
 }
 
-hipError_t launch_inv(const Args& a, hipStream_t s) {
+hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t) {
+  return with_prec(a.precision, [&](auto pt) {
+    using P = decltype(pt);
+    return with_K(a.K, [&](auto kc) {
+      constexpr int KK = decltype(kc)::value;
+      return launch(k_pencil<P, KK>, dim3(KK * pencil_xsplit(KK)), dim3(kPencilThreads),
+                    pencil_lds_bytes<P, KK>(), s, t, a);
+    });
+  });
+}
+
+hipError_t launch_reduce_ev(const Args& a, hipStream_t s) {
+  k_reduce_ev<<<dim3(1), dim3(kPlaneThreads), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        constexpr size_t lds = inv_lds_bytes<P, KK>();
-        k_inv_xy<P, KK, O><<<dim3(KK), dim3(kPlaneThreads), lds, s>>>(a);
-        return hipGetLastError();
+        const int blocks = KK + (a.reduce_ev ? 1 : 0);
+        return launch(k_inv_xy<P, KK, O>, dim3(blocks), dim3(kPlaneThreads), inv_lds_bytes<P, KK>(),
+                      s, t, a);
       });
     });
   });
 }
 
-hipError_t launch_gather(const Args& a, hipStream_t s) {
-  if (a.N == 0) return hipSuccess;
+hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t) {
+  if (a.N == 0) return skip(s, t);
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
@@ -765,8 +903,7 @@ hipError_t launch_gather(const Args& a, hipStream_t s) {
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
         const int blocks = (a.N + kGatherThreads - 1) / kGatherThreads;
-        k_gather<P, KK, O><<<dim3(blocks), dim3(kGatherThreads), 0, s>>>(a);
-        return hipGetLastError();
+        return launch(k_gather<P, KK, O>, dim3(blocks), dim3(kGatherThreads), 0, s, t, a);
       });
     });
   });
@@ -778,3 +915,12 @@ hipError_t launch_clear_flags(const Args& a, hipStream_t s) {
 }
 
 }  // namespace spme
+
+#ifdef SPME_TRACE
+// Trace builds only: point the phase trace at a device buffer of
+// 6 * 1024 * 16 uint64 (or NULL to stop tracing).
+extern "C" int spme_trace_set(void* buf) {
+  unsigned long long* p = static_cast<unsigned long long*>(buf);
+  return hipMemcpyToSymbol(HIP_SYMBOL(spme::g_trace), &p, sizeof(p)) == hipSuccess ? 0 : 5;
+}
+#endif

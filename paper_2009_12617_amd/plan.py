@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import PME_FP32_FIXED, PME_FP64, check
 
-KERNEL_NAMES = ("bin", "spread_xy", "convolve_z", "inverse_xy", "gather")
+KERNEL_NAMES = ("bin", "spread_x", "fft_y", "convolve_z", "inverse_xy", "gather")
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64}
 
 
