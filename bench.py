@@ -57,18 +57,22 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload="water_65535_k64"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when missing or taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     try:
-        d = json.load(open(path))
-    except (OSError, ValueError):
+        lines = open(path).read().splitlines()
+    except OSError:
         return None
-    if d.get("source_digest") != source_digest():
-        return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    for line in lines:
+        if line.startswith("BENCH_TRAFFIC_JSON "):
+            d = json.loads(line.split(" ", 1)[1])
+            if d.get("source_digest") != source_digest():
+                return None
+            k = d.get("kernels", {}).get(kernel)
+            return None if k is None else k.get("bytes_per_launch")
+    return None
 
 
 def main():
@@ -83,6 +87,9 @@ def main():
     ap.add_argument("--parity-frames", type=int, default=3)
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="with --profile: also run one plain device copy of this many MiB "
+                         "(calibrates hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -215,6 +222,15 @@ def main():
         print("bench.py: graph replay differs from host-launched steps", file=sys.stderr)
         sys.exit(1)
     if args.profile:
+        if args.copy_mib > 0:
+            n = args.copy_mib * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            print(f"# calibration copy: {args.copy_mib} MiB read + {args.copy_mib} MiB written",
+                  file=sys.stderr, flush=True)
         print(json.dumps({"metric": "us/PME step (65,535 atoms, 64^3)", "value": ms_step * 1e3,
                           "unit": "us/step", "mode": "profile",
                           "host_launched_us_per_step": ms_eager * 1e3}))

@@ -11,9 +11,10 @@ constexpr int kChunk = 1024;         // atoms per binning workgroup (one sorted 
 constexpr int kBinThreads = 1024;    // one atom per thread
 constexpr int kMaxBins = 1024;       // (z, y slice, head/body) bins per chunk: 2 K nq <= 1024
 constexpr int kItemMap = 4096;       // items per window of the spreading item map
+constexpr int kSegPerThread = 4;     // spreading segments described per thread per batch
 constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
 constexpr int kPlaneThreads = 512;   // one z-plane per workgroup
-constexpr int kPencilThreads = 256;  // z-pencils of one (y, x-range) per workgroup
+constexpr int kPencilThreads = 512;  // z-pencils of one (y, x-range) per workgroup
 constexpr int kGatherThreads = 256;  // one atom per thread
 constexpr int kNumKernels = 6;       // bin, spread+x, y, z-convolution, inverse xy, gather
 
@@ -49,8 +50,8 @@ struct Layout {
   size_t ctrl;     // unsigned[64]: [0] sticky flags
   size_t bsq;      // double[3][K]: squared B-spline moduli per axis
   size_t tw;       // complex[K]: exp(-2 pi i k/K), float2 or double2
-  size_t cnt;      // int[n_chunks][2 K nq]: atoms of chunk c in bin (z, y slice, head/body)
-  size_t off;      // int[n_chunks][2 K nq]: exclusive prefix of cnt within the chunk
+  size_t cnt;      // int2[n_chunks][2 K nq]: (count, offset within the chunk) of the
+                   // atoms of chunk c in bin (z, y slice, head/body)
   size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
   size_t rec;      // records [n_chunks * kChunk] (RecF or RecD)
   size_t spec;     // complex[K][K][K/2+1] half spectrum

@@ -152,8 +152,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a) {
   TRACE(0, 0);
   const int K = a.K, nq = nq_of(a.K), rows = K / nq, nbins = 2 * K * nq;
   const int c = blockIdx.x, tid = threadIdx.x;
-  int* cnt = reinterpret_cast<int*>(a.ws + a.lay.cnt) + (size_t)c * nbins;
-  int* off = reinterpret_cast<int*>(a.ws + a.lay.off) + (size_t)c * nbins;
+  int2* cnt = reinterpret_cast<int2*>(a.ws + a.lay.cnt) + (size_t)c * nbins;
   Rec* rec = reinterpret_cast<Rec*>(a.ws + a.lay.rec) + (size_t)c * kChunk;
   unsigned* flags = reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl);
   for (int b = tid; b < nbins; b += kBinThreads) hist[b] = 0;
@@ -202,10 +201,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a) {
   __syncthreads();
   TRACE(0, 3);
   if (bin >= 0) rec[hist[bin] + rank] = r;
-  if (tid < nbins) {
-    cnt[tid] = h;
-    off[tid] = ex;
-  }
+  if (tid < nbins) cnt[tid] = make_int2(h, ex);
   if (tid == 0) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = qsum;
   TRACE(0, 15);
 }
@@ -218,8 +214,8 @@ template <class P, int K>
 __host__ __device__ constexpr size_t spread_lds_bytes() {
   return (size_t)(K / nq_of(K)) * tile_pitch<P>(K) * 8 +
          (size_t)K * sizeof(cplx<typename P::real>) +
-         block_sum_doubles(1, kSpreadThreads) * sizeof(double) +
-         (size_t)(2 * kSpreadThreads + 2 + 32) * sizeof(int) + kItemMap * sizeof(unsigned short);
+         (size_t)(2 * kSegPerThread * kSpreadThreads + 2 + 32) * sizeof(int) +
+         kItemMap * sizeof(unsigned short);
 }
 
 template <class P, int K, int ORDER>
@@ -233,10 +229,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Acc* tile = reinterpret_cast<Acc*>(smem);
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + (size_t)R * PITCH * 8);
-  double* red = reinterpret_cast<double*>(tw + K);
-  int* segpre = reinterpret_cast<int*>(red + block_sum_doubles(1, kSpreadThreads));
-  int* segbeg = segpre + kSpreadThreads + 2;
-  int* wsum = segbeg + kSpreadThreads;
+  int* segpre = reinterpret_cast<int*>(tw + K);
+  int* segbeg = segpre + kSegPerThread * kSpreadThreads + 2;
+  int* wsum = segbeg + kSegPerThread * kSpreadThreads;
   unsigned short* imap = reinterpret_cast<unsigned short*>(wsum + 32);
 
   TRACE(1, 0);
@@ -245,8 +240,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   for (int i = tid; i < K; i += kSpreadThreads) tw[i] = twg[i];
   for (int i = tid; i < R * PITCH; i += kSpreadThreads) tile[i] = Acc(0);
-  const int* cnt = reinterpret_cast<const int*>(a.ws + a.lay.cnt);
-  const int* off = reinterpret_cast<const int*>(a.ws + a.lay.off);
+  const int2* cnt = reinterpret_cast<const int2*>(a.ws + a.lay.cnt);
   const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
   const double scale = ldexp(1.0, a.frac_bits);
   __syncthreads();
@@ -264,34 +258,55 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   constexpr int kItems = 4;
   constexpr int NB = 2 * K * NQ;
   constexpr int SPJ = 3;  // segments per (chunk, j): own head, own body, next head
+  constexpr int SPT = kSegPerThread;
   const int nseg = a.n_chunks * ORDER * SPJ;
-  for (int s0 = 0; s0 < nseg; s0 += kSpreadThreads) {
-    const int ns = min(kSpreadThreads, nseg - s0);
-    int len = 0, beg = 0;
-    if (tid < ns) {
-      const int seg = s0 + tid;
-      const int c = seg / (SPJ * ORDER), rem = seg - c * SPJ * ORDER;
-      const int j = rem / SPJ, d = rem - j * SPJ;
-      int bz = z + j;
-      if (bz >= K) bz -= K;
-      int by = qs + (d == 2 ? 1 : 0);
-      if (by >= NQ) by -= NQ;
-      const int b = (bz * NQ + by) * 2 + (d == 1 ? 1 : 0);
-      len = cnt[(size_t)c * NB + b];
-      beg = c * kChunk + off[(size_t)c * NB + b];
+  for (int s0 = 0; s0 < nseg; s0 += SPT * kSpreadThreads) {
+    const int ns = min(SPT * kSpreadThreads, nseg - s0);
+    // each thread describes SPT consecutive segments
+    int len[SPT], beg[SPT], mine = 0;
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      const int sl = tid * SPT + k;
+      len[k] = 0;
+      beg[k] = 0;
+      if (sl < ns) {
+        const int seg = s0 + sl;
+        const int c = seg / (SPJ * ORDER), rem = seg - c * SPJ * ORDER;
+        const int j = rem / SPJ, d = rem - j * SPJ;
+        int bz = z + j;
+        if (bz >= K) bz -= K;
+        int by = qs + (d == 2 ? 1 : 0);
+        if (by >= NQ) by -= NQ;
+        const int2 v = cnt[(size_t)c * NB + (bz * NQ + by) * 2 + (d == 1 ? 1 : 0)];
+        len[k] = v.x;
+        beg[k] = c * kChunk + v.y;
+      }
+      mine += len[k];
     }
     int total;
-    const int ex = block_exclusive_scan(len, wsum, &total);
-    if (tid < ns) {
-      segpre[tid] = ex;
-      segbeg[tid] = beg;
+    const int ex = block_exclusive_scan(mine, wsum, &total);
+    int pre[SPT];
+    {
+      int run = ex;
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        const int sl = tid * SPT + k;
+        pre[k] = run;
+        if (sl < ns) {
+          segpre[sl] = run;
+          segbeg[sl] = beg[k];
+        }
+        run += len[k];
+      }
     }
+    if (tid == 0) segpre[ns] = total;
     for (int w0 = 0; w0 < total; w0 += kItemMap) {
       const int wn = min(kItemMap, total - w0);
       // map the items of this window to their segments
-      if (tid < ns) {
-        const int lo = max(ex, w0), hi = min(ex + len, w0 + wn);
-        for (int t = lo; t < hi; ++t) imap[t - w0] = (unsigned short)tid;
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        const int lo = max(pre[k], w0), hi = min(pre[k] + len[k], w0 + wn);
+        for (int t = lo; t < hi; ++t) imap[t - w0] = (unsigned short)(tid * SPT + k);
       }
       __syncthreads();
       for (int it = 0; it < wn; it += kItems * kSpreadThreads) {
@@ -359,17 +374,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   }
   TRACE(1, 2);
 
-  // --- fixed-point headroom: sum |q| 2^F must stay below 2^51 so that every
-  // contribution and grid value is exact in FP64 and the rounding of
-  // to_fixed holds.
-  if (P::fixed && blockIdx.x == 0) {
-    const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
-    double v[1] = {0.0};
-    for (int c = tid; c < a.n_chunks; c += kSpreadThreads) v[0] += absq[c];
-    const double qsum = block_sums<1>(v, red);
-    if (tid == 0 && qsum * scale >= 2251799813685248.0)
-      atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
-  }
   if (a.keep_grid) {
     Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + ((size_t)z * K + y0) * K;
     for (int i = tid; i < R * K; i += kSpreadThreads) dbg[i] = tile[(i / K) * PITCH + (i % K)];
@@ -421,6 +425,13 @@ __host__ __device__ constexpr size_t plane_lds_bytes() {
   return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
          (size_t)K * sizeof(cplx<typename P::real>);
 }
+// k_fft_y also hosts the fixed-point headroom workgroup.
+template <class P, int K>
+__host__ __device__ constexpr size_t fft_y_lds_bytes() {
+  return plane_lds_bytes<P, K>() > block_sum_doubles(1, kPlaneThreads) * sizeof(double)
+             ? plane_lds_bytes<P, K>()
+             : block_sum_doubles(1, kPlaneThreads) * sizeof(double);
+}
 // k_inv_xy also hosts the energy/virial reduction workgroup.
 template <class P, int K>
 __host__ __device__ constexpr size_t inv_lds_bytes() {
@@ -438,6 +449,18 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a) {
   cplx<T>* tw = pl + K * PC;
   TRACE(2, 0);
   const int z = blockIdx.x, tid = threadIdx.x;
+  if (z == K) {
+    // the extra workgroup (fixed point only): sum |q| 2^F must stay below
+    // 2^51 so that every contribution and grid value is exact in FP64 and the
+    // rounding of to_fixed holds
+    const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
+    double v[1] = {0.0};
+    for (int c = tid; c < a.n_chunks; c += kPlaneThreads) v[0] += absq[c];
+    const double qsum = block_sums<1>(v, reinterpret_cast<double*>(smem));
+    if (tid == 0 && qsum * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
+      atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
+    return;
+  }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
   for (int i = tid; i < K * KH; i += kPlaneThreads) {
@@ -789,8 +812,7 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   L.ctrl = o;      o = align256(o + 64 * sizeof(unsigned));
   L.bsq = o;       o = align256(o + 3 * (size_t)K * sizeof(double));
   L.tw = o;        o = align256(o + (size_t)K * cpx);
-  L.cnt = o;       o = align256(o + (size_t)nch * nbins * sizeof(int));
-  L.off = o;       o = align256(o + (size_t)nch * nbins * sizeof(int));
+  L.cnt = o;       o = align256(o + (size_t)nch * nbins * 2 * sizeof(int));
   L.absq = o;      o = align256(o + (size_t)nch * sizeof(double));
   L.rec = o;       o = align256(o + (size_t)nch * kChunk * (fx ? sizeof(RecF) : sizeof(RecD)));
   L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
@@ -817,7 +839,7 @@ hipError_t prepare_kernels(int K, int order, int precision) {
         hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O>, attr,
                                            (int)spread_lds_bytes<P, KK>());
         if (e == hipSuccess)
-          e = hipFuncSetAttribute((const void*)k_fft_y<P, KK>, attr, (int)plane_lds_bytes<P, KK>());
+          e = hipFuncSetAttribute((const void*)k_fft_y<P, KK>, attr, (int)fft_y_lds_bytes<P, KK>());
         if (e == hipSuccess)
           e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O>, attr,
                                   (int)inv_lds_bytes<P, KK>());
@@ -857,8 +879,9 @@ hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
-      return launch(k_fft_y<P, KK>, dim3(KK), dim3(kPlaneThreads), plane_lds_bytes<P, KK>(), s, t,
-                    a);
+      const int blocks = KK + (P::fixed ? 1 : 0);
+      return launch(k_fft_y<P, KK>, dim3(blocks), dim3(kPlaneThreads), fft_y_lds_bytes<P, KK>(), s,
+                    t, a);
     });
   });
 }
