@@ -75,6 +75,95 @@ def measured_traffic(kernel, workload="water_65535_k64"):
     return None
 
 
+def bench_batched(torch, dev, Plan, Batch, I, reps=200):
+    """64 independent water boxes of uneven size (3k..65k atoms, grids 32/48/64
+    by ~1 A spacing), one step of all of them per batched run, timed as graph
+    replays; each system's result is checked against its own single step."""
+    mix = I.batch_mix()
+    systems = []
+    for m in mix:
+        pos, q, box = m.make()
+        plan = Plan(m.K, 4, 0.34, max_atoms=len(q), device=dev)
+        dp = torch.from_numpy(pos).to(dev)
+        dq = torch.from_numpy(q).to(dev)
+        f, e = plan.bind(dp, dq, box)
+        systems.append((m, plan, dp, dq, box, f, e))
+    batch = Batch([s[1] for s in systems])
+    for _ in range(3):
+        batch.run()
+    torch.cuda.synchronize()
+    got = [(s[5].clone(), s[6].clone()) for s in systems]
+    same = True
+    for s, (fb, eb) in zip(systems, got):
+        fa, ea = s[1].step(s[2], s[3], s[4])
+        same &= bool(torch.equal(fa, fb)) and bool(torch.equal(ea, eb))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream(device=dev)
+    with torch.cuda.graph(g, stream=cs):
+        batch.run(torch.cuda.current_stream(dev))
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for r in range(reps):
+        g.replay()
+        evs[r + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]) * 1e3
+    replay_same = all(bool(torch.equal(s[5], fb)) and bool(torch.equal(s[6], eb))
+                      for s, (fb, eb) in zip(systems, got))
+    atoms = sum(len(s[3]) for s in systems)
+    grids = {}
+    for m in mix:
+        grids[str(m.K)] = grids.get(str(m.K), 0) + 1
+    nbytes = sum(step_bytes(len(s[3]), s[0].K) for s in systems)
+    return {
+        "workload": "64 water boxes, atoms log-uniform in [3000, 65000], grid by ~1 A spacing, p=4, beta=0.34",
+        "systems": len(systems), "atoms": int(atoms), "grids": grids,
+        "us_per_batch": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                         "mean": float(per.mean()), "replays": reps},
+        "atoms_per_s": atoms / (per.mean() * 1e-6),
+        "step_algorithmic_bytes": int(nbytes),
+        "roofline_frac": nbytes / (per.mean() * 1e-6) / 1e9 / HBM_PEAK_GBS,
+        "same_as_single_steps": bool(same and replay_same),
+        "launch": "one HIP graph: 6 kernels x 3 grid groups, each launch over all systems of its group",
+    }
+
+
+def bench_serving(torch, dev, I, n_requests, rate, budget_gib):
+    """Open-loop Poisson arrivals over the batch mix plus four 128^3 boxes."""
+    from paper_2009_12617_amd.serve import PoolSystem, Server
+    from paper_2009_12617_amd import Plan
+    members = I.serving_pool()
+    pool = []
+    for m in members:
+        pos, q, box = m.make()
+        pool.append(PoolSystem(pos, q, box, m.K))
+    arrivals, ids = I.poisson_requests(n_requests=n_requests, rate=rate)
+    srv = Server(pool, hbm_budget_bytes=int(budget_gib * (1 << 30)), max_batch=64, device=dev)
+    done = srv.run(arrivals, ids)
+    st = srv.stats.summary()
+    # every request's energy against its system's own single step
+    ref_e = {}
+    same = True
+    for r in done:
+        if r.system_id not in ref_e:
+            s = pool[r.system_id]
+            plan = Plan(s.K, 4, 0.34, max_atoms=len(s.q), device=dev)
+            _, e = plan.step(torch.from_numpy(s.pos).to(dev), torch.from_numpy(s.q).to(dev), s.box)
+            ref_e[r.system_id] = e[0].item()
+        same &= (r.energy == ref_e[r.system_id])
+    st.update({
+        "workload": f"{n_requests} requests, Poisson {rate:g}/s; 90% from the 64-box mix, 10% 128^3 / 209,715-atom boxes",
+        "hbm_budget_gib": budget_gib,
+        "energies_same_as_single_steps": bool(same),
+        "latency_definition": "host: scheduled arrival to forces and energy in host memory",
+    })
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +176,11 @@ def main():
     ap.add_argument("--parity-frames", type=int, default=3)
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --profile: also run one plain device copy of this many MiB "
                          "(calibrates hardware byte counters)")
@@ -261,6 +355,20 @@ def main():
                 "step_roofline_frac": step_bytes(N, K, True) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"# fp64: {ms64 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        from paper_2009_12617_amd import Batch
+        batched = bench_batched(torch, dev, Plan, Batch, I)
+        print(f"# batched: {batched['us_per_batch']['mean']:.1f} us per 64-system batch "
+              f"(p99 {batched['us_per_batch']['p99']:.1f}), same as single: {batched['same_as_single_steps']}",
+              file=sys.stderr, flush=True)
+    serving = None
+    if not args.no_serving:
+        serving = bench_serving(torch, dev, I, args.serve_requests, args.serve_rate,
+                                args.serve_budget_gib)
+        print(f"# serving: {serving['throughput_per_s']:.0f} req/s, p50 {serving['latency_us']['p50']:.0f} us, "
+              f"p99 {serving['latency_us']['p99']:.0f} us", file=sys.stderr, flush=True)
+
     parity = None
     cpu = None
     if args.parity_frames > 0 or not args.no_cpu_baseline:
@@ -319,6 +427,8 @@ def main():
         "step_roofline_frac": step_bytes(N, K) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_algorithmic_bytes": step_bytes(N, K),
         "fp64_path": fp64,
+        "batched": batched,
+        "serving": serving,
         "parity": parity,
         "cpu_baseline": cpu,
     }

@@ -134,6 +134,22 @@ int pme_gather(pme_plan *plan, double *forces, int accumulate);
 int pme_step(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
              double *forces, int accumulate, double *ev);
 
+/* Bind the inputs and outputs of this plan's next batched steps (same
+ * meaning and checks as pme_step's arguments).  Copies them synchronously to
+ * the plan's workspace; rebind whenever a pointer, N or the box changes.
+ * Buffers must stay valid while batched runs use them. */
+int pme_bind(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
+             double *forces, int accumulate, double *ev);
+
+/* One step of each of n bound plans in one batched launch sequence on
+ * `stream` (hipStream_t): plans sharing precision, grid and order run as one
+ * launch of each kernel over a second grid dimension, so many independent
+ * systems of uneven size share every dispatch.  Enqueues kernel launches only
+ * (no allocation, copy or synchronisation), so a run can be captured in a
+ * hipGraph and replayed.  Each system's result is the same as its own
+ * pme_step.  Returns PME_ESTATE if a plan was never bound. */
+int pme_batch_run(pme_plan *const *plans, int n, void *stream);
+
 /* Keep a copy of the charge grid at each spread (costs K1 K2 K3 x 8 bytes
  * of extra writes; off by default). */
 int pme_set_debug(pme_plan *plan, int keep_charge_grid);

@@ -67,6 +67,10 @@ def load():
     lib.pme_gather.argtypes = [vp, vp, i]
     lib.pme_step.restype = i
     lib.pme_step.argtypes = [vp, vp, vp, i, dp, vp, i, vp]
+    lib.pme_bind.restype = i
+    lib.pme_bind.argtypes = [vp, vp, vp, i, dp, vp, i, vp]
+    lib.pme_batch_run.restype = i
+    lib.pme_batch_run.argtypes = [ctypes.POINTER(vp), i, vp]
     lib.pme_set_debug.restype = i
     lib.pme_set_debug.argtypes = [vp, i]
     lib.pme_debug_grid.restype = i

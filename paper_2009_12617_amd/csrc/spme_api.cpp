@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/spme.h"
@@ -49,6 +50,9 @@ struct pme_plan {
   size_t event_next = 0;
   std::vector<TimedLaunch> pending;
   int timed_steps = 0;
+  // arguments bound for batched runs (host copy of the device copy)
+  Args bound{};
+  int is_bound = 0;
 };
 
 namespace {
@@ -231,7 +235,11 @@ int pme_set_debug(pme_plan* p, int keep_charge_grid) {
   return PME_OK;
 }
 
-int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const double box[9]) {
+namespace {
+
+// Validate one step's inputs and fill the per-step fields of a.
+int set_inputs(pme_plan* p, Args& a, const double* pos, const double* q, int N,
+               const double box[9]) {
   if (p == nullptr || box == nullptr || N < 0 || N > p->max_atoms) return PME_EINVAL;
   if (N > 0 && (pos == nullptr || q == nullptr)) return PME_EINVAL;
   for (int i = 0; i < 9; ++i)
@@ -240,7 +248,6 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
       box[7] != 0.0)
     return PME_EUNSUPPORTED;  // triclinic cells are not supported on the GPU
   if (!(box[0] > 0.0 && box[4] > 0.0 && box[8] > 0.0)) return PME_EINVAL;
-  Args& a = p->cur;
   a.N = N;
   a.n_chunks = (N + spme::kChunk - 1) / spme::kChunk;
   a.pos = pos;
@@ -254,7 +261,17 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
   a.forces = nullptr;
   a.ev = nullptr;
   a.reduce_ev = 0;
-  int rc = timed(p, 0, [&](const spme::Timing& t) { return spme::launch_bin(a, p->stream, t); });
+  return PME_OK;
+}
+
+}  // namespace
+
+int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const double box[9]) {
+  if (p == nullptr) return PME_EINVAL;
+  Args& a = p->cur;
+  int rc = set_inputs(p, a, pos, q, N, box);
+  if (rc != PME_OK) return rc;
+  rc = timed(p, 0, [&](const spme::Timing& t) { return spme::launch_bin(a, p->stream, t); });
   if (rc == PME_OK)
     rc = timed(p, 1, [&](const spme::Timing& t) { return spme::launch_spread_x(a, p->stream, t); });
   if (rc == PME_OK)
@@ -322,6 +339,97 @@ int pme_step(pme_plan* p, const double* pos, const double* q, int N, const doubl
   if (rc == PME_OK) rc = solve_impl(p, ev, true);
   if (rc == PME_OK) rc = gather_impl(p, forces, accumulate);
   return rc;
+}
+
+int pme_bind(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
+             double* forces, int accumulate, double* ev) {
+  if (p == nullptr) return PME_EINVAL;
+  if (N > 0 && forces == nullptr) return PME_EINVAL;
+  Args b = p->cur;  // plan constants (K, order, precision, tables, layout)
+  int rc = set_inputs(p, b, pos, q, N, box);
+  if (rc != PME_OK) return rc;
+  b.forces = forces;
+  b.accumulate = accumulate ? 1 : 0;
+  b.ev = ev;
+  b.reduce_ev = ev != nullptr ? 1 : 0;
+  if (hipMemcpy(p->ws + p->lay.args, &b, sizeof(Args), hipMemcpyHostToDevice) != hipSuccess)
+    return PME_EDEVICE;
+  p->bound = b;
+  p->is_bound = 1;
+  return PME_OK;
+}
+
+int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
+  if (n < 0 || (n > 0 && plans == nullptr)) return PME_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (plans[i] == nullptr) return PME_EINVAL;
+    if (!plans[i]->is_bound) return PME_ESTATE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // groups of at most kMaxBatch plans sharing (precision, K, order)
+  std::vector<std::vector<int>> groups;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const Args &a = plans[x]->bound, &b = plans[y]->bound;
+    if (a.precision != b.precision) return a.precision < b.precision;
+    if (a.K != b.K) return a.K < b.K;
+    return a.order < b.order;
+  });
+  for (int i : order) {
+    const Args& a = plans[i]->bound;
+    if (!groups.empty()) {
+      const Args& g = plans[groups.back()[0]]->bound;
+      if (g.precision == a.precision && g.K == a.K && g.order == a.order &&
+          (int)groups.back().size() < spme::kMaxBatch) {
+        groups.back().push_back(i);
+        continue;
+      }
+    }
+    groups.push_back({i});
+  }
+  std::vector<spme::BatchArgs> bts(groups.size());
+  std::vector<Args> reps(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    spme::BatchArgs& bt = bts[g];
+    bt.n = (int)groups[g].size();
+    Args rep = plans[groups[g][0]]->bound;  // sizes the grids: largest system of the group
+    rep.reduce_ev = 0;
+    for (int k = 0; k < bt.n; ++k) {
+      const pme_plan* p = plans[groups[g][k]];
+      bt.sys[k] = reinterpret_cast<const Args*>(p->ws + p->lay.args);
+      rep.N = std::max(rep.N, p->bound.N);
+      rep.n_chunks = std::max(rep.n_chunks, p->bound.n_chunks);
+      rep.reduce_ev |= p->bound.reduce_ev;
+    }
+    reps[g] = rep;
+  }
+  const spme::Timing none;
+  // stage by stage over the groups, all on one stream
+  for (int stage = 0; stage < spme::kNumKernels; ++stage) {
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const Args& a = reps[g];
+      const spme::BatchArgs* bt = &bts[g];
+      hipError_t e = hipSuccess;
+      switch (stage) {
+        case 0: e = spme::launch_bin(a, s, none, bt); break;
+        case 1: e = spme::launch_spread_x(a, s, none, bt); break;
+        case 2: e = spme::launch_fft_y(a, s, none, bt); break;
+        case 3: e = spme::launch_pencil(a, s, none, bt); break;
+        case 4: e = spme::launch_inv(a, s, none, bt); break;
+        default: e = spme::launch_gather(a, s, none, bt); break;
+      }
+      if (e != hipSuccess) return PME_EDEVICE;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    pme_plan* p = plans[i];
+    p->cur = p->bound;
+    p->cur.reduce_ev = 0;
+    p->grid_kept = p->bound.keep_grid;
+    p->state = kSolved;
+  }
+  return PME_OK;
 }
 
 size_t pme_debug_grid_bytes(pme_plan* p, int which) {

@@ -58,6 +58,7 @@ struct Layout {
   size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
   size_t partial;  // double[pencil_blocks][8]: energy/virial partial sums
   size_t dbg;      // int64 or double [K][K][K]: charge-grid copy (debug)
+  size_t args;     // Args: device copy of the bound step arguments (batched runs)
   size_t total;
   int n_chunks_max;
   int pencil_blocks;
@@ -80,6 +81,14 @@ struct Args {
   Layout lay;
 };
 
+// Batched launches: device copies of the Args of up to kMaxBatch systems of
+// one (precision, K, order) group; workgroup (x, y) works on system y.
+constexpr int kMaxBatch = 128;
+struct BatchArgs {
+  int n;
+  const Args* sys[kMaxBatch];
+};
+
 // Optional events attached to one kernel dispatch (both null: untimed).
 struct Timing {
   hipEvent_t start = nullptr, stop = nullptr;
@@ -91,13 +100,19 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay);
 // Raise dynamic-LDS limits of the kernels a plan will launch.
 hipError_t prepare_kernels(int K, int order, int precision);
 
-hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t = Timing());
-hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t = Timing());
-hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t = Timing());
-hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
+hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
+hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
+hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
 hipError_t launch_reduce_ev(const Args& a, hipStream_t s);
-hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t = Timing());
-hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t = Timing());
+hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
+hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                      const BatchArgs* bt = nullptr);
 hipError_t launch_clear_flags(const Args& a, hipStream_t s);
 
 }  // namespace spme

@@ -72,6 +72,15 @@ struct PDouble {
 template <class P>
 __host__ __device__ constexpr int tile_pitch(int K) { return P::fixed ? K + 1 : K + 4; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap workgroup b of n (n a multiple of 8) so that XCD b % 8 owns the
+// contiguous block of logical indices [(b % 8) n/8, (b % 8 + 1) n/8): z-planes
+// that share atoms then share one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local(int b, int n) {
+  return (b % kXcds) * (n / kXcds) + b / kXcds;
+}
+
 template <int P, typename T>
 __device__ __forceinline__ T pick(const T* a, int i) {
   // a[i] for a register array and a lane-varying i, written as a masked sum
@@ -142,8 +151,10 @@ __device__ double block_sums(const double* v, double* red) {
 // ---------------------------------------------------------------------------
 // k_bin: one chunk of kChunk atoms per workgroup.
 // ---------------------------------------------------------------------------
-template <class P>
-__global__ __launch_bounds__(kBinThreads) void k_bin(Args a) {
+template <class P, bool BATCH>
+__global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  if (BATCH && (int)blockIdx.x >= a.n_chunks) return;
   using Rec = typename P::rec;
   using T = typename P::real;
   __shared__ int hist[kMaxBins];
@@ -218,8 +229,9 @@ __host__ __device__ constexpr size_t spread_lds_bytes() {
          kItemMap * sizeof(unsigned short);
 }
 
-template <class P, int K, int ORDER>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
+template <class P, int K, int ORDER, bool BATCH>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   using Acc = typename P::acc;
   using Rec = typename P::rec;
@@ -235,7 +247,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
   unsigned short* imap = reinterpret_cast<unsigned short*>(wsum + 32);
 
   TRACE(1, 0);
-  const int z = blockIdx.x / NQ, qs = blockIdx.x - z * NQ, y0 = qs * R;
+  static_assert((K * NQ) % kXcds == 0, "spreading tiles do not split over the XCDs");
+  const int tile_id = xcd_local(blockIdx.x, K * NQ);
+  const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
   const int tid = threadIdx.x;
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   for (int i = tid; i < K; i += kSpreadThreads) tw[i] = twg[i];
@@ -300,6 +314,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
       }
     }
     if (tid == 0) segpre[ns] = total;
+    TRACE(1, 4);
     for (int w0 = 0; w0 < total; w0 += kItemMap) {
       const int wn = min(kItemMap, total - w0);
       // map the items of this window to their segments
@@ -309,6 +324,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a) {
         for (int t = lo; t < hi; ++t) imap[t - w0] = (unsigned short)(tid * SPT + k);
       }
       __syncthreads();
+      TRACE(1, 5);
       for (int it = 0; it < wn; it += kItems * kSpreadThreads) {
         int idx[kItems], jz[kItems];
 #pragma unroll
@@ -440,16 +456,17 @@ __host__ __device__ constexpr size_t inv_lds_bytes() {
              : block_sum_doubles(7, kPlaneThreads) * sizeof(double);
 }
 
-template <class P, int K>
-__global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a) {
+template <class P, int K, bool BATCH>
+__global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int KH = K / 2 + 1, PC = KH + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K * PC;
   TRACE(2, 0);
-  const int z = blockIdx.x, tid = threadIdx.x;
-  if (z == K) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x == K) {
     // the extra workgroup (fixed point only): sum |q| 2^F must stay below
     // 2^51 so that every contribution and grid value is exact in FP64 and the
     // rounding of to_fixed holds
@@ -461,6 +478,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a) {
       atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
     return;
   }
+  static_assert(K % kXcds == 0, "planes do not split over the XCDs");
+  const int z = xcd_local(blockIdx.x, K);
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
   for (int i = tid; i < K * KH; i += kPlaneThreads) {
@@ -495,8 +514,9 @@ __host__ __device__ constexpr size_t pencil_lds_bytes() {
          block_sum_doubles(7, kPencilThreads) * sizeof(double);
 }
 
-template <class P, int K>
-__global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a) {
+template <class P, int K, bool BATCH>
+__global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int KH = K / 2 + 1;
   constexpr int XS = pencil_xsplit(K);
@@ -624,8 +644,9 @@ __global__ __launch_bounds__(kPlaneThreads) void k_reduce_ev(Args a) {
 // ---------------------------------------------------------------------------
 // k_inv_xy: inverse y FFT and complex-to-real x FFT of one z-plane.
 // ---------------------------------------------------------------------------
-template <class P, int K, int ORDER>
-__global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
+template <class P, int K, int ORDER, bool BATCH>
+__global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int M = K / 2, KH = K / 2 + 1, PC = KH + 1;
   constexpr int PP = phi_pitch_of(K, ORDER);
@@ -633,12 +654,13 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K * PC;
   TRACE(4, 0);
-  const int z = blockIdx.x, tid = threadIdx.x;
-  if (z == K) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x == K) {
     // the extra workgroup: energy and virial
-    reduce_ev(a, reinterpret_cast<double*>(smem));
+    if (a.reduce_ev) reduce_ev(a, reinterpret_cast<double*>(smem));
     return;
   }
+  const int z = xcd_local(blockIdx.x, K);
   const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
   for (int i = tid; i < K * KH; i += kPlaneThreads) {
     const int y = i / KH, x = i - y * KH;
@@ -681,8 +703,9 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a) {
 // ---------------------------------------------------------------------------
 // k_gather: force interpolation, one atom per thread in sorted order.
 // ---------------------------------------------------------------------------
-template <class P, int K, int ORDER>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Args a) {
+template <class P, int K, int ORDER, bool BATCH>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   using Rec = typename P::rec;
   constexpr int PP = phi_pitch_of(K, ORDER);
@@ -747,14 +770,18 @@ template <int V>
 using ic = std::integral_constant<int, V>;
 
 // Launch with optional timing events attached to the dispatch itself (the
-// kernel's own start and end), or plainly.
+// kernel's own start and end), or plainly.  Batched launches add a second
+// grid dimension over the systems of the batch.
 template <typename Kern>
 hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, const Timing& t,
-                  const Args& a) {
+                  const Args& a, const BatchArgs* bt) {
+  static const BatchArgs kNoBatch{};
+  const BatchArgs& b = bt != nullptr ? *bt : kNoBatch;
+  if (bt != nullptr) grid.y = bt->n;
   if (t.start != nullptr)
-    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t.start, t.stop, 0u, a);
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t.start, t.stop, 0u, a, b);
   else
-    kernel<<<grid, block, lds, s>>>(a);
+    kernel<<<grid, block, lds, s>>>(a, b);
   return hipGetLastError();
 }
 
@@ -822,10 +849,25 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   L.pencil_blocks = K * L.xsplit;
   L.partial = o;   o = align256(o + (size_t)L.pencil_blocks * 8 * sizeof(double));
   L.dbg = o;       o = align256(o + (size_t)K * K * K * 8);
+  L.args = o;      o = align256(o + sizeof(Args));
   L.total = o;
   L.n_chunks_max = nch;
   *lay = L;
   return true;
+}
+
+template <class P, int KK, int O, bool B>
+hipError_t raise_lds_limits() {
+  const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O, B>, attr,
+                                     (int)spread_lds_bytes<P, KK>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_y<P, KK, B>, attr, (int)fft_y_lds_bytes<P, KK>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O, B>, attr, (int)inv_lds_bytes<P, KK>());
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_pencil<P, KK, B>, attr, (int)pencil_lds_bytes<P, KK>());
+  return e;
 }
 
 hipError_t prepare_kernels(int K, int order, int precision) {
@@ -835,64 +877,72 @@ hipError_t prepare_kernels(int K, int order, int precision) {
       constexpr int KK = decltype(kc)::value;
       return with_order(order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
-        hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O>, attr,
-                                           (int)spread_lds_bytes<P, KK>());
-        if (e == hipSuccess)
-          e = hipFuncSetAttribute((const void*)k_fft_y<P, KK>, attr, (int)fft_y_lds_bytes<P, KK>());
-        if (e == hipSuccess)
-          e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O>, attr,
-                                  (int)inv_lds_bytes<P, KK>());
-        if (e == hipSuccess)
-          e = hipFuncSetAttribute((const void*)k_pencil<P, KK>, attr,
-                                  (int)pencil_lds_bytes<P, KK>());
-        return e;
+        hipError_t e = raise_lds_limits<P, KK, O, false>();
+        return e == hipSuccess ? raise_lds_limits<P, KK, O, true>() : e;
       });
     });
   });
 }
 
-hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t) {
+template <class F>
+hipError_t with_batch(const BatchArgs* bt, F&& f) {
+  if (bt != nullptr) return f(std::true_type{});
+  return f(std::false_type{});
+}
+
+hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   if (a.n_chunks == 0) return skip(s, t);
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    return launch(k_bin<P>, dim3(a.n_chunks), dim3(kBinThreads), 0, s, t, a);
+    return with_batch(bt, [&](auto bc) {
+      constexpr bool B = decltype(bc)::value;
+      return launch(k_bin<P, B>, dim3(a.n_chunks), dim3(kBinThreads), 0, s, t, a, bt);
+    });
   });
 }
 
-hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t) {
+hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        return launch(k_spread_x<P, KK, O>, dim3(KK * nq_of(KK)), dim3(kSpreadThreads),
-                      spread_lds_bytes<P, KK>(), s, t, a);
+        return with_batch(bt, [&](auto bc) {
+          constexpr bool B = decltype(bc)::value;
+          return launch(k_spread_x<P, KK, O, B>, dim3(KK * nq_of(KK)), dim3(kSpreadThreads),
+                        spread_lds_bytes<P, KK>(), s, t, a, bt);
+        });
       });
     });
   });
 }
 
-hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t) {
+hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
-      const int blocks = KK + (P::fixed ? 1 : 0);
-      return launch(k_fft_y<P, KK>, dim3(blocks), dim3(kPlaneThreads), fft_y_lds_bytes<P, KK>(), s,
-                    t, a);
+      return with_batch(bt, [&](auto bc) {
+        constexpr bool B = decltype(bc)::value;
+        const int blocks = KK + (P::fixed ? 1 : 0);
+        return launch(k_fft_y<P, KK, B>, dim3(blocks), dim3(kPlaneThreads),
+                      fft_y_lds_bytes<P, KK>(), s, t, a, bt);
+      });
     });
   });
 }
 
-hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t) {
+hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
-      return launch(k_pencil<P, KK>, dim3(KK * pencil_xsplit(KK)), dim3(kPencilThreads),
-                    pencil_lds_bytes<P, KK>(), s, t, a);
+      return with_batch(bt, [&](auto bc) {
+        constexpr bool B = decltype(bc)::value;
+        return launch(k_pencil<P, KK, B>, dim3(KK * pencil_xsplit(KK)), dim3(kPencilThreads),
+                      pencil_lds_bytes<P, KK>(), s, t, a, bt);
+      });
     });
   });
 }
@@ -902,22 +952,25 @@ hipError_t launch_reduce_ev(const Args& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t) {
+hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        const int blocks = KK + (a.reduce_ev ? 1 : 0);
-        return launch(k_inv_xy<P, KK, O>, dim3(blocks), dim3(kPlaneThreads), inv_lds_bytes<P, KK>(),
-                      s, t, a);
+        return with_batch(bt, [&](auto bc) {
+          constexpr bool B = decltype(bc)::value;
+          const int blocks = KK + ((a.reduce_ev || B) ? 1 : 0);
+          return launch(k_inv_xy<P, KK, O, B>, dim3(blocks), dim3(kPlaneThreads),
+                        inv_lds_bytes<P, KK>(), s, t, a, bt);
+        });
       });
     });
   });
 }
 
-hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t) {
+hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   if (a.N == 0) return skip(s, t);
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
@@ -925,8 +978,11 @@ hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t) {
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        const int blocks = (a.N + kGatherThreads - 1) / kGatherThreads;
-        return launch(k_gather<P, KK, O>, dim3(blocks), dim3(kGatherThreads), 0, s, t, a);
+        return with_batch(bt, [&](auto bc) {
+          constexpr bool B = decltype(bc)::value;
+          const int blocks = (a.N + kGatherThreads - 1) / kGatherThreads;
+          return launch(k_gather<P, KK, O, B>, dim3(blocks), dim3(kGatherThreads), 0, s, t, a, bt);
+        });
       });
     });
   });

@@ -72,6 +72,13 @@ class Plan:
         self._keep = ()
         self._n = 0
 
+    @staticmethod
+    def workspace_bytes_for(K, order, max_atoms, precision="fp32_fixed"):
+        """Device workspace a plan with these parameters needs (0 if unsupported)."""
+        lib = _lib.load()
+        return int(lib.pme_workspace_bytes(int(K), int(K), int(K), int(order), int(max_atoms),
+                                           PRECISIONS[precision]))
+
     # -- lifetime -----------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -131,6 +138,24 @@ class Plan:
               "pme_step")
         return forces, ev
 
+    def bind(self, pos, q, box, forces=None, ev=None, accumulate=False):
+        """Bind the buffers of this plan's batched steps (see Batch); returns (forces, ev)."""
+        n = int(q.shape[0])
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=self.device)
+        _dev_f64(forces, (n, 3), "forces")
+        _dev_f64(ev, (7,), "ev")
+        check(self._lib.pme_bind(self._h, pos.data_ptr(), q.data_ptr(), n, _box9(box),
+                                 forces.data_ptr(), int(bool(accumulate)), ev.data_ptr()),
+              "pme_bind")
+        self._bound = (pos, q, forces, ev)
+        self._n = n
+        return forces, ev
+
     # -- inspection -----------------------------------------------------------
     def set_debug(self, keep_charge_grid=True):
         check(self._lib.pme_set_debug(self._h, int(bool(keep_charge_grid))), "pme_set_debug")
@@ -170,3 +195,22 @@ class Plan:
         check(self._lib.pme_kernel_times(self._h, ms, len(KERNEL_NAMES), ctypes.byref(steps)),
               "pme_kernel_times")
         return dict(zip(KERNEL_NAMES, list(ms))), int(steps.value)
+
+
+class Batch:
+    """One step of many bound plans per run: plans that share precision, grid
+    and spline order share every kernel launch (pme_batch_run)."""
+
+    def __init__(self, plans, stream=None):
+        self.plans = list(plans)
+        for pl in self.plans:
+            if getattr(pl, "_bound", None) is None:
+                raise RuntimeError("every plan of a batch must be bound first (Plan.bind)")
+        self._lib = _lib.load()
+        self._handles = (ctypes.c_void_p * len(self.plans))(*[pl._h.value for pl in self.plans])
+        self.stream = stream
+
+    def run(self, stream=None):
+        st = stream or self.stream or torch.cuda.current_stream()
+        check(self._lib.pme_batch_run(self._handles, len(self.plans), ctypes.c_void_p(st.cuda_stream)),
+              "pme_batch_run")
