@@ -4,9 +4,9 @@
 Workload: 21,845 TIP3P-like waters (65,535 atoms) in an 86.8 A cubic box, 64^3
 grid, B-spline order 4, beta = 0.34 1/A; a random walk of N(0, 0.01 A) per
 coordinate per frame gives the frame sequence, staged in HBM before timing.
-A step is one full pme_step (bin, spread + x/y FFT, z FFT + influence
-function + energy/virial, inverse x/y FFT, force interpolation) on the next
-frame, stream-ordered after the previous one.
+A step is one full pme_step (bin, spread + x FFT, y/z FFTs + influence
+function + energy/virial + inverse z/y FFTs, inverse x FFT + force
+interpolation) on the next frame, stream-ordered after the previous one.
 
 Prints one JSON line (rank 0).  Extra fields: the plain FP64 path's time on
 the same frames, per-step p50/p99 latency, per-kernel times, the roofline of
@@ -26,28 +26,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(N, K, kernel, fp64=False):
+def algorithmic_bytes(N, K, kernel, fp64=False, fused=True):
     """Algorithmic HBM bytes one launch of `kernel` moves:
     atoms 32 B read by spreading, 32 B read + 24 B written by interpolation;
     the charge grid (8 B/point) written and read; the half spectrum
-    (8 or 16 B/point) across the two corner turns; the potential written and
-    read.  Each term is charged to the kernel that performs that step."""
+    (8 or 16 B/point) across the two corner turns (written by the forward
+    slab pass, read and written by the pencil pass, read by the inverse slab
+    pass); the potential written and read.  Each term is charged to the
+    kernel that performs that step; with the fused interpolation the
+    inverse-x terms go to "gather"."""
     kh = K // 2 + 1
     cs = 16 if fp64 else 8       # complex bytes
     rs = 8 if fp64 else 4        # potential bytes
+    inv_x = cs * K * K * kh + rs * K ** 3
     return {
         "bin": 32 * N,
-        "spread_x": 8 * K ** 3,
-        "fft_y": 8 * K ** 3 + cs * K * K * kh,
-        "convolve_z": 2 * cs * K * K * kh,
-        "inverse_xy": cs * K * K * kh + rs * K ** 3,
-        "gather": 56 * N + rs * K ** 3,
+        "spread_x": 16 * K ** 3 + cs * K * K * kh,
+        "convolve_yz": 2 * cs * K * K * kh,
+        "inverse_x": 0 if fused else inv_x,
+        "gather": 56 * N + rs * K ** 3 + (inv_x if fused else 0),
     }[kernel]
 
 
 def step_bytes(N, K, fp64=False):
     return sum(algorithmic_bytes(N, K, k, fp64) for k in
-               ("bin", "spread_x", "fft_y", "convolve_z", "inverse_xy", "gather"))
+               ("bin", "spread_x", "convolve_yz", "inverse_x", "gather"))
 
 
 def source_digest():
@@ -340,7 +343,7 @@ def main():
     print("# per-kernel us: " + ", ".join(f"{k}={v:.2f}" for k, v in kavg_us.items()),
           file=sys.stderr, flush=True)
     dom = max(kavg_us, key=kavg_us.get)
-    dom_bytes = algorithmic_bytes(N, K, dom)
+    dom_bytes = algorithmic_bytes(N, K, dom, fused=plan.interp_fused)
     achieved = dom_bytes / (kavg_us[dom] * 1e-6) / 1e9
     traffic = measured_traffic(dom)
 

@@ -106,10 +106,11 @@ int pme_destroy(pme_plan *plan);
 /* Change the stream subsequent calls enqueue on. */
 int pme_set_stream(pme_plan *plan, void *stream);
 
-/* Charge spreading and the first FFT passes (§III.A.1, first half of
- * §III.A.2): bins the atoms, spreads them into the fixed-point (or FP64) grid
- * and transforms it along x (real-to-complex) and y.  With the FP32/fixed
- * path the plan raises PME_FLAG_OVERFLOW when sum |q| 2^F >= 2^51.
+/* Charge spreading and the first FFT pass (§III.A.1, start of §III.A.2):
+ * bins the atoms, spreads them into the fixed-point (or FP64) grid and
+ * transforms it along x (real-to-complex).  With the FP32/fixed path the
+ * following pme_solve raises PME_FLAG_OVERFLOW when the spread charges had
+ * sum |q| 2^F >= 2^51.
  *   pos  device [N][3] doubles (Angstrom, any image; wrapped internally)
  *   q    device [N] doubles
  *   N    0 <= N <= max_atoms
@@ -118,14 +119,13 @@ int pme_set_stream(pme_plan *plan, void *stream);
  * enqueued (it reads q again). */
 int pme_spread(pme_plan *plan, const double *pos, const double *q, int N, const double box[9]);
 
-/* Green's-function convolution (§III.A.2: the z transform, multiply,
- * inverse z transform), energy and virial.
+/* Green's-function convolution (§III.A.2: the y and z transforms, the
+ * multiplication, the inverse z and y transforms), energy and virial.
  *   ev   device [7] doubles: E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz (overwritten),
  *        or NULL to skip writing them. */
 int pme_solve(pme_plan *plan, double *ev);
 
-/* Inverse y and x transforms and force interpolation (§III.A.2 second
- * corner turn, §III.A.3).
+/* Inverse x transform and force interpolation (end of §III.A.2, §III.A.3).
  *   forces      device [N][3] doubles in the caller's atom order
  *   accumulate  0 overwrites, 1 adds to the existing values */
 int pme_gather(pme_plan *plan, double *forces, int accumulate);
@@ -158,9 +158,10 @@ int pme_set_debug(pme_plan *plan, int keep_charge_grid);
  *   which 0: charge grid [K3][K2][K1], int64 (FP32_FIXED, raw fixed point with
  *            frac_bits fraction bits) or double (FP64); needs pme_set_debug(1)
  *            before the spread
- *   which 1: the half spectrum [K3][K2][K1/2+1] complex (float2 / double2):
- *            after pme_spread the forward transform of the charge grid along
- *            x and y; after pme_solve G F transformed back along z
+ *   which 1: the half spectrum, stored as columns [K1/2+1][K3][K2] complex
+ *            (float2 / double2; index m1 slowest, y fastest): after
+ *            pme_spread the forward transform of the charge grid along x;
+ *            after pme_solve G F transformed back along z and y
  *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED) or double */
 int pme_debug_grid(pme_plan *plan, int which, void *dst);
 
@@ -177,11 +178,18 @@ int pme_check(pme_plan *plan, unsigned *flags);
  * the dispatch itself (hipExtLaunchKernel), so the elapsed time is the
  * kernel's own execution; pme_kernel_times
  * synchronises, adds the elapsed times of all completed launches into
- * ms[0..n-1] (kernel order: bin, spread + x FFT, y FFT, z-convolution,
- * inverse y/x FFT, gather) and returns the number of steps accumulated in
- * *steps. */
+ * ms[0..n-1] (kernel order: 0 bin, 1 spread + x FFT, 2 y/z FFTs with the
+ * influence function and the inverse z/y FFTs, 3 inverse x FFT, 4 force
+ * interpolation) and returns the number of steps accumulated in *steps.
+ * Where pme_interp_fused(plan) is 1, slot 4 times the inverse x FFT and the
+ * interpolation together and slot 3 stays 0. */
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
+
+/* 1 when the plan runs the inverse x FFT and force interpolation as one
+ * launch (the potential then never leaves LDS), 0 when they are two launches
+ * through the workspace (FP64 with K = 128 and p = 6), -1 for a NULL plan. */
+int pme_interp_fused(const pme_plan *plan);
 
 /* Human-readable text for a pme_status. */
 const char *pme_strerror(int code);

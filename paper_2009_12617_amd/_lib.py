@@ -83,6 +83,8 @@ def load():
     lib.pme_kernel_timing.argtypes = [vp, i]
     lib.pme_kernel_times.restype = i
     lib.pme_kernel_times.argtypes = [vp, dp, i, ctypes.POINTER(ctypes.c_int)]
+    lib.pme_interp_fused.restype = i
+    lib.pme_interp_fused.argtypes = [vp]
     _lib = lib
     return lib
 

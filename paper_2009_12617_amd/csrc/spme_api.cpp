@@ -40,6 +40,7 @@ struct pme_plan {
   int state = kCreated;
   int keep_grid = 0;
   int grid_kept = 0;
+  int fused_interp = 1;  // inverse x and interpolation in one launch
   // host copies of the uploaded tables
   std::vector<double> bsq;
   std::vector<double> tw64;
@@ -110,7 +111,7 @@ int timed(pme_plan* p, int kernel, F&& launch) {
 
 extern "C" {
 
-int pme_version(void) { return 100; }
+int pme_version(void) { return 200; }
 
 const char* pme_strerror(int code) {
   switch (code) {
@@ -185,6 +186,7 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   p->tw32.resize(2 * (size_t)K);
   for (int i = 0; i < 2 * K; ++i) p->tw32[i] = (float)p->tw64[i];
 
+  p->fused_interp = spme::interp_is_fused(K, order, precision) ? 1 : 0;
   hipError_t e = spme::prepare_kernels(K, order, precision);
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ctrl, 0, 64 * sizeof(unsigned), p->stream);
   if (e == hipSuccess)
@@ -274,8 +276,6 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
   rc = timed(p, 0, [&](const spme::Timing& t) { return spme::launch_bin(a, p->stream, t); });
   if (rc == PME_OK)
     rc = timed(p, 1, [&](const spme::Timing& t) { return spme::launch_spread_x(a, p->stream, t); });
-  if (rc == PME_OK)
-    rc = timed(p, 2, [&](const spme::Timing& t) { return spme::launch_fft_y(a, p->stream, t); });
   if (rc != PME_OK) return rc;
   p->grid_kept = p->keep_grid;
   p->state = kSpread;
@@ -284,15 +284,15 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
 
 namespace {
 
-// The z-convolution writes one energy/virial row per workgroup; the rows are
-// summed either by the next kernel of the step (fused = true) or by a
+// The convolution writes one energy/virial row per column; the rows are
+// summed either by the next launch of the step (fused = true) or by a
 // one-workgroup kernel right away.
 int solve_impl(pme_plan* p, double* ev, bool fused) {
   if (p->state < kSpread) return PME_ESTATE;
   Args& a = p->cur;
   a.ev = ev;
   a.reduce_ev = 0;
-  int rc = timed(p, 3, [&](const spme::Timing& t) { return spme::launch_pencil(a, p->stream, t); });
+  int rc = timed(p, 2, [&](const spme::Timing& t) { return spme::launch_conv(a, p->stream, t); });
   if (rc != PME_OK) return rc;
   if (ev != nullptr) {
     if (fused)
@@ -311,10 +311,16 @@ int gather_impl(pme_plan* p, double* forces, int accumulate) {
   if (a.N > 0 && forces == nullptr) return PME_EINVAL;
   a.forces = forces;
   a.accumulate = accumulate ? 1 : 0;
-  int rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_inv(a, p->stream, t); });
-  a.reduce_ev = 0;  // the energy/virial rows are summed once
-  if (rc == PME_OK)
-    rc = timed(p, 5, [&](const spme::Timing& t) { return spme::launch_gather(a, p->stream, t); });
+  int rc;
+  if (p->fused_interp) {
+    rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_interp(a, p->stream, t); });
+  } else {
+    rc = timed(p, 3, [&](const spme::Timing& t) { return spme::launch_inv_x(a, p->stream, t); });
+    a.reduce_ev = 0;  // the energy/virial rows are summed once
+    if (rc == PME_OK)
+      rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_gather(a, p->stream, t); });
+  }
+  a.reduce_ev = 0;
   if (rc == PME_OK && p->timing) p->timed_steps++;
   return rc;
 }
@@ -411,13 +417,15 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
       const Args& a = reps[g];
       const spme::BatchArgs* bt = &bts[g];
       hipError_t e = hipSuccess;
+      const bool fused = plans[groups[g][0]]->fused_interp;
       switch (stage) {
         case 0: e = spme::launch_bin(a, s, none, bt); break;
         case 1: e = spme::launch_spread_x(a, s, none, bt); break;
-        case 2: e = spme::launch_fft_y(a, s, none, bt); break;
-        case 3: e = spme::launch_pencil(a, s, none, bt); break;
-        case 4: e = spme::launch_inv(a, s, none, bt); break;
-        default: e = spme::launch_gather(a, s, none, bt); break;
+        case 2: e = spme::launch_conv(a, s, none, bt); break;
+        case 3: e = fused ? hipSuccess : spme::launch_inv_x(a, s, none, bt); break;
+        default:
+          e = fused ? spme::launch_interp(a, s, none, bt) : spme::launch_gather(a, s, none, bt);
+          break;
       }
       if (e != hipSuccess) return PME_EDEVICE;
     }
@@ -460,12 +468,18 @@ int pme_debug_grid(pme_plan* p, int which, void* dst) {
       if (p->state < kSpread) return PME_ESTATE;
       e = hipMemcpyAsync(dst, p->ws + p->lay.spec, bytes, hipMemcpyDeviceToDevice, p->stream);
       break;
-    default:
+    default: {
       if (p->state < kSolved) return PME_ESTATE;
+      // the potential rows, from the spectrum the step left in the workspace
+      Args a = p->cur;
+      a.reduce_ev = 0;
+      e = spme::launch_inv_x(a, p->stream);
+      if (e != hipSuccess) break;
       e = hipMemcpy2DAsync(dst, K * real, p->ws + p->lay.phi + (p->order - 1) * real,
                            (size_t)p->lay.phi_pitch * real, K * real, K * K,
                            hipMemcpyDeviceToDevice, p->stream);
       break;
+    }
   }
   return device_error(e);
 }
@@ -484,6 +498,8 @@ int pme_check(pme_plan* p, unsigned* flags) {
   if (f & PME_FLAG_OVERFLOW) return PME_EOVERFLOW;
   return PME_OK;
 }
+
+int pme_interp_fused(const pme_plan* p) { return p == nullptr ? -1 : p->fused_interp; }
 
 int pme_kernel_timing(pme_plan* p, int enable) {
   if (p == nullptr) return PME_EINVAL;

@@ -14,27 +14,29 @@ constexpr int kItemMap = 4096;       // items per window of the spreading item m
 constexpr int kSegPerThread = 4;     // spreading segments described per thread per batch
 constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
 constexpr int kPlaneThreads = 512;   // one z-plane per workgroup
-constexpr int kPencilThreads = 512;  // z-pencils of one (y, x-range) per workgroup
+constexpr int kInterpThreads = 512;  // one (z-plane, y slice) bin per workgroup
+constexpr int kInterpItems = 2048;   // atoms per window of the interpolation item list
 constexpr int kGatherThreads = 256;  // one atom per thread
-constexpr int kNumKernels = 6;       // bin, spread+x, y, z-convolution, inverse xy, gather
+constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kNumKernels = 5;       // bin, spread+x, yz convolution, inverse x, interpolation
 
 // y slices per z-plane in the spreading pass (rows per slice >= 8 > p - 1,
 // so an atom's support reaches at most one slice below its own).
 __host__ __device__ constexpr int nq_of(int K) { return K >= 32 ? 4 : K / 8; }
-__host__ __device__ constexpr int pencil_xsplit(int K) { return K >= 32 ? 2 : 1; }
 __host__ __device__ constexpr int phi_pitch_of(int K, int order) {
   return (K + order - 1 + 3) / 4 * 4;
 }
 
 // Sorted atom record of the FP32/fixed path (32 bytes): packed base grid
 // index (x | y << 10 | z << 20), single-precision fractional offsets and
-// charge, index of the atom in the caller's order.
+// charge (spreading), index of the atom in the caller's order, and the
+// double-precision charge (interpolation).
 struct RecF {
   int g;
   float w[3];
   float q;
   int idx;
-  int pad[2];
+  double qd;
 };
 // FP64 path (48 bytes).
 struct RecD {
@@ -42,7 +44,7 @@ struct RecD {
   int idx;
   double w[3];
   double q;
-  double pad;
+  double qd;  // same as q
 };
 
 // Byte offsets of the workspace regions (each 256-byte aligned).
@@ -54,15 +56,14 @@ struct Layout {
                    // atoms of chunk c in bin (z, y slice, head/body)
   size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
   size_t rec;      // records [n_chunks * kChunk] (RecF or RecD)
-  size_t spec;     // complex[K][K][K/2+1] half spectrum
+  size_t spec;     // complex[K/2+1][K][K] half spectrum, columns [x'][z][y]
   size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
-  size_t partial;  // double[pencil_blocks][8]: energy/virial partial sums
+  size_t partial;  // double[conv_blocks][8]: energy/virial partial sums
   size_t dbg;      // int64 or double [K][K][K]: charge-grid copy (debug)
   size_t args;     // Args: device copy of the bound step arguments (batched runs)
   size_t total;
   int n_chunks_max;
-  int pencil_blocks;
-  int xsplit;
+  int conv_blocks;  // K/2+1 columns, one partial row each
   int phi_pitch;
 };
 
@@ -70,7 +71,7 @@ struct Args {
   int K, order, precision, frac_bits;
   int N, n_chunks;
   int accumulate, keep_grid;
-  int reduce_ev;  // k_inv_xy's first workgroup adds the energy/virial rows
+  int reduce_ev;  // the last launch's extra workgroup adds the energy/virial rows
   double L[3], invL[3];
   double beta, coulomb, volume;
   const double* pos;
@@ -104,15 +105,18 @@ hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t = Timing(),
                       const BatchArgs* bt = nullptr);
 hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t = Timing(),
                       const BatchArgs* bt = nullptr);
-hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t = Timing(),
-                      const BatchArgs* bt = nullptr);
-hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t = Timing(),
-                      const BatchArgs* bt = nullptr);
+hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                       const BatchArgs* bt = nullptr);
 hipError_t launch_reduce_ev(const Args& a, hipStream_t s);
-hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t = Timing(),
-                      const BatchArgs* bt = nullptr);
+hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                        const BatchArgs* bt = nullptr);
+hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t = Timing(),
+                         const BatchArgs* bt = nullptr);
 hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t = Timing(),
-                      const BatchArgs* bt = nullptr);
+                         const BatchArgs* bt = nullptr);
+// Whether the inverse x transform and interpolation run as one launch
+// (k_interp) for these parameters, or as k_inv_x + k_gather.
+bool interp_is_fused(int K, int order, int precision);
 hipError_t launch_clear_flags(const Args& a, hipStream_t s);
 
 }  // namespace spme

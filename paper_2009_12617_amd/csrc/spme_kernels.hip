@@ -1,31 +1,29 @@
 // HIP kernels of the SPME reciprocal-space step for gfx950 (CDNA4).
 //
-// One step is six launches on one stream:
+// One step is four launches on one stream:
 //   k_bin       fractional coordinates, base grid index and offsets of each
 //               atom; a per-chunk counting sort of the atoms by (base z,
-//               y slice) -- the GPU counterpart of the
-//               paper's atom reordering for hazard suppression (§III.A.1, §V.C)
+//               y slice, head/body) -- the GPU counterpart of the paper's
+//               atom reordering for hazard suppression (§III.A.1, §V.C)
 //   k_spread_x  one y slice of one z-plane per workgroup: every atom whose
 //               support covers the slice adds its contributions into an LDS
 //               tile in 64-bit fixed point (integer adds commute, so the grid
 //               is bit-identical whatever the order); the finished rows are
-//               converted to FP32 and transformed along x (real-to-complex)
-//   k_fft_y     one z-plane per workgroup: y transforms (§III.A.2: "each
-//               slab runs independently to compute X and Y transforms")
-//   k_pencil    one y row (or half of it) per workgroup: z transforms,
-//               multiplication by the influence function with FP64 energy and
-//               virial partials, inverse z transforms (§III.A.2: "Z direction
-//               transforms, multiply by Green's function data, compute Z^-1
-//               transforms")
-//   k_inv_xy    one z-plane per workgroup: inverse y and complex-to-real x
-//               transforms; potential rows written with a (p-1)-point wrap
-//               halo so interpolation reads contiguous runs; one extra
-//               workgroup adds the energy/virial partial rows
-//   k_gather    one atom per thread: B-spline weights and derivatives, p^3
-//               potential reads, forces scattered back to the caller's atom
-//               order (§III.A.3)
-// The paper's two all-to-all corner turns become the HBM round trips between
-// plane and pencil passes.
+//               converted to FP32, transformed along x (real-to-complex) and
+//               stored as columns [x'][z][y] of the half spectrum
+//   k_conv      one x' column per workgroup: y and z transforms, the
+//               influence function with FP64 energy and virial partials,
+//               inverse z and y transforms (§III.A.2)
+//   k_interp    one (z-plane, y-slice) bin per workgroup: complex-to-real x
+//               transforms of the p planes and p-1+R rows that the bin's
+//               atoms touch, then force interpolation from LDS, forces
+//               scattered back to the caller's atom order (§III.A.3); one
+//               extra workgroup adds the energy/virial partial rows
+// Where the interpolation tile does not fit in LDS (FP64, K = 128, p = 6) the
+// last launch is split into k_inv_x (potential rows into the workspace) and
+// k_gather (one atom per thread).  The paper's two all-to-all corner turns
+// (§III.A.2, §IV.C) become the column layout of the half spectrum: each
+// column holds every y and z of one x', so both turns happen inside k_conv.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
@@ -38,7 +36,7 @@ namespace spme {
 
 // Optional phase trace (build with -DSPME_TRACE): thread 0 of each workgroup
 // stamps the 100 MHz wall clock at phase boundaries into
-// trace[kernel][workgroup][phase]; kernels 0..5 in launch order, phase 0 at
+// trace[kernel][workgroup][phase]; kernels 0..4 as in the timing order, phase 0 at
 // entry and 15 at exit.
 #ifdef SPME_TRACE
 __device__ unsigned long long* g_trace;
@@ -66,11 +64,16 @@ struct PDouble {
   static constexpr bool fixed = false;
 };
 
-// Row pitch of an LDS grid tile in 8-byte units.  Fixed point: K int64
-// values per row (the half spectrum of K/2+1 float2 fits in place).  FP64:
-// room for K/2+1 double2.  The extra unit skews rows across LDS banks.
+// Row pitch of an LDS grid tile in 8-byte units.  Fixed point: at least K
+// int64 values per row (the half spectrum of K/2+1 float2 fits in place).
+// FP64: room for K/2+1 double2.  The padding skews rows across LDS banks.
 template <class P>
-__host__ __device__ constexpr int tile_pitch(int K) { return P::fixed ? K + 1 : K + 4; }
+__host__ __device__ constexpr int tile_pitch(int K) {
+  // chosen with a bank model of the x transform's Stockham stages over rows
+  // of this pitch (64-lane wavefront, 4-byte banks)
+  return P::fixed ? (K == 32 ? 34 : K == 64 ? 66 : K == 96 ? 98 : K == 128 ? 135 : K + 1)
+                  : 2 * (K == 128 ? 71 : K / 2 + 1);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Remap workgroup b of n (n a multiple of 8) so that XCD b % 8 owns the
@@ -117,35 +120,57 @@ __device__ int block_exclusive_scan(int v, int* wsum, int* total) {
   return (wave > 0 ? wsum[16 + wave - 1] : 0) + x - v;
 }
 
-// Sums of V doubles over the block in a fixed order: every thread stores its
-// values, 16 threads per value add consecutive runs of blockDim/16 entries,
-// then thread c < V adds the 16 run sums of value c in order and returns it
-// (other threads return 0).  red needs block_sum_doubles(V, blockDim)
-// doubles; the caller synchronises before reusing red.
-__host__ __device__ constexpr int block_sum_doubles(int V, int threads) { return V * (threads + 16); }
+// One DPP move of a double within the wavefront (each half moved with the
+// same control); lanes without a source, or outside row_mask, read 0.0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
+// Inclusive prefix sums of V doubles across the 16 lanes of each DPP row
+// (row_shr 1, 2, 4, 8).
 template <int V>
-__device__ double block_sums(const double* v, double* red) {
-  const int n = blockDim.x, tid = threadIdx.x;
+__device__ __forceinline__ void row_scan_add(double* v) {
 #pragma unroll
-  for (int c = 0; c < V; ++c) red[c * n + tid] = v[c];
-  __syncthreads();
-  double* part = red + V * n;
-  const int run = n / 16;
-  if (tid < V * 16) {
-    const int c = tid / 16, k = tid - c * 16;
-    const double* src = red + c * n + k * run;
-    double s = 0.0;
-    for (int i = 0; i < run; ++i) s += src[i];
-    part[tid] = s;
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x111, 0xf>(v[c]);
+#pragma unroll
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x112, 0xf>(v[c]);
+#pragma unroll
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x114, 0xf>(v[c]);
+#pragma unroll
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x118, 0xf>(v[c]);
+}
+
+// Sums of V doubles over the block in a fixed order: an inclusive DPP scan
+// over each wavefront (rows, then row_bcast 15 and 31), whose lane 63 holds
+// the wavefront's sums; then the wavefront sums in wavefront order by a row
+// scan in wavefront 0.  Thread 15 ends with the block sums in v.  Every
+// thread must call it (at most 16 wavefronts); wred needs 16 * 8 doubles; it
+// synchronises once and the caller synchronises before reusing wred.
+template <int V>
+__device__ __forceinline__ void block_sums(double* v, double* wred) {
+  row_scan_add<V>(v);
+#pragma unroll
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x142, 0xa>(v[c]);
+#pragma unroll
+  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x143, 0xc>(v[c]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) {
+#pragma unroll
+    for (int c = 0; c < V; ++c) wred[wave * 8 + c] = v[c];
   }
   __syncthreads();
-  double s = 0.0;
-  if (tid < V) {
+  if (wave == 0) {
+    const int nw = blockDim.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s += part[tid * 16 + k];
+    for (int c = 0; c < V; ++c) v[c] = lane < nw ? wred[lane * 8 + c] : 0.0;
+    row_scan_add<V>(v);
   }
-  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -159,7 +184,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   using T = typename P::real;
   __shared__ int hist[kMaxBins];
   __shared__ int wsum[32];
-  __shared__ double red[block_sum_doubles(1, kBinThreads)];
+  __shared__ double wred[16 * 8];
   TRACE(0, 0);
   const int K = a.K, nq = nq_of(a.K), rows = K / nq, nbins = 2 * K * nq;
   const int c = blockIdx.x, tid = threadIdx.x;
@@ -193,6 +218,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
     r.w[1] = (T)w[1];
     r.w[2] = (T)w[2];
     r.q = (T)qi;
+    r.qd = qi;
     r.idx = i;
     // bin (z, y slice, head/body): the head holds the atoms whose support
     // also reaches the slice below (g_y mod rows < p - 1)
@@ -202,7 +228,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   }
   // sum |q| of the chunk (fixed-point headroom), before any global store so
   // that the barriers below do not wait on outstanding writes
-  const double qsum = block_sums<1>(v, red);
+  block_sums<1>(v, wred);
   TRACE(0, 2);
   // exclusive scan of the bin counts, one bin per thread
   const int h = (tid < nbins) ? hist[tid] : 0;
@@ -213,7 +239,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   TRACE(0, 3);
   if (bin >= 0) rec[hist[bin] + rank] = r;
   if (tid < nbins) cnt[tid] = make_int2(h, ex);
-  if (tid == 0) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = qsum;
+  if (tid == 15) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = v[0];
   TRACE(0, 15);
 }
 
@@ -423,229 +449,290 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   __syncthreads();
   TRACE(1, 3);
 
-  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + ((size_t)z * K + y0) * KH;
+  // half spectrum columns [x'][z][y]: runs of R rows per x'
+  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K + y0;
   constexpr int PC = P::fixed ? PITCH : PITCH / 2;
   const cplx<T>* tc = reinterpret_cast<const cplx<T>*>(tile);
   for (int i = tid; i < R * KH; i += kSpreadThreads) {
-    const int y = i / KH, x = i - y * KH;
-    spec[i] = tc[y * PC + x];
+    const int x = i / R, y = i - x * R;
+    spec[(size_t)x * K * K + y] = tc[y * PC + x];
   }
   TRACE(1, 15);
 }
 
 // ---------------------------------------------------------------------------
-// k_fft_y: forward y FFT of one z-plane of the half spectrum.
+// k_conv: one x' column of the half spectrum (every y and z of one m1) per
+// workgroup: forward y and z transforms, the influence function with FP64
+// energy/virial partials, inverse z and y transforms (§III.A.2: the slab
+// transforms, the multiplication by Green's function data and the inverse
+// transforms, with the two corner turns folded into this one column).  When
+// the K x K column does not fit in LDS (FP64, K = 128) it is staged through
+// the workspace in halves.
 // ---------------------------------------------------------------------------
+// Threads per column: 1024, or 512 where the FP64 radix stages of K = 128
+// need more than the 128 registers a 1024-thread workgroup leaves per lane.
 template <class P, int K>
-__host__ __device__ constexpr size_t plane_lds_bytes() {
-  return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
-         (size_t)K * sizeof(cplx<typename P::real>);
+__host__ __device__ constexpr int conv_threads() {
+  return (sizeof(typename P::real) == 8 && K >= 128) ? 512 : 1024;
 }
-// k_fft_y also hosts the fixed-point headroom workgroup.
 template <class P, int K>
-__host__ __device__ constexpr size_t fft_y_lds_bytes() {
-  return plane_lds_bytes<P, K>() > block_sum_doubles(1, kPlaneThreads) * sizeof(double)
-             ? plane_lds_bytes<P, K>()
-             : block_sum_doubles(1, kPlaneThreads) * sizeof(double);
+__host__ __device__ constexpr size_t conv_tables_bytes() {
+  // twiddles, per-axis factors, one energy/virial row per wavefront
+  return (size_t)K * sizeof(cplx<typename P::real>) + 3 * (size_t)K * sizeof(double) +
+         16 * 8 * sizeof(double);
 }
-// k_inv_xy also hosts the energy/virial reduction workgroup.
+// Row pitch (complex elements) of the column in LDS: rows are y pencils,
+// columns z pencils; chosen with a bank model of the Stockham stages over
+// both (64-lane wavefront, 4-byte banks).
 template <class P, int K>
-__host__ __device__ constexpr size_t inv_lds_bytes() {
-  return plane_lds_bytes<P, K>() > block_sum_doubles(7, kPlaneThreads) * sizeof(double)
-             ? plane_lds_bytes<P, K>()
-             : block_sum_doubles(7, kPlaneThreads) * sizeof(double);
+__host__ __device__ constexpr int conv_pitch() {
+  return sizeof(typename P::real) == 4
+             ? (K == 16 ? 18 : K == 32 ? 38 : K == 48 ? 50 : K == 64 ? 71 : K == 96 ? 100
+                : K == 128 ? 135 : K + 1)
+             : (K == 64 ? 71 : K == 96 ? 102 : K == 128 ? 131 : K + 1);
+}
+// z-planes (y pass) or y rows (z pass) per LDS chunk
+template <class P, int K>
+__host__ __device__ constexpr int conv_chunk() {
+  return (size_t)K * conv_pitch<P, K>() * sizeof(cplx<typename P::real>) +
+                     conv_tables_bytes<P, K>() <= kMaxLds
+             ? K
+             : K / 2;
+}
+// z pass row pitch when the column is staged in chunks
+template <class P, int K>
+__host__ __device__ constexpr int conv_zpitch() {
+  return conv_chunk<P, K>() == K ? conv_pitch<P, K>() : conv_chunk<P, K>() + 3;
+}
+template <class P, int K>
+__host__ __device__ constexpr size_t conv_buf_bytes() {
+  constexpr size_t C = conv_chunk<P, K>();
+  constexpr size_t ny = C * conv_pitch<P, K>(), nz = (size_t)K * conv_zpitch<P, K>();
+  return (ny > nz ? ny : nz) * sizeof(cplx<typename P::real>);
+}
+template <class P, int K>
+__host__ __device__ constexpr size_t conv_lds_bytes() {
+  return conv_buf_bytes<P, K>() + conv_tables_bytes<P, K>();
 }
 
 template <class P, int K, bool BATCH>
-__global__ __launch_bounds__(kPlaneThreads) void k_fft_y(Args a_in, BatchArgs bt) {
+__global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
-  constexpr int KH = K / 2 + 1, PC = KH + 1;
+  constexpr int KH = K / 2 + 1;
+  constexpr int C = conv_chunk<P, K>();
+  constexpr int NC = K / C;
+  constexpr int PY = conv_pitch<P, K>();      // y pass: one row of pitch PY per z
+  constexpr int PZ = conv_zpitch<P, K>();     // z pass: one row of pitch PZ per z
+  constexpr int TK = fft_lanes(K);
+  constexpr int NT = conv_threads<P, K>();
+  constexpr double PI = 3.14159265358979323846;
+  static_assert(conv_lds_bytes<P, K>() <= kMaxLds, "convolution column does not fit in LDS");
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = pl + K * PC;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + conv_buf_bytes<P, K>());
+  double* bs = reinterpret_cast<double*>(tw + K);
+  double* wred = bs + 3 * K;
   TRACE(2, 0);
   const int tid = threadIdx.x;
-  if (blockIdx.x == K) {
+  if (blockIdx.x == KH) {
     // the extra workgroup (fixed point only): sum |q| 2^F must stay below
     // 2^51 so that every contribution and grid value is exact in FP64 and the
     // rounding of to_fixed holds
     const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
     double v[1] = {0.0};
-    for (int c = tid; c < a.n_chunks; c += kPlaneThreads) v[0] += absq[c];
-    const double qsum = block_sums<1>(v, reinterpret_cast<double*>(smem));
-    if (tid == 0 && qsum * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
+    for (int c = tid; c < a.n_chunks; c += NT) v[0] += absq[c];
+    block_sums<1>(v, wred);
+    if (tid == 15 && v[0] * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
       atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
     return;
   }
-  static_assert(K % kXcds == 0, "planes do not split over the XCDs");
-  const int z = xcd_local(blockIdx.x, K);
+  const int xp = blockIdx.x;  // m1
+  cplx<T>* col = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)xp * K * K;  // [z][y]
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
-  for (int i = tid; i < K * KH; i += kPlaneThreads) {
-    const int y = i / KH, x = i - y * KH;
-    pl[y * PC + x] = spec[i];
+  const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
+  for (int i = tid; i < K; i += NT) tw[i] = twg[i];
+  {
+    // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
+    const double fac = PI * PI / (a.beta * a.beta);
+    for (int i = tid; i < 3 * K; i += NT) {
+      const int ax = i / K, m = i - ax * K;
+      const int mt = (m <= K / 2) ? m : m - K;
+      // (a select, not a[ax]: a dynamic index would move a batched run's
+      // Args copy to scratch)
+      const double il = ax == 0 ? a.invL[0] : ax == 1 ? a.invL[1] : a.invL[2];
+      const double u = mt * il;
+      bs[i] = bsg[i] * exp(-fac * u * u);
+    }
   }
-  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
-  __syncthreads();
+
+  // --- forward y: one pencil per z
+  for (int c = 0; c < NC; ++c) {
+    const int z0 = c * C;
+    for (int i = tid; i < C * K; i += NT) {
+      const int zz = i / K, y = i - zz * K;
+      buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+    }
+    __syncthreads();
+    for (int task = tid; task < C * TK; task += NT) {
+      const int zz = task / TK, l = task - zz * TK;
+      fft_pencil<T, K, -1>(buf + zz * PY, 1, l, tw, 1);
+    }
+    __syncthreads();
+    if constexpr (NC > 1) {
+      for (int i = tid; i < C * K; i += NT) {
+        const int zz = i / K, y = i - zz * K;
+        col[(size_t)(z0 + zz) * K + y] = buf[zz * PY + y];
+      }
+      __syncthreads();
+    }
+  }
   TRACE(2, 1);
-  constexpr int TK = fft_lanes(K);
-  for (int task = tid; task < KH * TK; task += kPlaneThreads) {
-    const int x = task / TK, l = task - x * TK;
-    fft_pencil<T, K, -1>(pl + x, PC, l, tw, 1);
+
+  // --- z: forward transform, influence function, inverse transform.
+  // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) with
+  // B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3) in an orthorhombic
+  // cell.  The half spectrum counts every m1 = 1 .. K/2-1 twice (its
+  // Hermitian partner), m1 = 0 and m1 = K/2 once.  Per mode, with
+  // e = w G |F|^2 and u = 1/|m|^2 + pi^2/beta^2:
+  //   E += e,  P_ab += e (delta_ab - 2 u m_a m_b),
+  // accumulated as S0 = sum e and S_ab = sum e u m_a m_b, so that
+  // P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A Nyquist index aliases +K/2
+  // and -K/2 equally, so its sign-odd (off-diagonal) products vanish.
+  const double pref = a.coulomb / (PI * a.volume);
+  const double fac = PI * PI / (a.beta * a.beta);
+  const double mvx = xp * a.invL[0];
+  const double nx = (2 * xp == K) ? 0.0 : mvx;
+  const double wx = (xp == 0 || 2 * xp == K) ? 0.5 : 1.0;
+  const double mvx2 = mvx * mvx;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // S0, Sxx, Syy, Szz, Sxy, Sxz, Syz
+  for (int c = 0; c < NC; ++c) {
+    const int y0 = c * C;
+    if constexpr (NC > 1) {
+      for (int i = tid; i < K * C; i += NT) {
+        const int z = i / C, yy = i - z * C;
+        buf[z * PZ + yy] = col[(size_t)z * K + y0 + yy];
+      }
+      __syncthreads();
+    }
+    for (int task = tid; task < C * TK; task += NT) {
+      const int yy = task / TK, l = task - yy * TK;
+      fft_pencil<T, K, -1>(buf + yy, PZ, l, tw, 1);
+    }
+    __syncthreads();
+    TRACE(2, 2);
+    const double A = pref * bs[xp];
+#pragma unroll 2
+    for (int i = tid; i < K * C; i += NT) {
+      const int z = i / C, yy = i - z * C, y = y0 + yy;
+      const int my = (y <= K / 2) ? y : y - K, mz = (z <= K / 2) ? z : z - K;
+      const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
+      const double ny = (2 * y == K) ? 0.0 : mvy, nz = (2 * z == K) ? 0.0 : mvz;
+      const cplx<T> f = buf[z * PZ + yy];
+      double G = 0.0;
+      if (xp != 0 || y != 0 || z != 0) {
+        const double msq = fma(mvz, mvz, fma(mvy, mvy, mvx2));
+        // 1/msq: hardware reciprocal and two Newton steps
+        double r = __builtin_amdgcn_rcp(msq);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        G = A * bs[K + y] * bs[2 * K + z] * r;
+        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+        const double e = wx * G * f2;
+        const double eu = e * (r + fac);
+        const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
+        acc[0] += e;
+        acc[1] = fma(eux, mvx, acc[1]);
+        acc[2] = fma(euy, mvy, acc[2]);
+        acc[3] = fma(eu * mvz, mvz, acc[3]);
+        acc[4] = fma(eun, ny, acc[4]);
+        acc[5] = fma(eun, nz, acc[5]);
+        acc[6] = fma(eu * ny, nz, acc[6]);
+      }
+      const T g = (T)G;
+      buf[z * PZ + yy] = {f.x * g, f.y * g};
+    }
+    __syncthreads();
+    TRACE(2, 3);
+    for (int task = tid; task < C * TK; task += NT) {
+      const int yy = task / TK, l = task - yy * TK;
+      fft_pencil<T, K, 1>(buf + yy, PZ, l, tw, 1);
+    }
+    __syncthreads();
+    if constexpr (NC > 1) {
+      for (int i = tid; i < K * C; i += NT) {
+        const int z = i / C, yy = i - z * C;
+        col[(size_t)z * K + y0 + yy] = buf[z * PZ + yy];
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  TRACE(2, 2);
-  for (int i = tid; i < K * KH; i += kPlaneThreads) {
-    const int y = i / KH, x = i - y * KH;
-    spec[i] = pl[y * PC + x];
+  TRACE(2, 5);
+  // Energy/virial: fixed-order block sums -- one partial row per column
+  // (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz), added in column order later.
+  block_sums<7>(acc, wred);
+  if (tid == 15) {
+    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + xp * 8;
+    row[0] = acc[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
+#pragma unroll
+    for (int c = 4; c < 7; ++c) row[c] = -2.0 * acc[c];
+  }
+  TRACE(2, 4);
+
+  // --- inverse y
+  for (int c = 0; c < NC; ++c) {
+    const int z0 = c * C;
+    if constexpr (NC > 1) {
+      for (int i = tid; i < C * K; i += NT) {
+        const int zz = i / K, y = i - zz * K;
+        buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+      }
+      __syncthreads();
+    }
+    for (int task = tid; task < C * TK; task += NT) {
+      const int zz = task / TK, l = task - zz * TK;
+      fft_pencil<T, K, 1>(buf + zz * PY, 1, l, tw, 1);
+    }
+    __syncthreads();
+    for (int i = tid; i < C * K; i += NT) {
+      const int zz = i / K, y = i - zz * K;
+      col[(size_t)(z0 + zz) * K + y] = buf[zz * PY + y];
+    }
+    if constexpr (NC > 1) __syncthreads();
   }
   TRACE(2, 15);
 }
 
+// Sum of the energy/virial partial rows in row order, one thread per value
+// (the same order whatever the workgroup).
+__device__ void reduce_ev(const Args& a) {
+  const double* partial = reinterpret_cast<const double*>(a.ws + a.lay.partial);
+  const int c = threadIdx.x;
+  if (c < 7) {
+    double s = 0.0;
+    for (int b = 0; b < a.lay.conv_blocks; ++b) s += partial[b * 8 + c];
+    a.ev[c] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_reduce_ev(Args a) { reduce_ev(a); }
+
 // ---------------------------------------------------------------------------
-// k_pencil: z FFT, influence function with energy/virial, inverse z FFT.
+// k_inv_x: complex-to-real x transform of one z-plane into the potential
+// rows of the workspace (with a (p-1)-point wrap halo in front).  Used where
+// the fused interpolation below does not fit in LDS, and for the debug copy
+// of the potential; one extra workgroup adds the energy/virial rows.
 // ---------------------------------------------------------------------------
 template <class P, int K>
-__host__ __device__ constexpr size_t pencil_lds_bytes() {
-  constexpr int KH = K / 2 + 1, XW = (KH + pencil_xsplit(K) - 1) / pencil_xsplit(K);
-  return (size_t)K * (XW + 1) * sizeof(cplx<typename P::real>) +
-         (size_t)K * sizeof(cplx<typename P::real>) + 3 * (size_t)K * sizeof(double) +
-         block_sum_doubles(7, kPencilThreads) * sizeof(double);
+__host__ __device__ constexpr size_t inv_x_lds_bytes() {
+  return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
+         (size_t)K * sizeof(cplx<typename P::real>);
 }
 
-template <class P, int K, bool BATCH>
-__global__ __launch_bounds__(kPencilThreads) void k_pencil(Args a_in, BatchArgs bt) {
-  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
-  using T = typename P::real;
-  constexpr int KH = K / 2 + 1;
-  constexpr int XS = pencil_xsplit(K);
-  constexpr int XW = (KH + XS - 1) / XS;
-  constexpr int PW = XW + 1;
-  constexpr double PI = 3.14159265358979323846;
-  extern __shared__ __align__(16) unsigned char smem[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + K * PW;
-  double* bs = reinterpret_cast<double*>(tw + K);
-  double* red = bs + 3 * K;
-
-  TRACE(3, 0);
-  const int tid = threadIdx.x;
-  const int y = blockIdx.x / XS;
-  const int x0 = (blockIdx.x - y * XS) * XW;
-  const int xw = min(XW, KH - x0);
-  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec);
-  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
-  for (int i = tid; i < K * XW; i += kPencilThreads) {
-    const int zz = i / XW, xx = i - zz * XW;
-    if (xx < xw) buf[zz * PW + xx] = spec[((size_t)zz * K + y) * KH + x0 + xx];
-  }
-  for (int i = tid; i < K; i += kPencilThreads) tw[i] = twg[i];
-  {
-    // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
-    const double fac = PI * PI / (a.beta * a.beta);
-    for (int i = tid; i < 3 * K; i += kPencilThreads) {
-      const int ax = i / K, m = i - ax * K;
-      const int mt = (m <= K / 2) ? m : m - K;
-      const double u = mt * a.invL[ax];
-      bs[i] = bsg[i] * exp(-fac * u * u);
-    }
-  }
-  __syncthreads();
-  TRACE(3, 1);
-
-  constexpr int TK = fft_lanes(K);
-  for (int task = tid; task < XW * TK; task += kPencilThreads) {
-    const int xx = task / TK, l = task - xx * TK;
-    if (xx < xw) fft_pencil<T, K, -1>(buf + xx, PW, l, tw, 1);
-  }
-  __syncthreads();
-  TRACE(3, 2);
-
-  // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2).  In an
-  // orthorhombic cell B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3).
-  // The half spectrum counts every m1 = 1 .. K/2-1 twice (its Hermitian
-  // partner), m1 = 0 and m1 = K/2 once.
-  const double pref = a.coulomb / (PI * a.volume);
-  const double fac = PI * PI / (a.beta * a.beta);
-  const int my = (y <= K / 2) ? y : y - K;
-  const double mvy = my * a.invL[1];
-  const double ny = (2 * y == K) ? 0.0 : mvy;
-  const double Ty = bs[K + y];
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int i = tid; i < K * XW; i += kPencilThreads) {
-    const int zz = i / XW, xx = i - zz * XW;
-    if (xx >= xw) continue;
-    const int m1 = x0 + xx;
-    const int mz = (zz <= K / 2) ? zz : zz - K;
-    const double mvx = m1 * a.invL[0], mvz = mz * a.invL[2];
-    // a Nyquist index aliases +K/2 and -K/2 equally: its sign-odd products vanish
-    const double nx = (2 * m1 == K) ? 0.0 : mvx, nz = (2 * zz == K) ? 0.0 : mvz;
-    const double msq = mvx * mvx + mvy * mvy + mvz * mvz;
-    double G = 0.0, t = 0.0;
-    if (m1 != 0 || y != 0 || zz != 0) {
-      const double inv = 1.0 / msq;
-      G = pref * bs[m1] * Ty * bs[2 * K + zz] * inv;
-      t = 2.0 * (inv + fac);
-    }
-    cplx<T> f = buf[zz * PW + xx];
-    const double f2 = (double)f.x * (double)f.x + (double)f.y * (double)f.y;
-    const double e = ((m1 == 0 || 2 * m1 == K) ? 0.5 : 1.0) * G * f2;
-    acc[0] += e;
-    acc[1] += e * (1.0 - t * mvx * mvx);
-    acc[2] += e * (1.0 - t * mvy * mvy);
-    acc[3] += e * (1.0 - t * mvz * mvz);
-    acc[4] -= e * t * nx * ny;
-    acc[5] -= e * t * nx * nz;
-    acc[6] -= e * t * ny * nz;
-    const T g = (T)G;
-    buf[zz * PW + xx] = {f.x * g, f.y * g};
-  }
-  // Energy/virial: fixed-order block sums, one partial row per workgroup,
-  // added in workgroup order by the next kernel on the stream.  (Done before
-  // the final stores: a barrier after global stores waits for them.)
-  const double tot = block_sums<7>(acc, red);
-  if (tid < 7) reinterpret_cast<double*>(a.ws + a.lay.partial)[blockIdx.x * 8 + tid] = tot;
-  TRACE(3, 3);
-
-  for (int task = tid; task < XW * TK; task += kPencilThreads) {
-    const int xx = task / TK, l = task - xx * TK;
-    if (xx < xw) fft_pencil<T, K, 1>(buf + xx, PW, l, tw, 1);
-  }
-  __syncthreads();
-  TRACE(3, 4);
-  for (int i = tid; i < K * XW; i += kPencilThreads) {
-    const int zz = i / XW, xx = i - zz * XW;
-    if (xx < xw) spec[((size_t)zz * K + y) * KH + x0 + xx] = buf[zz * PW + xx];
-  }
-  TRACE(3, 15);
-}
-
-// Sum of the energy/virial partial rows in row order by one workgroup.
-__device__ void reduce_ev(const Args& a, double* red) {
-  const double* partial = reinterpret_cast<const double*>(a.ws + a.lay.partial);
-  const int rows = a.lay.pencil_blocks;
-  double r[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = threadIdx.x; b < rows; b += blockDim.x) {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) r[c] += partial[b * 8 + c];
-  }
-  const double tot = block_sums<7>(r, red);
-  if (threadIdx.x < 7) a.ev[threadIdx.x] = tot;
-}
-
-// (same block size as k_inv_xy's reduction workgroup: identical sum order)
-__global__ __launch_bounds__(kPlaneThreads) void k_reduce_ev(Args a) {
-  __shared__ double red[block_sum_doubles(7, kPlaneThreads)];
-  reduce_ev(a, red);
-}
-
-// ---------------------------------------------------------------------------
-// k_inv_xy: inverse y FFT and complex-to-real x FFT of one z-plane.
-// ---------------------------------------------------------------------------
 template <class P, int K, int ORDER, bool BATCH>
-__global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a_in, BatchArgs bt) {
+__global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int M = K / 2, KH = K / 2 + 1, PC = KH + 1;
@@ -653,32 +740,21 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a_in, BatchArgs b
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K * PC;
-  TRACE(4, 0);
+  TRACE(3, 0);
   const int tid = threadIdx.x;
   if (blockIdx.x == K) {
-    // the extra workgroup: energy and virial
-    if (a.reduce_ev) reduce_ev(a, reinterpret_cast<double*>(smem));
+    if (a.reduce_ev) reduce_ev(a);
     return;
   }
   const int z = xcd_local(blockIdx.x, K);
-  const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K * KH;
-  for (int i = tid; i < K * KH; i += kPlaneThreads) {
-    const int y = i / KH, x = i - y * KH;
-    pl[y * PC + x] = spec[i];
+  const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
+  for (int i = tid; i < KH * K; i += kPlaneThreads) {
+    const int x = i / K, y = i - x * K;
+    pl[y * PC + x] = spec[((size_t)x * K + z) * K + y];
   }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
   __syncthreads();
-  TRACE(4, 1);
-
-  constexpr int TK = fft_lanes(K);
-  for (int task = tid; task < KH * TK; task += kPlaneThreads) {
-    const int x = task / TK, l = task - x * TK;
-    fft_pencil<T, K, 1>(pl + x, PC, l, tw, 1);
-  }
-  __syncthreads();
-  TRACE(4, 2);
-
   constexpr int TM = fft_lanes(M);
   for (int task = tid; task < K * TM; task += kPlaneThreads) {
     const int y = task / TM, l = task - y * TM;
@@ -687,8 +763,6 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a_in, BatchArgs b
     fft_pencil<T, M, 1>(row, 1, l, tw, 2);
   }
   __syncthreads();
-  TRACE(4, 3);
-
   T* phi = reinterpret_cast<T*>(a.ws + a.lay.phi) + (size_t)z * K * PP;
   for (int i = tid; i < K * PP; i += kPlaneThreads) {
     const int y = i / PP, xh = i - y * PP;
@@ -697,25 +771,35 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_xy(Args a_in, BatchArgs b
     if (x >= K) x -= K;
     phi[i] = reinterpret_cast<const T*>(pl + y * PC)[x];
   }
-  TRACE(4, 15);
+  TRACE(3, 15);
 }
 
 // ---------------------------------------------------------------------------
-// k_gather: force interpolation, one atom per thread in sorted order.
+// k_interp: complex-to-real x transforms and force interpolation for the
+// atoms of one (z-plane, y-slice) bin per workgroup (§III.A.3).  The
+// workgroup transforms the p planes z-p+1 .. z, rows y0-p+1 .. y0+R-1, of
+// the spectrum into LDS -- the potential every atom of the bin reads -- and
+// interpolates those atoms from LDS, one per thread.  The arithmetic per atom
+// is that of k_gather.
 // ---------------------------------------------------------------------------
-template <class P, int K, int ORDER, bool BATCH>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs bt) {
-  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+template <class P, int K, int ORDER>
+__host__ __device__ constexpr size_t interp_lds_bytes() {
+  constexpr size_t R = K / nq_of(K), NROW = (size_t)ORDER * (R + ORDER - 1), PC = K / 2 + 2;
+  return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)K * sizeof(cplx<typename P::real>) +
+         (size_t)(kInterpItems + 32) * sizeof(int);
+}
+template <class P, int K, int ORDER>
+__host__ __device__ constexpr bool interp_fused() {
+  return interp_lds_bytes<P, K, ORDER>() <= kMaxLds;
+}
+
+// Force on one atom from the potential: rows(jz, jy) points at the potential
+// row of support point (jz, jy) and xs[jx] at the x index of point jx.
+template <class P, int ORDER, class Rows>
+__device__ __forceinline__ void interpolate(const Args& a, const typename P::rec& r, Rows rows,
+                                            const int* xs, int K) {
+  const double qi = r.qd;
   using T = typename P::real;
-  using Rec = typename P::rec;
-  constexpr int PP = phi_pitch_of(K, ORDER);
-  TRACE(5, 0);
-  const int t = blockIdx.x * kGatherThreads + threadIdx.x;
-  if (t >= a.N) return;
-  const Rec r = reinterpret_cast<const Rec*>(a.ws + a.lay.rec)[t];
-  const double qi = a.q[r.idx];
-  const T* phi = reinterpret_cast<const T*>(a.ws + a.lay.phi);
-  const int gx = r.g & 1023, gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
   T thx[ORDER], thy[ORDER], thz[ORDER], dthx[ORDER], dthy[ORDER], dthz[ORDER];
   bspline<ORDER>(r.w[0], thx, dthx);
   bspline<ORDER>(r.w[1], thy, dthy);
@@ -723,17 +807,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs 
   T sx = 0, sy = 0, sz = 0;
 #pragma unroll
   for (int jz = 0; jz < ORDER; ++jz) {
-    int zz = gz - ORDER + 1 + jz;
-    if (zz < 0) zz += K;
 #pragma unroll
     for (int jy = 0; jy < ORDER; ++jy) {
-      int yy = gy - ORDER + 1 + jy;
-      if (yy < 0) yy += K;
-      const T* row = phi + ((size_t)zz * K + yy) * PP + gx;
+      const T* row = rows(jz, jy);
       T s0 = 0, s1 = 0;
 #pragma unroll
       for (int jx = 0; jx < ORDER; ++jx) {
-        const T v = row[jx];
+        const T v = row[xs[jx]];
         s0 += thx[jx] * v;
         s1 += dthx[jx] * v;
       }
@@ -742,11 +822,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs 
       sz += thy[jy] * dthz[jz] * s0;
     }
   }
-  const int idx = r.idx;
   const double qk = -qi * (double)K;
   const double f[3] = {qk * a.invL[0] * (double)sx, qk * a.invL[1] * (double)sy,
                        qk * a.invL[2] * (double)sz};
-  double* out = a.forces + 3 * (size_t)idx;
+  double* out = a.forces + 3 * (size_t)r.idx;
   if (a.accumulate) {
     out[0] += f[0];
     out[1] += f[1];
@@ -756,7 +835,150 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs 
     out[1] = f[1];
     out[2] = f[2];
   }
-  TRACE(5, 15);
+}
+
+template <class P, int K, int ORDER, bool BATCH>
+__global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs bt) {
+  if constexpr (interp_fused<P, K, ORDER>()) {
+    const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+    using T = typename P::real;
+    using Rec = typename P::rec;
+    constexpr int M = K / 2, KH = M + 1, PC = KH + 1;
+    constexpr int NQ = nq_of(K), R = K / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
+    constexpr int NB = 2 * K * NQ;
+    constexpr int NT = kInterpThreads;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* tw = buf + NROW * PC;
+    int* list = reinterpret_cast<int*>(tw + K);
+    int* wsum = list + kInterpItems;
+    TRACE(4, 0);
+    const int tid = threadIdx.x;
+    if (blockIdx.x == K * NQ) {
+      if (a.reduce_ev) reduce_ev(a);
+      return;
+    }
+    if (a.N == 0) return;
+    static_assert((K * NQ) % kXcds == 0, "interpolation tiles do not split over the XCDs");
+    const int tile_id = xcd_local(blockIdx.x, K * NQ);
+    const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
+    const int2* cnt = reinterpret_cast<const int2*>(a.ws + a.lay.cnt);
+    const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
+    const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
+    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+    // the bin's atoms: bins (z, qs, head) and (z, qs, body) are adjacent, so
+    // in chunk c they are one run of records
+    const int b0 = (z * NQ + qs) * 2;
+    int2 dh = {0, 0}, db = {0, 0};
+    if (tid < a.n_chunks) {
+      dh = cnt[(size_t)tid * NB + b0];
+      db = cnt[(size_t)tid * NB + b0 + 1];
+    }
+    // spectrum rows (jz, r): plane z-p+1+jz, row y0-p+1+r, all x'
+    constexpr int NE = KH * NROW;
+#pragma unroll 4
+    for (int e = tid; e < NE; e += NT) {
+      const int r = e % RR, t2 = e / RR, jz = t2 % ORDER, x = t2 / ORDER;
+      int zz = z - ORDER + 1 + jz, yy = y0 - ORDER + 1 + r;
+      if (zz < 0) zz += K;
+      if (yy < 0) yy += K;
+      buf[(jz * RR + r) * PC + x] = spec[((size_t)x * K + zz) * K + yy];
+    }
+    if (tid < K) tw[tid] = twg[tid];
+    TRACE(4, 1);
+
+    bool phi_ready = false;
+    for (int c0 = 0; c0 < a.n_chunks; c0 += NT) {
+      int len = 0, beg = 0;
+      if (c0 > 0 && c0 + tid < a.n_chunks) {
+        dh = cnt[(size_t)(c0 + tid) * NB + b0];
+        db = cnt[(size_t)(c0 + tid) * NB + b0 + 1];
+      }
+      if (c0 + tid < a.n_chunks) {
+        len = dh.x + db.x;
+        beg = (c0 + tid) * kChunk + dh.y;
+      }
+      int total;
+      const int pre = block_exclusive_scan(len, wsum, &total);
+      TRACE(4, 3);
+      for (int w0 = 0; w0 < total; w0 += kInterpItems) {
+        const int wn = min(kInterpItems, total - w0);
+        const int lo = max(pre, w0), hi = min(pre + len, w0 + wn);
+        for (int t = lo; t < hi; ++t) list[t - w0] = beg + (t - pre);
+        __syncthreads();
+        TRACE(4, 4);
+        // the first record loads are issued before the transforms
+        int it = tid;
+        Rec r;
+        if (it < wn) r = rec[list[it]];
+        if (!phi_ready) {
+          constexpr int TM = fft_lanes(M);
+          for (int task = tid; task < NROW * TM; task += NT) {
+            const int row = task / TM, l = task - row * TM;
+            c2r_pre<T, K>(buf + row * PC, l, tw);
+            fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
+          }
+          __syncthreads();
+          phi_ready = true;
+          TRACE(4, 2);
+        }
+        for (; it < wn; it += NT) {
+          Rec rn;
+          if (it + NT < wn) rn = rec[list[it + NT]];
+          const int gx = r.g & 1023, gy = (r.g >> 10) & 1023;
+          int xs[ORDER];
+#pragma unroll
+          for (int jx = 0; jx < ORDER; ++jx) {
+            const int x = gx - ORDER + 1 + jx;
+            xs[jx] = x < 0 ? x + K : x;
+          }
+          const int ry = gy - y0;
+          interpolate<P, ORDER>(
+              a, r,
+              [&](int jz, int jy) {
+                return reinterpret_cast<const T*>(buf + (jz * RR + ry + jy) * PC);
+              },
+              xs, K);
+          r = rn;
+        }
+        __syncthreads();
+      }
+      __syncthreads();  // wsum is reused by the next batch's scan
+    }
+    TRACE(4, 15);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_gather: force interpolation from the potential rows of the workspace, one
+// atom per thread in sorted order (§III.A.3).
+// ---------------------------------------------------------------------------
+template <class P, int K, int ORDER, bool BATCH>
+__global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  using T = typename P::real;
+  using Rec = typename P::rec;
+  constexpr int PP = phi_pitch_of(K, ORDER);
+  TRACE(4, 0);
+  const int t = blockIdx.x * kGatherThreads + threadIdx.x;
+  if (t >= a.N) return;
+  const Rec r = reinterpret_cast<const Rec*>(a.ws + a.lay.rec)[t];
+  const T* phi = reinterpret_cast<const T*>(a.ws + a.lay.phi);
+  const int gx = r.g & 1023, gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
+  // rows carry a (p-1)-point halo in front: point jx of the support is gx + jx
+  int xs[ORDER];
+#pragma unroll
+  for (int jx = 0; jx < ORDER; ++jx) xs[jx] = gx + jx;
+  interpolate<P, ORDER>(
+      a, r,
+      [&](int jz, int jy) {
+        int zz = gz - ORDER + 1 + jz, yy = gy - ORDER + 1 + jy;
+        if (zz < 0) zz += K;
+        if (yy < 0) yy += K;
+        return phi + ((size_t)zz * K + yy) * PP;
+      },
+      xs, K);
+  TRACE(4, 15);
 }
 
 __global__ void k_clear_flags(unsigned* ctrl) {
@@ -845,9 +1067,8 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
   L.phi_pitch = phi_pitch_of(K, order);
   L.phi = o;       o = align256(o + (size_t)K * K * L.phi_pitch * real);
-  L.xsplit = pencil_xsplit(K);
-  L.pencil_blocks = K * L.xsplit;
-  L.partial = o;   o = align256(o + (size_t)L.pencil_blocks * 8 * sizeof(double));
+  L.conv_blocks = (int)kh;
+  L.partial = o;   o = align256(o + (size_t)L.conv_blocks * 8 * sizeof(double));
   L.dbg = o;       o = align256(o + (size_t)K * K * K * 8);
   L.args = o;      o = align256(o + sizeof(Args));
   L.total = o;
@@ -862,11 +1083,12 @@ hipError_t raise_lds_limits() {
   hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O, B>, attr,
                                      (int)spread_lds_bytes<P, KK>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_fft_y<P, KK, B>, attr, (int)fft_y_lds_bytes<P, KK>());
+    e = hipFuncSetAttribute((const void*)k_conv<P, KK, B>, attr, (int)conv_lds_bytes<P, KK>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_inv_xy<P, KK, O, B>, attr, (int)inv_lds_bytes<P, KK>());
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_pencil<P, KK, B>, attr, (int)pencil_lds_bytes<P, KK>());
+    e = hipFuncSetAttribute((const void*)k_inv_x<P, KK, O, B>, attr, (int)inv_x_lds_bytes<P, KK>());
+  if (e == hipSuccess && interp_fused<P, KK, O>())
+    e = hipFuncSetAttribute((const void*)k_interp<P, KK, O, B>, attr,
+                            (int)interp_lds_bytes<P, KK, O>());
   return e;
 }
 
@@ -882,6 +1104,22 @@ hipError_t prepare_kernels(int K, int order, int precision) {
       });
     });
   });
+}
+
+bool interp_is_fused(int K, int order, int precision) {
+  bool fused = false;
+  (void)with_prec(precision, [&](auto pt) {
+    using P = decltype(pt);
+    return with_K(K, [&](auto kc) {
+      constexpr int KK = decltype(kc)::value;
+      return with_order(order, [&](auto oc) {
+        constexpr int O = decltype(oc)::value;
+        fused = interp_fused<P, KK, O>();
+        return hipSuccess;
+      });
+    });
+  });
+  return fused;
 }
 
 template <class F>
@@ -918,41 +1156,27 @@ hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t, const 
   });
 }
 
-hipError_t launch_fft_y(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
+hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
       constexpr int KK = decltype(kc)::value;
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
-        const int blocks = KK + (P::fixed ? 1 : 0);
-        return launch(k_fft_y<P, KK, B>, dim3(blocks), dim3(kPlaneThreads),
-                      fft_y_lds_bytes<P, KK>(), s, t, a, bt);
-      });
-    });
-  });
-}
-
-hipError_t launch_pencil(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
-  return with_prec(a.precision, [&](auto pt) {
-    using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
-      return with_batch(bt, [&](auto bc) {
-        constexpr bool B = decltype(bc)::value;
-        return launch(k_pencil<P, KK, B>, dim3(KK * pencil_xsplit(KK)), dim3(kPencilThreads),
-                      pencil_lds_bytes<P, KK>(), s, t, a, bt);
+        const int blocks = KK / 2 + 1 + (P::fixed ? 1 : 0);
+        return launch(k_conv<P, KK, B>, dim3(blocks), dim3(conv_threads<P, KK>()),
+                      conv_lds_bytes<P, KK>(), s, t, a, bt);
       });
     });
   });
 }
 
 hipError_t launch_reduce_ev(const Args& a, hipStream_t s) {
-  k_reduce_ev<<<dim3(1), dim3(kPlaneThreads), 0, s>>>(a);
+  k_reduce_ev<<<dim3(1), dim3(64), 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
+hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
     return with_K(a.K, [&](auto kc) {
@@ -962,9 +1186,31 @@ hipError_t launch_inv(const Args& a, hipStream_t s, const Timing& t, const Batch
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
           const int blocks = KK + ((a.reduce_ev || B) ? 1 : 0);
-          return launch(k_inv_xy<P, KK, O, B>, dim3(blocks), dim3(kPlaneThreads),
-                        inv_lds_bytes<P, KK>(), s, t, a, bt);
+          return launch(k_inv_x<P, KK, O, B>, dim3(blocks), dim3(kPlaneThreads),
+                        inv_x_lds_bytes<P, KK>(), s, t, a, bt);
         });
+      });
+    });
+  });
+}
+
+hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
+  return with_prec(a.precision, [&](auto pt) {
+    using P = decltype(pt);
+    return with_K(a.K, [&](auto kc) {
+      constexpr int KK = decltype(kc)::value;
+      return with_order(a.order, [&](auto oc) {
+        constexpr int O = decltype(oc)::value;
+        if constexpr (!interp_fused<P, KK, O>()) {
+          return hipErrorInvalidValue;
+        } else {
+          return with_batch(bt, [&](auto bc) {
+            constexpr bool B = decltype(bc)::value;
+            const int blocks = KK * nq_of(KK) + ((a.reduce_ev || B) ? 1 : 0);
+            return launch(k_interp<P, KK, O, B>, dim3(blocks), dim3(kInterpThreads),
+                          interp_lds_bytes<P, KK, O>(), s, t, a, bt);
+          });
+        }
       });
     });
   });
@@ -997,7 +1243,7 @@ hipError_t launch_clear_flags(const Args& a, hipStream_t s) {
 
 #ifdef SPME_TRACE
 // Trace builds only: point the phase trace at a device buffer of
-// 6 * 1024 * 16 uint64 (or NULL to stop tracing).
+// 5 * 1024 * 16 uint64 (or NULL to stop tracing).
 extern "C" int spme_trace_set(void* buf) {
   unsigned long long* p = static_cast<unsigned long long*>(buf);
   return hipMemcpyToSymbol(HIP_SYMBOL(spme::g_trace), &p, sizeof(p)) == hipSuccess ? 0 : 5;

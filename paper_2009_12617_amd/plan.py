@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import PME_FP32_FIXED, PME_FP64, check
 
-KERNEL_NAMES = ("bin", "spread_x", "fft_y", "convolve_z", "inverse_xy", "gather")
+KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "inverse_x", "gather")
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64}
 
 
@@ -161,14 +161,15 @@ class Plan:
         check(self._lib.pme_set_debug(self._h, int(bool(keep_charge_grid))), "pme_set_debug")
 
     def debug_grid(self, which):
-        """0: charge grid (int64 fixed point or float64), 1: half spectrum
-        (complex), 2: potential phi; shaped [K, K, K] / [K, K, K/2+1]."""
+        """0: charge grid (int64 fixed point or float64) [z, y, x], 1: half
+        spectrum (complex) as columns [x', z, y] of shape [K/2+1, K, K],
+        2: potential phi [z, y, x]."""
         K, kh = self.K, self.K // 2 + 1
         fx = self.precision == "fp32_fixed"
         if which == 0:
             out = torch.empty((K, K, K), dtype=torch.int64 if fx else torch.float64, device=self.device)
         elif which == 1:
-            out = torch.empty((K, K, kh), dtype=torch.complex64 if fx else torch.complex128, device=self.device)
+            out = torch.empty((kh, K, K), dtype=torch.complex64 if fx else torch.complex128, device=self.device)
         elif which == 2:
             out = torch.empty((K, K, K), dtype=torch.float32 if fx else torch.float64, device=self.device)
         else:
@@ -184,6 +185,12 @@ class Plan:
         if rc not in (0, 4, 6):
             check(rc, "pme_check")
         return int(flags.value)
+
+    @property
+    def interp_fused(self):
+        """True when the inverse x FFT and interpolation run as one launch
+        (timed in the "gather" slot; "inverse_x" stays empty)."""
+        return self._lib.pme_interp_fused(self._h) == 1
 
     def kernel_timing(self, enable=True):
         check(self._lib.pme_kernel_timing(self._h, int(bool(enable))), "pme_kernel_timing")

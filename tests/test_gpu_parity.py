@@ -80,11 +80,12 @@ def test_fixed_point_grid_bit_exact(P, case):
     got = plan.debug_grid(0).cpu().numpy()
     ref, ref32 = oracle.mirror_grid(pos, q, box, K, p)
     assert np.array_equal(got, ref), f"{int((got != ref).sum())} grid points differ"
-    # first FFT passes (x real-to-complex, then y) of the quantised grid
+    # first FFT pass (x, real-to-complex) of the quantised grid, stored as
+    # columns [x', z, y]
     spec = plan.debug_grid(1).cpu().numpy().astype(np.complex128)
-    want = np.fft.fft(np.fft.rfft(ref32.astype(np.float64), axis=2), axis=1)
+    want = np.fft.rfft(ref32.astype(np.float64), axis=2).transpose(2, 0, 1)
     err = np.abs(spec - want).max() / np.abs(want).max()
-    print(f"xy-pass max rel err {err:.2e}", flush=True)
+    print(f"x-pass max rel err {err:.2e}", flush=True)
     assert err < 2e-6
 
 
@@ -227,7 +228,7 @@ def test_sticky_flags(P):
     assert plan.check() == 0  # cleared
     ref, _ = oracle.mirror_grid(bad, q, box, 32, 4, allow_nonfinite=True)
     assert np.array_equal(grid, ref)
-    # fixed-point headroom: sum |q| 2^F >= 2^52 raises the overflow flag
+    # fixed-point headroom: sum |q| 2^F >= 2^51 raises the overflow flag
     plan2 = P.Plan(32, 4, 0.35, max_atoms=300, frac_bits=40)
     plan2.step(dev(pos), dev(q * 200.0), box)
     assert plan2.check() & 2
