@@ -6,7 +6,8 @@ grid, B-spline order 4, beta = 0.34 1/A; a random walk of N(0, 0.01 A) per
 coordinate per frame gives the frame sequence, staged in HBM before timing.
 A step is one full pme_step (bin, spread + x FFT, y/z FFTs + influence
 function + energy/virial + inverse z/y FFTs, inverse x FFT + force
-interpolation) on the next frame, stream-ordered after the previous one.
+interpolation: four launches) on the next frame, stream-ordered after the
+previous one.
 
 Prints one JSON line (rank 0).  Extra fields: the plain FP64 path's time on
 the same frames, per-step p50/p99 latency, per-kernel times, the roofline of
@@ -26,31 +27,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(N, K, kernel, fp64=False, fused=True):
+def algorithmic_bytes(N, K, kernel, fp64=False):
     """Algorithmic HBM bytes one launch of `kernel` moves:
     atoms 32 B read by spreading, 32 B read + 24 B written by interpolation;
     the charge grid (8 B/point) written and read; the half spectrum
     (8 or 16 B/point) across the two corner turns (written by the forward
     slab pass, read and written by the pencil pass, read by the inverse slab
     pass); the potential written and read.  Each term is charged to the
-    kernel that performs that step; with the fused interpolation the
-    inverse-x terms go to "gather"."""
+    kernel that performs that step."""
     kh = K // 2 + 1
     cs = 16 if fp64 else 8       # complex bytes
     rs = 8 if fp64 else 4        # potential bytes
-    inv_x = cs * K * K * kh + rs * K ** 3
     return {
         "bin": 32 * N,
         "spread_x": 16 * K ** 3 + cs * K * K * kh,
         "convolve_yz": 2 * cs * K * K * kh,
-        "inverse_x": 0 if fused else inv_x,
-        "gather": 56 * N + rs * K ** 3 + (inv_x if fused else 0),
+        "interpolate": cs * K * K * kh + 2 * rs * K ** 3 + 56 * N,
     }[kernel]
 
 
 def step_bytes(N, K, fp64=False):
     return sum(algorithmic_bytes(N, K, k, fp64) for k in
-               ("bin", "spread_x", "convolve_yz", "inverse_x", "gather"))
+               ("bin", "spread_x", "convolve_yz", "interpolate"))
 
 
 def source_digest():
@@ -131,7 +129,7 @@ def bench_batched(torch, dev, Plan, Batch, I, reps=200):
         "step_algorithmic_bytes": int(nbytes),
         "roofline_frac": nbytes / (per.mean() * 1e-6) / 1e9 / HBM_PEAK_GBS,
         "same_as_single_steps": bool(same and replay_same),
-        "launch": "one HIP graph: 6 kernels x 3 grid groups, each launch over all systems of its group",
+        "launch": "one HIP graph: 4 kernels x 3 grid groups, each launch over all systems of its group",
     }
 
 
@@ -343,7 +341,7 @@ def main():
     print("# per-kernel us: " + ", ".join(f"{k}={v:.2f}" for k, v in kavg_us.items()),
           file=sys.stderr, flush=True)
     dom = max(kavg_us, key=kavg_us.get)
-    dom_bytes = algorithmic_bytes(N, K, dom, fused=plan.interp_fused)
+    dom_bytes = algorithmic_bytes(N, K, dom)
     achieved = dom_bytes / (kavg_us[dom] * 1e-6) / 1e9
     traffic = measured_traffic(dom)
 

@@ -75,6 +75,9 @@ typedef enum {
 /* Sticky device flags reported by pme_check. */
 #define PME_FLAG_NONFINITE 1u
 #define PME_FLAG_OVERFLOW 2u
+/* Atom buckets still held a previous binning (a replayed graph that holds
+ * part of a step); atoms were dropped. */
+#define PME_FLAG_BUCKETS 4u
 
 /* Bytes of device workspace a plan with these parameters needs (0 when the
  * parameters are unsupported).  Host only; no device is touched. */
@@ -115,17 +118,21 @@ int pme_set_stream(pme_plan *plan, void *stream);
  *   q    device [N] doubles
  *   N    0 <= N <= max_atoms
  *   box  HOST [9] doubles, rows a1, a2, a3; must be diagonal (orthorhombic)
- * pos and q must stay valid until pme_gather of the same step has been
- * enqueued (it reads q again). */
+ * pos and q are read by the launches this call enqueues only.  A spread
+ * that follows a spread without pme_solve in between first clears the
+ * earlier one's atom buckets (one extra small launch). */
 int pme_spread(pme_plan *plan, const double *pos, const double *q, int N, const double box[9]);
 
 /* Green's-function convolution (§III.A.2: the y and z transforms, the
  * multiplication, the inverse z and y transforms), energy and virial.
+ * Exactly once after each pme_spread (else PME_ESTATE): it transforms the
+ * spectrum in place.
  *   ev   device [7] doubles: E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz (overwritten),
  *        or NULL to skip writing them. */
 int pme_solve(pme_plan *plan, double *ev);
 
 /* Inverse x transform and force interpolation (end of §III.A.2, §III.A.3).
+ * After pme_solve (else PME_ESTATE); may be repeated.
  *   forces      device [N][3] doubles in the caller's atom order
  *   accumulate  0 overwrites, 1 adds to the existing values */
 int pme_gather(pme_plan *plan, double *forces, int accumulate);
@@ -147,7 +154,10 @@ int pme_bind(pme_plan *plan, const double *pos, const double *q, int N, const do
  * systems of uneven size share every dispatch.  Enqueues kernel launches only
  * (no allocation, copy or synchronisation), so a run can be captured in a
  * hipGraph and replayed.  Each system's result is the same as its own
- * pme_step.  Returns PME_ESTATE if a plan was never bound. */
+ * pme_step.  Returns PME_ESTATE if a plan was never bound.
+ * A replayed graph must hold whole steps (pme_step, or pme_spread through
+ * pme_gather, or pme_batch_run): the atom buckets a spread fills are moved
+ * on by the convolution that follows it. */
 int pme_batch_run(pme_plan *const *plans, int n, void *stream);
 
 /* Keep a copy of the charge grid at each spread (costs K1 K2 K3 x 8 bytes
@@ -170,7 +180,8 @@ size_t pme_debug_grid_bytes(pme_plan *plan, int which);
 
 /* Synchronise the plan's stream, return the sticky device flags
  * (PME_FLAG_*) in *flags and clear them.  Returns PME_ENONFINITE or
- * PME_EOVERFLOW when the matching flag was set, else PME_OK. */
+ * PME_EOVERFLOW, or PME_ESTATE for PME_FLAG_BUCKETS, when the matching flag
+ * was set, else PME_OK. */
 int pme_check(pme_plan *plan, unsigned *flags);
 
 /* Per-kernel timing with HIP events on the plan's stream (off by default).
@@ -179,17 +190,10 @@ int pme_check(pme_plan *plan, unsigned *flags);
  * kernel's own execution; pme_kernel_times
  * synchronises, adds the elapsed times of all completed launches into
  * ms[0..n-1] (kernel order: 0 bin, 1 spread + x FFT, 2 y/z FFTs with the
- * influence function and the inverse z/y FFTs, 3 inverse x FFT, 4 force
- * interpolation) and returns the number of steps accumulated in *steps.
- * Where pme_interp_fused(plan) is 1, slot 4 times the inverse x FFT and the
- * interpolation together and slot 3 stays 0. */
+ * influence function and the inverse z/y FFTs, 3 inverse x FFT + force
+ * interpolation) and returns the number of steps accumulated in *steps. */
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
-
-/* 1 when the plan runs the inverse x FFT and force interpolation as one
- * launch (the potential then never leaves LDS), 0 when they are two launches
- * through the workspace (FP64 with K = 128 and p = 6), -1 for a NULL plan. */
-int pme_interp_fused(const pme_plan *plan);
 
 /* Human-readable text for a pme_status. */
 const char *pme_strerror(int code);

@@ -15,6 +15,7 @@ PME_FP64 = 0
 PME_FP32_FIXED = 1
 PME_FLAG_NONFINITE = 1
 PME_FLAG_OVERFLOW = 2
+PME_FLAG_BUCKETS = 4
 
 STATUS = {0: "PME_OK", 1: "PME_EINVAL", 2: "PME_EUNSUPPORTED", 3: "PME_EWORKSPACE",
           4: "PME_EOVERFLOW", 5: "PME_EDEVICE", 6: "PME_ENONFINITE", 7: "PME_ESTATE"}
@@ -83,8 +84,6 @@ def load():
     lib.pme_kernel_timing.argtypes = [vp, i]
     lib.pme_kernel_times.restype = i
     lib.pme_kernel_times.argtypes = [vp, dp, i, ctypes.POINTER(ctypes.c_int)]
-    lib.pme_interp_fused.restype = i
-    lib.pme_interp_fused.argtypes = [vp]
     _lib = lib
     return lib
 

@@ -25,7 +25,10 @@ struct TimedLaunch {
   hipEvent_t start, stop;
 };
 
-enum State { kCreated = 0, kSpread = 1, kSolved = 2 };
+// kSpread: binned and spread, bucket counts still live (a new spread must
+// clear them first); kSolved: convolved, counts cleared; kDirty: a launch
+// failed midway, counts unknown.
+enum State { kCreated = 0, kSpread = 1, kSolved = 2, kDirty = 3 };
 
 }  // namespace
 
@@ -40,7 +43,6 @@ struct pme_plan {
   int state = kCreated;
   int keep_grid = 0;
   int grid_kept = 0;
-  int fused_interp = 1;  // inverse x and interpolation in one launch
   // host copies of the uploaded tables
   std::vector<double> bsq;
   std::vector<double> tw64;
@@ -186,9 +188,12 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   p->tw32.resize(2 * (size_t)K);
   for (int i = 0; i < 2 * K; ++i) p->tw32[i] = (float)p->tw64[i];
 
-  p->fused_interp = spme::interp_is_fused(K, order, precision) ? 1 : 0;
   hipError_t e = spme::prepare_kernels(K, order, precision);
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ctrl, 0, 64 * sizeof(unsigned), p->stream);
+  // bucket and overflow counts start at zero; each step's convolution
+  // clears them again for the next
+  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.bcnt, 0, L.bcnt2 - L.bcnt, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ovf, 0, 4 * sizeof(unsigned), p->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * 3 * K,
                        hipMemcpyHostToDevice, p->stream);
@@ -273,6 +278,11 @@ int pme_spread(pme_plan* p, const double* pos, const double* q, int N, const dou
   Args& a = p->cur;
   int rc = set_inputs(p, a, pos, q, N, box);
   if (rc != PME_OK) return rc;
+  if (p->state == kSpread || p->state == kDirty) {
+    // the previous binning's counts were never moved on by a convolution
+    if (spme::launch_clear_counts(a, p->stream) != hipSuccess) return PME_EDEVICE;
+  }
+  p->state = kDirty;
   rc = timed(p, 0, [&](const spme::Timing& t) { return spme::launch_bin(a, p->stream, t); });
   if (rc == PME_OK)
     rc = timed(p, 1, [&](const spme::Timing& t) { return spme::launch_spread_x(a, p->stream, t); });
@@ -288,11 +298,14 @@ namespace {
 // summed either by the next launch of the step (fused = true) or by a
 // one-workgroup kernel right away.
 int solve_impl(pme_plan* p, double* ev, bool fused) {
-  if (p->state < kSpread) return PME_ESTATE;
+  // exactly once per spread: the convolution transforms the spectrum in
+  // place and moves the bucket counts on
+  if (p->state != kSpread) return PME_ESTATE;
   Args& a = p->cur;
   a.ev = ev;
   a.reduce_ev = 0;
   int rc = timed(p, 2, [&](const spme::Timing& t) { return spme::launch_conv(a, p->stream, t); });
+  if (rc != PME_OK) p->state = kDirty;
   if (rc != PME_OK) return rc;
   if (ev != nullptr) {
     if (fused)
@@ -306,20 +319,12 @@ int solve_impl(pme_plan* p, double* ev, bool fused) {
 }
 
 int gather_impl(pme_plan* p, double* forces, int accumulate) {
-  if (p->state < kSolved) return PME_ESTATE;
+  if (p->state != kSolved) return PME_ESTATE;
   Args& a = p->cur;
   if (a.N > 0 && forces == nullptr) return PME_EINVAL;
   a.forces = forces;
   a.accumulate = accumulate ? 1 : 0;
-  int rc;
-  if (p->fused_interp) {
-    rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_interp(a, p->stream, t); });
-  } else {
-    rc = timed(p, 3, [&](const spme::Timing& t) { return spme::launch_inv_x(a, p->stream, t); });
-    a.reduce_ev = 0;  // the energy/virial rows are summed once
-    if (rc == PME_OK)
-      rc = timed(p, 4, [&](const spme::Timing& t) { return spme::launch_gather(a, p->stream, t); });
-  }
+  int rc = timed(p, 3, [&](const spme::Timing& t) { return spme::launch_interp(a, p->stream, t); });
   a.reduce_ev = 0;
   if (rc == PME_OK && p->timing) p->timed_steps++;
   return rc;
@@ -411,21 +416,25 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     reps[g] = rep;
   }
   const spme::Timing none;
+  // plans whose last binning was not followed by a convolution
+  for (int i = 0; i < n; ++i) {
+    pme_plan* p = plans[i];
+    if (p->state == kSpread || p->state == kDirty) {
+      if (spme::launch_clear_counts(p->bound, s) != hipSuccess) return PME_EDEVICE;
+    }
+    p->state = kDirty;
+  }
   // stage by stage over the groups, all on one stream
   for (int stage = 0; stage < spme::kNumKernels; ++stage) {
     for (size_t g = 0; g < groups.size(); ++g) {
       const Args& a = reps[g];
       const spme::BatchArgs* bt = &bts[g];
       hipError_t e = hipSuccess;
-      const bool fused = plans[groups[g][0]]->fused_interp;
       switch (stage) {
         case 0: e = spme::launch_bin(a, s, none, bt); break;
         case 1: e = spme::launch_spread_x(a, s, none, bt); break;
         case 2: e = spme::launch_conv(a, s, none, bt); break;
-        case 3: e = fused ? hipSuccess : spme::launch_inv_x(a, s, none, bt); break;
-        default:
-          e = fused ? spme::launch_interp(a, s, none, bt) : spme::launch_gather(a, s, none, bt);
-          break;
+        default: e = spme::launch_interp(a, s, none, bt); break;
       }
       if (e != hipSuccess) return PME_EDEVICE;
     }
@@ -496,10 +505,9 @@ int pme_check(pme_plan* p, unsigned* flags) {
   *flags = f;
   if (f & PME_FLAG_NONFINITE) return PME_ENONFINITE;
   if (f & PME_FLAG_OVERFLOW) return PME_EOVERFLOW;
+  if (f & PME_FLAG_BUCKETS) return PME_ESTATE;
   return PME_OK;
 }
-
-int pme_interp_fused(const pme_plan* p) { return p == nullptr ? -1 : p->fused_interp; }
 
 int pme_kernel_timing(pme_plan* p, int enable) {
   if (p == nullptr) return PME_EINVAL;

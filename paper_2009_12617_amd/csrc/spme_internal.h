@@ -7,24 +7,28 @@
 
 namespace spme {
 
-constexpr int kChunk = 1024;         // atoms per binning workgroup (one sorted chunk)
+constexpr int kChunk = 1024;         // atoms per binning workgroup
 constexpr int kBinThreads = 1024;    // one atom per thread
-constexpr int kMaxBins = 1024;       // (z, y slice, head/body) bins per chunk: 2 K nq <= 1024
-constexpr int kItemMap = 4096;       // items per window of the spreading item map
-constexpr int kSegPerThread = 4;     // spreading segments described per thread per batch
+constexpr int kMaxBins = 2048;       // (z, y slice, head/body) bins: 2 K nq <= 2048
 constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
-constexpr int kPlaneThreads = 512;   // one z-plane per workgroup
+constexpr int kPlaneThreads = 512;   // one z-plane per workgroup (debug potential copy)
 constexpr int kInterpThreads = 512;  // one (z-plane, y slice) bin per workgroup
-constexpr int kInterpItems = 2048;   // atoms per window of the interpolation item list
-constexpr int kGatherThreads = 256;  // one atom per thread
 constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int kNumKernels = 5;       // bin, spread+x, yz convolution, inverse x, interpolation
+constexpr int kNumKernels = 4;       // bin, spread+x, yz convolution, inverse x + interpolation
 
-// y slices per z-plane in the spreading pass (rows per slice >= 8 > p - 1,
-// so an atom's support reaches at most one slice below its own).
-__host__ __device__ constexpr int nq_of(int K) { return K >= 32 ? 4 : K / 8; }
+// y slices per z-plane (rows per slice >= 8 > p - 1, so an atom's support
+// reaches at most one slice below its own); FP64 at K = 128 uses narrower
+// slices so that the interpolation tile fits in LDS.
+__host__ __device__ constexpr int nq_of(int K, bool fixed) {
+  return (!fixed && K == 128) ? 8 : K >= 32 ? 4 : K / 8;
+}
 __host__ __device__ constexpr int phi_pitch_of(int K, int order) {
   return (K + order - 1 + 3) / 4 * 4;
+}
+// Records per bucket: twice the mean number of atoms per (z, slice) plus a
+// margin; fuller buckets spill to the overflow list.
+__host__ __device__ constexpr int bucket_cap(int K, int nq, int max_atoms) {
+  return (int)(((2 * (long long)max_atoms / (K * nq) + 64 + 31) / 32) * 32);
 }
 
 // Sorted atom record of the FP32/fixed path (32 bytes): packed base grid
@@ -52,10 +56,12 @@ struct Layout {
   size_t ctrl;     // unsigned[64]: [0] sticky flags
   size_t bsq;      // double[3][K]: squared B-spline moduli per axis
   size_t tw;       // complex[K]: exp(-2 pi i k/K), float2 or double2
-  size_t cnt;      // int2[n_chunks][2 K nq]: (count, offset within the chunk) of the
-                   // atoms of chunk c in bin (z, y slice, head/body)
+  size_t bcnt;     // unsigned[2 K nq]: atoms binned so far per bucket (zero between steps)
+  size_t bcnt2;    // unsigned[2 K nq]: this step's counts, kept for the interpolation
+  size_t ovf;      // unsigned[4]: [0] overflow records so far, [1] this step's, kept
   size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
-  size_t rec;      // records [n_chunks * kChunk] (RecF or RecD)
+  size_t rec;      // records [2 K nq][cap] (RecF or RecD): one bucket per bin
+  size_t orec;     // records [max_atoms]: atoms that found their bucket full
   size_t spec;     // complex[K/2+1][K][K] half spectrum, columns [x'][z][y]
   size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
   size_t partial;  // double[conv_blocks][8]: energy/virial partial sums
@@ -63,6 +69,8 @@ struct Layout {
   size_t args;     // Args: device copy of the bound step arguments (batched runs)
   size_t total;
   int n_chunks_max;
+  int cap;          // records per bucket
+  int orec_max;     // overflow records (max_atoms)
   int conv_blocks;  // K/2+1 columns, one partial row each
   int phi_pitch;
 };
@@ -112,11 +120,7 @@ hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t = Timing()
                         const BatchArgs* bt = nullptr);
 hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t = Timing(),
                          const BatchArgs* bt = nullptr);
-hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t = Timing(),
-                         const BatchArgs* bt = nullptr);
-// Whether the inverse x transform and interpolation run as one launch
-// (k_interp) for these parameters, or as k_inv_x + k_gather.
-bool interp_is_fused(int K, int order, int precision);
+hipError_t launch_clear_counts(const Args& a, hipStream_t s);
 hipError_t launch_clear_flags(const Args& a, hipStream_t s);
 
 }  // namespace spme

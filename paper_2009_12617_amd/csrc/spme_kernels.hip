@@ -2,9 +2,9 @@
 //
 // One step is four launches on one stream:
 //   k_bin       fractional coordinates, base grid index and offsets of each
-//               atom; a per-chunk counting sort of the atoms by (base z,
-//               y slice, head/body) -- the GPU counterpart of the paper's
-//               atom reordering for hazard suppression (§III.A.1, §V.C)
+//               atom; the atoms are put into buckets by (base z, y slice,
+//               head/body) -- the GPU counterpart of the paper's atom
+//               reordering for hazard suppression (§III.A.1, §V.C)
 //   k_spread_x  one y slice of one z-plane per workgroup: every atom whose
 //               support covers the slice adds its contributions into an LDS
 //               tile in 64-bit fixed point (integer adds commute, so the grid
@@ -13,17 +13,17 @@
 //               stored as columns [x'][z][y] of the half spectrum
 //   k_conv      one x' column per workgroup: y and z transforms, the
 //               influence function with FP64 energy and virial partials,
-//               inverse z and y transforms (§III.A.2)
+//               inverse z and y transforms (§III.A.2); one extra workgroup
+//               keeps the bucket counts for k_interp and clears them
 //   k_interp    one (z-plane, y-slice) bin per workgroup: complex-to-real x
 //               transforms of the p planes and p-1+R rows that the bin's
 //               atoms touch, then force interpolation from LDS, forces
 //               scattered back to the caller's atom order (§III.A.3); one
 //               extra workgroup adds the energy/virial partial rows
-// Where the interpolation tile does not fit in LDS (FP64, K = 128, p = 6) the
-// last launch is split into k_inv_x (potential rows into the workspace) and
-// k_gather (one atom per thread).  The paper's two all-to-all corner turns
-// (§III.A.2, §IV.C) become the column layout of the half spectrum: each
-// column holds every y and z of one x', so both turns happen inside k_conv.
+// The paper's two all-to-all corner turns (§III.A.2, §IV.C) become the
+// column layout of the half spectrum: each column holds every y and z of one
+// x', so both turns happen inside k_conv.  k_inv_x (debug copies only)
+// writes the potential rows to the workspace.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
@@ -94,32 +94,6 @@ __device__ __forceinline__ T pick(const T* a, int i) {
   return v;
 }
 
-// Exclusive prefix sum over the block; wsum needs 32 ints.  Every thread
-// must call it; the caller synchronises before reusing wsum.
-__device__ int block_exclusive_scan(int v, int* wsum, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[wave] = x;
-  __syncthreads();
-  if (wave == 0) {
-    int w = (lane < nw) ? wsum[lane] : 0;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-      const int y = __shfl_up(w, d, 64);
-      if (lane >= d) w += y;
-    }
-    if (lane < nw) wsum[16 + lane] = w;
-  }
-  __syncthreads();
-  *total = wsum[16 + nw - 1];
-  return (wave > 0 ? wsum[16 + wave - 1] : 0) + x - v;
-}
-
 // One DPP move of a double within the wavefront (each half moved with the
 // same control); lanes without a source, or outside row_mask, read 0.0.
 template <int CTRL, int ROW_MASK>
@@ -174,7 +148,14 @@ __device__ __forceinline__ void block_sums(double* v, double* wred) {
 }
 
 // ---------------------------------------------------------------------------
-// k_bin: one chunk of kChunk atoms per workgroup.
+// k_bin: one chunk of kChunk atoms per workgroup, one atom per thread.  Each
+// atom goes to the bucket of its bin (base z, y slice, head/body); a bucket
+// is a fixed run of `cap` records.  The chunk counts its atoms per bin in
+// LDS, reserves that many slots of each bucket with one global add, and
+// writes its records there; atoms beyond a full bucket go to the overflow
+// list, which every consumer also scans.  The order of records inside a
+// bucket varies from run to run; nothing downstream depends on it (the grid
+// is an order-free integer sum, forces are per atom).
 // ---------------------------------------------------------------------------
 template <class P, bool BATCH>
 __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
@@ -183,19 +164,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   using Rec = typename P::rec;
   using T = typename P::real;
   __shared__ int hist[kMaxBins];
-  __shared__ int wsum[32];
   __shared__ double wred[16 * 8];
   TRACE(0, 0);
-  const int K = a.K, nq = nq_of(a.K), rows = K / nq, nbins = 2 * K * nq;
+  const int K = a.K, nq = nq_of(a.K, P::fixed), rows = K / nq, nbins = 2 * K * nq;
+  const int cap = a.lay.cap;
   const int c = blockIdx.x, tid = threadIdx.x;
-  int2* cnt = reinterpret_cast<int2*>(a.ws + a.lay.cnt) + (size_t)c * nbins;
-  Rec* rec = reinterpret_cast<Rec*>(a.ws + a.lay.rec) + (size_t)c * kChunk;
+  unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
+  unsigned* ovf = reinterpret_cast<unsigned*>(a.ws + a.lay.ovf);
+  Rec* rec = reinterpret_cast<Rec*>(a.ws + a.lay.rec);
+  Rec* orec = reinterpret_cast<Rec*>(a.ws + a.lay.orec);
   unsigned* flags = reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl);
   for (int b = tid; b < nbins; b += kBinThreads) hist[b] = 0;
   __syncthreads();
   TRACE(0, 1);
 
-  // one atom per thread
   const int i = c * kChunk + tid;
   Rec r;
   int bin = -1, rank = 0;
@@ -226,19 +208,28 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
     bin = (g[2] * nq + sl) * 2 + ((g[1] - sl * rows) >= a.order - 1 ? 1 : 0);
     rank = atomicAdd(&hist[bin], 1);
   }
-  // sum |q| of the chunk (fixed-point headroom), before any global store so
-  // that the barriers below do not wait on outstanding writes
+  // sum |q| of the chunk (fixed-point headroom); its barrier also completes
+  // the histogram
   block_sums<1>(v, wred);
   TRACE(0, 2);
-  // exclusive scan of the bin counts, one bin per thread
-  const int h = (tid < nbins) ? hist[tid] : 0;
-  int total;
-  const int ex = block_exclusive_scan(h, wsum, &total);
-  if (tid < nbins) hist[tid] = ex;  // own slot: read above by this thread only
+  for (int b = tid; b < nbins; b += kBinThreads) {
+    const int h = hist[b];
+    if (h > 0) hist[b] = (int)atomicAdd(&bcnt[b], (unsigned)h);
+  }
   __syncthreads();
   TRACE(0, 3);
-  if (bin >= 0) rec[hist[bin] + rank] = r;
-  if (tid < nbins) cnt[tid] = make_int2(h, ex);
+  if (bin >= 0) {
+    const int slot = hist[bin] + rank;
+    if (slot < cap) {
+      rec[(size_t)bin * cap + slot] = r;
+    } else {
+      const unsigned o = atomicAdd(&ovf[0], 1u);
+      if (o < (unsigned)a.lay.orec_max)
+        orec[o] = r;
+      else  // counts left over from a step that never reached its convolution
+        atomicOr(flags, PME_FLAG_BUCKETS);
+    }
+  }
   if (tid == 15) reinterpret_cast<double*>(a.ws + a.lay.absq)[c] = v[0];
   TRACE(0, 15);
 }
@@ -249,10 +240,57 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
 // ---------------------------------------------------------------------------
 template <class P, int K>
 __host__ __device__ constexpr size_t spread_lds_bytes() {
-  return (size_t)(K / nq_of(K)) * tile_pitch<P>(K) * 8 +
-         (size_t)K * sizeof(cplx<typename P::real>) +
-         (size_t)(2 * kSegPerThread * kSpreadThreads + 2 + 32) * sizeof(int) +
-         kItemMap * sizeof(unsigned short);
+  return (size_t)(K / nq_of(K, P::fixed)) * tile_pitch<P>(K) * 8 +
+         (size_t)K * sizeof(cplx<typename P::real>) + 64 * sizeof(int);
+}
+
+// Contributions of one atom to the plane of support point jz (z order) of
+// the tile holding rows y0 .. y0+R-1: its p x p (y, x) points in the slice,
+// in the product order z, y, x; fixed point: rounded to integers and added
+// with 64-bit LDS atomics.
+template <class P, int K, int ORDER, int R, int PITCH>
+__device__ __forceinline__ void spread_atom(typename P::acc* tile, const typename P::rec& r, int jz,
+                                            int y0, double scale) {
+  using T = typename P::real;
+  using Acc = typename P::acc;
+  const int gx = r.g & 1023, gy = (r.g >> 10) & 1023;
+  T tx[ORDER], ty[ORDER], tz[ORDER];
+  bspline<ORDER>(r.w[0], tx, (T*)nullptr);
+  bspline<ORDER>(r.w[1], ty, (T*)nullptr);
+  bspline<ORDER>(r.w[2], tz, (T*)nullptr);
+  int xs[ORDER];
+#pragma unroll
+  for (int jx = 0; jx < ORDER; ++jx) {
+    const int x = gx - ORDER + 1 + jx;
+    xs[jx] = x < 0 ? x + K : x;
+  }
+  if constexpr (P::fixed) {
+#pragma clang fp contract(off)
+    const float cz = r.q * pick<ORDER>(tz, jz);
+#pragma unroll
+    for (int jy = 0; jy < ORDER; ++jy) {
+      int dy = gy - ORDER + 1 + jy - y0;
+      if (dy < 0) dy += K;
+      if (dy >= R) continue;
+      Acc* row = tile + dy * PITCH;
+      const float cy = cz * ty[jy];
+#pragma unroll
+      for (int jx = 0; jx < ORDER; ++jx)
+        atomicAdd(&row[xs[jx]], (unsigned long long)to_fixed(cy * tx[jx], scale));
+    }
+  } else {
+    const double cz = r.q * pick<ORDER>(tz, jz);
+#pragma unroll
+    for (int jy = 0; jy < ORDER; ++jy) {
+      int dy = gy - ORDER + 1 + jy - y0;
+      if (dy < 0) dy += K;
+      if (dy >= R) continue;
+      Acc* row = tile + dy * PITCH;
+      const double cy = cz * ty[jy];
+#pragma unroll
+      for (int jx = 0; jx < ORDER; ++jx) atomicAdd(&row[xs[jx]], cy * tx[jx]);
+    }
+  }
 }
 
 template <class P, int K, int ORDER, bool BATCH>
@@ -262,158 +300,105 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   using Acc = typename P::acc;
   using Rec = typename P::rec;
   constexpr int M = K / 2, KH = K / 2 + 1;
-  constexpr int NQ = nq_of(K), R = K / NQ;
+  constexpr int NQ = nq_of(K, P::fixed), R = K / NQ;
   constexpr int PITCH = tile_pitch<P>(K);
+  constexpr int NBK = 3 * ORDER;  // buckets read per tile
   extern __shared__ __align__(16) unsigned char smem[];
   Acc* tile = reinterpret_cast<Acc*>(smem);
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + (size_t)R * PITCH * 8);
-  int* segpre = reinterpret_cast<int*>(tw + K);
-  int* segbeg = segpre + kSegPerThread * kSpreadThreads + 2;
-  int* wsum = segbeg + kSegPerThread * kSpreadThreads;
-  unsigned short* imap = reinterpret_cast<unsigned short*>(wsum + 32);
+  int* bk_pre = reinterpret_cast<int*>(tw + K);  // [NBK + 1] item offsets
+  int* bk_base = bk_pre + 24;                     // [NBK] first record
+  int* bk_n = bk_base + 20;                       // [NBK] counts, then the overflow count
 
   TRACE(1, 0);
   static_assert((K * NQ) % kXcds == 0, "spreading tiles do not split over the XCDs");
   const int tile_id = xcd_local(blockIdx.x, K * NQ);
   const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
   const int tid = threadIdx.x;
+  const int cap = a.lay.cap;
+  const unsigned* bcnt = reinterpret_cast<const unsigned*>(a.ws + a.lay.bcnt);
+  const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
+  const Rec* orec = reinterpret_cast<const Rec*>(a.ws + a.lay.orec);
+  // The tile (rows y0 .. y0+R-1 of plane z) receives the atoms whose base z
+  // index b lies in z .. z+p-1 (mod K) -- for b = z + j the plane is support
+  // point jz = p-1-j -- and whose base y index lies in this slice, or in the
+  // head (first p-1 rows) of the next slice: an atom touches rows
+  // g_y-p+1 .. g_y.  Bucket k = 3j + d: d = 0 own head, 1 own body, 2 next
+  // slice's head.
+  if (tid < NBK) {
+    const int j = tid / 3, d = tid - 3 * j;
+    int bz = z + j;
+    if (bz >= K) bz -= K;
+    int by = qs + (d == 2 ? 1 : 0);
+    if (by >= NQ) by -= NQ;
+    const int b = (bz * NQ + by) * 2 + (d == 1 ? 1 : 0);
+    bk_n[tid] = min((int)bcnt[b], cap);
+    bk_base[tid] = b * cap;
+  } else if (tid == NBK) {
+    bk_n[NBK] = (int)min(reinterpret_cast<const unsigned*>(a.ws + a.lay.ovf)[0],
+                         (unsigned)a.lay.orec_max);
+  }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   for (int i = tid; i < K; i += kSpreadThreads) tw[i] = twg[i];
   for (int i = tid; i < R * PITCH; i += kSpreadThreads) tile[i] = Acc(0);
-  const int2* cnt = reinterpret_cast<const int2*>(a.ws + a.lay.cnt);
-  const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
   const double scale = ldexp(1.0, a.frac_bits);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int k = 0; k < NBK; ++k) {
+      bk_pre[k] = run;
+      run += bk_n[k];
+    }
+    bk_pre[NBK] = run;
+  }
   __syncthreads();
   TRACE(1, 1);
 
-  // --- spreading.  The tile (rows y0 .. y0+R-1 of plane z) receives the
-  // atoms whose base z index b lies in z .. z+p-1 (mod K) -- for b = z + j
-  // the plane is support point jz = p-1-j -- and whose base y index lies in
-  // this slice, or in the head (first p-1 rows) of the next slice: an atom
-  // touches rows g_y-p+1 .. g_y.  A segment is the run of one such bin
-  // (z, slice, head/body) inside one sorted chunk; segments are taken
-  // kSpreadThreads at a time and their items are numbered consecutively.  An
-  // LDS map gives each item's segment; each thread then owns kItems items per
-  // pass so that their record loads overlap.
+  // items: the records of the buckets one after another; kItems per thread
+  // per pass so that their loads overlap
   constexpr int kItems = 4;
-  constexpr int NB = 2 * K * NQ;
-  constexpr int SPJ = 3;  // segments per (chunk, j): own head, own body, next head
-  constexpr int SPT = kSegPerThread;
-  const int nseg = a.n_chunks * ORDER * SPJ;
-  for (int s0 = 0; s0 < nseg; s0 += SPT * kSpreadThreads) {
-    const int ns = min(SPT * kSpreadThreads, nseg - s0);
-    // each thread describes SPT consecutive segments
-    int len[SPT], beg[SPT], mine = 0;
+  const int total = bk_pre[NBK];
+  int pre[NBK + 1];
 #pragma unroll
-    for (int k = 0; k < SPT; ++k) {
-      const int sl = tid * SPT + k;
-      len[k] = 0;
-      beg[k] = 0;
-      if (sl < ns) {
-        const int seg = s0 + sl;
-        const int c = seg / (SPJ * ORDER), rem = seg - c * SPJ * ORDER;
-        const int j = rem / SPJ, d = rem - j * SPJ;
-        int bz = z + j;
-        if (bz >= K) bz -= K;
-        int by = qs + (d == 2 ? 1 : 0);
-        if (by >= NQ) by -= NQ;
-        const int2 v = cnt[(size_t)c * NB + (bz * NQ + by) * 2 + (d == 1 ? 1 : 0)];
-        len[k] = v.x;
-        beg[k] = c * kChunk + v.y;
-      }
-      mine += len[k];
-    }
-    int total;
-    const int ex = block_exclusive_scan(mine, wsum, &total);
-    int pre[SPT];
-    {
-      int run = ex;
+  for (int k = 0; k <= NBK; ++k) pre[k] = bk_pre[k];
+  for (int it = 0; it < total; it += kItems * kSpreadThreads) {
+    int idx[kItems], jz[kItems];
 #pragma unroll
-      for (int k = 0; k < SPT; ++k) {
-        const int sl = tid * SPT + k;
-        pre[k] = run;
-        if (sl < ns) {
-          segpre[sl] = run;
-          segbeg[sl] = beg[k];
-        }
-        run += len[k];
+    for (int u = 0; u < kItems; ++u) {
+      const int t = it + u * kSpreadThreads + tid;
+      jz[u] = -1;
+      idx[u] = 0;
+      if (t < total) {
+        int k = 0;
+#pragma unroll
+        for (int kk = 1; kk < NBK; ++kk) k += (t >= pre[kk]) ? 1 : 0;
+        idx[u] = bk_base[k] + (t - bk_pre[k]);
+        jz[u] = ORDER - 1 - k / 3;
       }
     }
-    if (tid == 0) segpre[ns] = total;
-    TRACE(1, 4);
-    for (int w0 = 0; w0 < total; w0 += kItemMap) {
-      const int wn = min(kItemMap, total - w0);
-      // map the items of this window to their segments
+    Rec r[kItems];
 #pragma unroll
-      for (int k = 0; k < SPT; ++k) {
-        const int lo = max(pre[k], w0), hi = min(pre[k] + len[k], w0 + wn);
-        for (int t = lo; t < hi; ++t) imap[t - w0] = (unsigned short)(tid * SPT + k);
-      }
-      __syncthreads();
-      TRACE(1, 5);
-      for (int it = 0; it < wn; it += kItems * kSpreadThreads) {
-        int idx[kItems], jz[kItems];
+    for (int u = 0; u < kItems; ++u)
+      if (jz[u] >= 0) r[u] = rec[idx[u]];
 #pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          const int t = it + u * kSpreadThreads + tid;
-          jz[u] = -1;
-          idx[u] = 0;
-          if (t < wn) {
-            const int sg = imap[t];
-            idx[u] = segbeg[sg] + (w0 + t - segpre[sg]);
-            jz[u] = ORDER - 1 - ((s0 + sg) % (SPJ * ORDER)) / SPJ;
-          }
-        }
-        Rec r[kItems];
-#pragma unroll
-        for (int u = 0; u < kItems; ++u)
-          if (jz[u] >= 0) r[u] = rec[idx[u]];
-#pragma unroll
-        for (int u = 0; u < kItems; ++u) {
-          if (jz[u] < 0) continue;
-          const int gx = r[u].g & 1023, gy = (r[u].g >> 10) & 1023;
-          T tx[ORDER], ty[ORDER], tz[ORDER];
-          bspline<ORDER>(r[u].w[0], tx, (T*)nullptr);
-          bspline<ORDER>(r[u].w[1], ty, (T*)nullptr);
-          bspline<ORDER>(r[u].w[2], tz, (T*)nullptr);
-          int xs[ORDER];
-#pragma unroll
-          for (int jx = 0; jx < ORDER; ++jx) {
-            const int x = gx - ORDER + 1 + jx;
-            xs[jx] = x < 0 ? x + K : x;
-          }
-          if constexpr (P::fixed) {
-#pragma clang fp contract(off)
-            const float cz = r[u].q * pick<ORDER>(tz, jz[u]);  // product order z, y, x
-#pragma unroll
-            for (int jy = 0; jy < ORDER; ++jy) {
-              int dy = gy - ORDER + 1 + jy - y0;
-              if (dy < 0) dy += K;
-              if (dy >= R) continue;
-              Acc* row = tile + dy * PITCH;
-              const float cy = cz * ty[jy];
-#pragma unroll
-              for (int jx = 0; jx < ORDER; ++jx)
-                atomicAdd(&row[xs[jx]], (unsigned long long)to_fixed(cy * tx[jx], scale));
-            }
-          } else {
-            const double cz = r[u].q * pick<ORDER>(tz, jz[u]);
-#pragma unroll
-            for (int jy = 0; jy < ORDER; ++jy) {
-              int dy = gy - ORDER + 1 + jy - y0;
-              if (dy < 0) dy += K;
-              if (dy >= R) continue;
-              Acc* row = tile + dy * PITCH;
-              const double cy = cz * ty[jy];
-#pragma unroll
-              for (int jx = 0; jx < ORDER; ++jx) atomicAdd(&row[xs[jx]], cy * tx[jx]);
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
+    for (int u = 0; u < kItems; ++u)
+      if (jz[u] >= 0) spread_atom<P, K, ORDER, R, PITCH>(tile, r[u], jz[u], y0, scale);
   }
+  // atoms of full buckets: the whole overflow list, each atom taken if it
+  // belongs to this tile
+  const int novf = bk_n[NBK];
+  for (int o = tid; o < novf; o += kSpreadThreads) {
+    const Rec r = orec[o];
+    const int gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
+    int j = gz - z;
+    if (j < 0) j += K;
+    const int sl = gy / R;
+    int nsl = qs + 1;
+    if (nsl >= NQ) nsl -= NQ;
+    if (j < ORDER && (sl == qs || (sl == nsl && gy - sl * R < ORDER - 1)))
+      spread_atom<P, K, ORDER, R, PITCH>(tile, r, ORDER - 1 - j, y0, scale);
+  }
+  __syncthreads();
   TRACE(1, 2);
 
   if (a.keep_grid) {
@@ -536,15 +521,31 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   TRACE(2, 0);
   const int tid = threadIdx.x;
   if (blockIdx.x == KH) {
-    // the extra workgroup (fixed point only): sum |q| 2^F must stay below
-    // 2^51 so that every contribution and grid value is exact in FP64 and the
-    // rounding of to_fixed holds
-    const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
-    double v[1] = {0.0};
-    for (int c = tid; c < a.n_chunks; c += NT) v[0] += absq[c];
-    block_sums<1>(v, wred);
-    if (tid == 15 && v[0] * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
-      atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
+    // the extra workgroup: keeps the bucket counts of this step for the
+    // interpolation pass and clears them (and the overflow count) for the
+    // next step's binning
+    unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
+    unsigned* bcnt2 = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt2);
+    unsigned* ovf = reinterpret_cast<unsigned*>(a.ws + a.lay.ovf);
+    constexpr int NBINS = 2 * K * nq_of(K, P::fixed);
+    for (int b = tid; b < NBINS; b += NT) {
+      bcnt2[b] = bcnt[b];
+      bcnt[b] = 0u;
+    }
+    if (tid == 0) {
+      ovf[1] = ovf[0];
+      ovf[0] = 0u;
+    }
+    if constexpr (P::fixed) {
+      // sum |q| 2^F must stay below 2^51 so that every contribution and grid
+      // value is exact in FP64 and the rounding of to_fixed holds
+      const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
+      double v[1] = {0.0};
+      for (int c = tid; c < a.n_chunks; c += NT) v[0] += absq[c];
+      block_sums<1>(v, wred);
+      if (tid == 15 && v[0] * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
+        atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
+    }
     return;
   }
   const int xp = blockIdx.x;  // m1
@@ -740,12 +741,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K * PC;
-  TRACE(3, 0);
   const int tid = threadIdx.x;
-  if (blockIdx.x == K) {
-    if (a.reduce_ev) reduce_ev(a);
-    return;
-  }
   const int z = xcd_local(blockIdx.x, K);
   const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
   for (int i = tid; i < KH * K; i += kPlaneThreads) {
@@ -771,7 +767,6 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
     if (x >= K) x -= K;
     phi[i] = reinterpret_cast<const T*>(pl + y * PC)[x];
   }
-  TRACE(3, 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,18 +774,15 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
 // atoms of one (z-plane, y-slice) bin per workgroup (§III.A.3).  The
 // workgroup transforms the p planes z-p+1 .. z, rows y0-p+1 .. y0+R-1, of
 // the spectrum into LDS -- the potential every atom of the bin reads -- and
-// interpolates those atoms from LDS, one per thread.  The arithmetic per atom
-// is that of k_gather.
+// interpolates those atoms from LDS, one per thread; forces go to the
+// caller's atom order.
 // ---------------------------------------------------------------------------
 template <class P, int K, int ORDER>
 __host__ __device__ constexpr size_t interp_lds_bytes() {
-  constexpr size_t R = K / nq_of(K), NROW = (size_t)ORDER * (R + ORDER - 1), PC = K / 2 + 2;
+  constexpr size_t R = K / nq_of(K, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
+  constexpr size_t PC = K / 2 + 2;
   return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)K * sizeof(cplx<typename P::real>) +
-         (size_t)(kInterpItems + 32) * sizeof(int);
-}
-template <class P, int K, int ORDER>
-__host__ __device__ constexpr bool interp_fused() {
-  return interp_lds_bytes<P, K, ORDER>() <= kMaxLds;
+         4 * sizeof(int);
 }
 
 // Force on one atom from the potential: rows(jz, jy) points at the potential
@@ -798,8 +790,8 @@ __host__ __device__ constexpr bool interp_fused() {
 template <class P, int ORDER, class Rows>
 __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec& r, Rows rows,
                                             const int* xs, int K) {
-  const double qi = r.qd;
   using T = typename P::real;
+  const double qi = r.qd;
   T thx[ORDER], thy[ORDER], thz[ORDER], dthx[ORDER], dthy[ORDER], dthz[ORDER];
   bspline<ORDER>(r.w[0], thx, dthx);
   bspline<ORDER>(r.w[1], thy, dthy);
@@ -839,146 +831,103 @@ __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec
 
 template <class P, int K, int ORDER, bool BATCH>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs bt) {
-  if constexpr (interp_fused<P, K, ORDER>()) {
-    const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
-    using T = typename P::real;
-    using Rec = typename P::rec;
-    constexpr int M = K / 2, KH = M + 1, PC = KH + 1;
-    constexpr int NQ = nq_of(K), R = K / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
-    constexpr int NB = 2 * K * NQ;
-    constexpr int NT = kInterpThreads;
-    extern __shared__ __align__(16) unsigned char smem[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-    cplx<T>* tw = buf + NROW * PC;
-    int* list = reinterpret_cast<int*>(tw + K);
-    int* wsum = list + kInterpItems;
-    TRACE(4, 0);
-    const int tid = threadIdx.x;
-    if (blockIdx.x == K * NQ) {
-      if (a.reduce_ev) reduce_ev(a);
-      return;
-    }
-    if (a.N == 0) return;
-    static_assert((K * NQ) % kXcds == 0, "interpolation tiles do not split over the XCDs");
-    const int tile_id = xcd_local(blockIdx.x, K * NQ);
-    const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
-    const int2* cnt = reinterpret_cast<const int2*>(a.ws + a.lay.cnt);
-    const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
-    const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
-    const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-    // the bin's atoms: bins (z, qs, head) and (z, qs, body) are adjacent, so
-    // in chunk c they are one run of records
-    const int b0 = (z * NQ + qs) * 2;
-    int2 dh = {0, 0}, db = {0, 0};
-    if (tid < a.n_chunks) {
-      dh = cnt[(size_t)tid * NB + b0];
-      db = cnt[(size_t)tid * NB + b0 + 1];
-    }
-    // spectrum rows (jz, r): plane z-p+1+jz, row y0-p+1+r, all x'
-    constexpr int NE = KH * NROW;
-#pragma unroll 4
-    for (int e = tid; e < NE; e += NT) {
-      const int r = e % RR, t2 = e / RR, jz = t2 % ORDER, x = t2 / ORDER;
-      int zz = z - ORDER + 1 + jz, yy = y0 - ORDER + 1 + r;
-      if (zz < 0) zz += K;
-      if (yy < 0) yy += K;
-      buf[(jz * RR + r) * PC + x] = spec[((size_t)x * K + zz) * K + yy];
-    }
-    if (tid < K) tw[tid] = twg[tid];
-    TRACE(4, 1);
-
-    bool phi_ready = false;
-    for (int c0 = 0; c0 < a.n_chunks; c0 += NT) {
-      int len = 0, beg = 0;
-      if (c0 > 0 && c0 + tid < a.n_chunks) {
-        dh = cnt[(size_t)(c0 + tid) * NB + b0];
-        db = cnt[(size_t)(c0 + tid) * NB + b0 + 1];
-      }
-      if (c0 + tid < a.n_chunks) {
-        len = dh.x + db.x;
-        beg = (c0 + tid) * kChunk + dh.y;
-      }
-      int total;
-      const int pre = block_exclusive_scan(len, wsum, &total);
-      TRACE(4, 3);
-      for (int w0 = 0; w0 < total; w0 += kInterpItems) {
-        const int wn = min(kInterpItems, total - w0);
-        const int lo = max(pre, w0), hi = min(pre + len, w0 + wn);
-        for (int t = lo; t < hi; ++t) list[t - w0] = beg + (t - pre);
-        __syncthreads();
-        TRACE(4, 4);
-        // the first record loads are issued before the transforms
-        int it = tid;
-        Rec r;
-        if (it < wn) r = rec[list[it]];
-        if (!phi_ready) {
-          constexpr int TM = fft_lanes(M);
-          for (int task = tid; task < NROW * TM; task += NT) {
-            const int row = task / TM, l = task - row * TM;
-            c2r_pre<T, K>(buf + row * PC, l, tw);
-            fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
-          }
-          __syncthreads();
-          phi_ready = true;
-          TRACE(4, 2);
-        }
-        for (; it < wn; it += NT) {
-          Rec rn;
-          if (it + NT < wn) rn = rec[list[it + NT]];
-          const int gx = r.g & 1023, gy = (r.g >> 10) & 1023;
-          int xs[ORDER];
-#pragma unroll
-          for (int jx = 0; jx < ORDER; ++jx) {
-            const int x = gx - ORDER + 1 + jx;
-            xs[jx] = x < 0 ? x + K : x;
-          }
-          const int ry = gy - y0;
-          interpolate<P, ORDER>(
-              a, r,
-              [&](int jz, int jy) {
-                return reinterpret_cast<const T*>(buf + (jz * RR + ry + jy) * PC);
-              },
-              xs, K);
-          r = rn;
-        }
-        __syncthreads();
-      }
-      __syncthreads();  // wsum is reused by the next batch's scan
-    }
-    TRACE(4, 15);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_gather: force interpolation from the potential rows of the workspace, one
-// atom per thread in sorted order (§III.A.3).
-// ---------------------------------------------------------------------------
-template <class P, int K, int ORDER, bool BATCH>
-__global__ __launch_bounds__(kGatherThreads) void k_gather(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   using Rec = typename P::rec;
-  constexpr int PP = phi_pitch_of(K, ORDER);
-  TRACE(4, 0);
-  const int t = blockIdx.x * kGatherThreads + threadIdx.x;
-  if (t >= a.N) return;
-  const Rec r = reinterpret_cast<const Rec*>(a.ws + a.lay.rec)[t];
-  const T* phi = reinterpret_cast<const T*>(a.ws + a.lay.phi);
-  const int gx = r.g & 1023, gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
-  // rows carry a (p-1)-point halo in front: point jx of the support is gx + jx
-  int xs[ORDER];
+  constexpr int M = K / 2, KH = M + 1, PC = KH + 1;
+  constexpr int NQ = nq_of(K, P::fixed), R = K / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
+  constexpr int NT = kInterpThreads;
+  static_assert(interp_lds_bytes<P, K, ORDER>() <= kMaxLds, "interpolation tile does not fit in LDS");
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + NROW * PC;
+  int* nb = reinterpret_cast<int*>(tw + K);  // head count, body count, overflow count
+  TRACE(3, 0);
+  const int tid = threadIdx.x;
+  if (blockIdx.x == K * NQ) {
+    if (a.reduce_ev) reduce_ev(a);
+    return;
+  }
+  if (a.N == 0) return;
+  static_assert((K * NQ) % kXcds == 0, "interpolation tiles do not split over the XCDs");
+  const int tile_id = xcd_local(blockIdx.x, K * NQ);
+  const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
+  const int cap = a.lay.cap;
+  const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
+  const Rec* orec = reinterpret_cast<const Rec*>(a.ws + a.lay.orec);
+  const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+  // the bin's buckets (z, qs, head) and (z, qs, body), with the counts the
+  // convolution kept for this pass
+  const int b0 = (z * NQ + qs) * 2;
+  if (tid < 2)
+    nb[tid] = min((int)reinterpret_cast<const unsigned*>(a.ws + a.lay.bcnt2)[b0 + tid], cap);
+  else if (tid == 2)
+    nb[2] = (int)min(reinterpret_cast<const unsigned*>(a.ws + a.lay.ovf)[1],
+                     (unsigned)a.lay.orec_max);
+  // spectrum rows (jz, r): plane z-p+1+jz, row y0-p+1+r, all x'
+  constexpr int NE = KH * NROW;
+#pragma unroll 4
+  for (int e = tid; e < NE; e += NT) {
+    const int r = e % RR, t2 = e / RR, jz = t2 % ORDER, x = t2 / ORDER;
+    int zz = z - ORDER + 1 + jz, yy = y0 - ORDER + 1 + r;
+    if (zz < 0) zz += K;
+    if (yy < 0) yy += K;
+    buf[(jz * RR + r) * PC + x] = spec[((size_t)x * K + zz) * K + yy];
+  }
+  if (tid < K) tw[tid] = twg[tid];
+  __syncthreads();
+  TRACE(3, 1);
+  const int n0 = nb[0], total = n0 + nb[1], novf = nb[2];
+  if (total == 0 && novf == 0) return;
+  // the first record loads are issued before the transforms
+  Rec r;
+  if (tid < total) r = rec[tid < n0 ? (size_t)b0 * cap + tid : (size_t)(b0 + 1) * cap + (tid - n0)];
+  constexpr int TM = fft_lanes(M);
+  for (int task = tid; task < NROW * TM; task += NT) {
+    const int row = task / TM, l = task - row * TM;
+    c2r_pre<T, K>(buf + row * PC, l, tw);
+    fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
+  }
+  __syncthreads();
+  TRACE(3, 2);
+  auto gather = [&](const Rec& rr) {
+    const int gx = rr.g & 1023, gy = (rr.g >> 10) & 1023;
+    int xs[ORDER];
 #pragma unroll
-  for (int jx = 0; jx < ORDER; ++jx) xs[jx] = gx + jx;
-  interpolate<P, ORDER>(
-      a, r,
-      [&](int jz, int jy) {
-        int zz = gz - ORDER + 1 + jz, yy = gy - ORDER + 1 + jy;
-        if (zz < 0) zz += K;
-        if (yy < 0) yy += K;
-        return phi + ((size_t)zz * K + yy) * PP;
-      },
-      xs, K);
-  TRACE(4, 15);
+    for (int jx = 0; jx < ORDER; ++jx) {
+      const int x = gx - ORDER + 1 + jx;
+      xs[jx] = x < 0 ? x + K : x;
+    }
+    const int ry = gy - y0;
+    interpolate<P, ORDER>(
+        a, rr,
+        [&](int jz, int jy) { return reinterpret_cast<const T*>(buf + (jz * RR + ry + jy) * PC); },
+        xs, K);
+  };
+  for (int t = tid; t < total; t += NT) {
+    Rec rn;
+    const int tn = t + NT;
+    if (tn < total) rn = rec[tn < n0 ? (size_t)b0 * cap + tn : (size_t)(b0 + 1) * cap + (tn - n0)];
+    gather(r);
+    r = rn;
+  }
+  // atoms of full buckets: those of the overflow list that belong to this bin
+  for (int o = tid; o < novf; o += NT) {
+    const Rec ro = orec[o];
+    const int gy = (ro.g >> 10) & 1023, gz = (ro.g >> 20) & 1023;
+    if (gz == z && gy / R == qs) gather(ro);
+  }
+  TRACE(3, 15);
+}
+
+// Clears the bucket and overflow counts of a step whose binning ran without
+// its convolution (one workgroup).
+__global__ void k_clear_counts(Args a) {
+  unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
+  const int nbins = 2 * a.K * nq_of(a.K, a.precision == PME_FP32_FIXED);
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) bcnt[b] = 0u;
+  if (threadIdx.x == 0) reinterpret_cast<unsigned*>(a.ws + a.lay.ovf)[0] = 0u;
 }
 
 __global__ void k_clear_flags(unsigned* ctrl) {
@@ -1055,15 +1004,21 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   const size_t real = fx ? 4 : 8, cpx = 2 * real;
   const size_t kh = (size_t)K / 2 + 1;
   const int nch = (max_atoms + kChunk - 1) / kChunk;
-  const size_t nbins = 2 * (size_t)K * nq_of(K);
+  const size_t nbins = 2 * (size_t)K * nq_of(K, fx);
+  const size_t rsz = fx ? sizeof(RecF) : sizeof(RecD);
   Layout L{};
   size_t o = 0;
   L.ctrl = o;      o = align256(o + 64 * sizeof(unsigned));
   L.bsq = o;       o = align256(o + 3 * (size_t)K * sizeof(double));
   L.tw = o;        o = align256(o + (size_t)K * cpx);
-  L.cnt = o;       o = align256(o + (size_t)nch * nbins * 2 * sizeof(int));
+  L.bcnt = o;      o = align256(o + nbins * sizeof(unsigned));
+  L.bcnt2 = o;     o = align256(o + nbins * sizeof(unsigned));
+  L.ovf = o;       o = align256(o + 4 * sizeof(unsigned));
   L.absq = o;      o = align256(o + (size_t)nch * sizeof(double));
-  L.rec = o;       o = align256(o + (size_t)nch * kChunk * (fx ? sizeof(RecF) : sizeof(RecD)));
+  L.cap = bucket_cap(K, nq_of(K, fx), max_atoms);
+  L.rec = o;       o = align256(o + nbins * (size_t)L.cap * rsz);
+  L.orec = o;      o = align256(o + (size_t)max_atoms * rsz);
+  L.orec_max = max_atoms;
   L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
   L.phi_pitch = phi_pitch_of(K, order);
   L.phi = o;       o = align256(o + (size_t)K * K * L.phi_pitch * real);
@@ -1086,7 +1041,7 @@ hipError_t raise_lds_limits() {
     e = hipFuncSetAttribute((const void*)k_conv<P, KK, B>, attr, (int)conv_lds_bytes<P, KK>());
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_inv_x<P, KK, O, B>, attr, (int)inv_x_lds_bytes<P, KK>());
-  if (e == hipSuccess && interp_fused<P, KK, O>())
+  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_interp<P, KK, O, B>, attr,
                             (int)interp_lds_bytes<P, KK, O>());
   return e;
@@ -1104,22 +1059,6 @@ hipError_t prepare_kernels(int K, int order, int precision) {
       });
     });
   });
-}
-
-bool interp_is_fused(int K, int order, int precision) {
-  bool fused = false;
-  (void)with_prec(precision, [&](auto pt) {
-    using P = decltype(pt);
-    return with_K(K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
-      return with_order(order, [&](auto oc) {
-        constexpr int O = decltype(oc)::value;
-        fused = interp_fused<P, KK, O>();
-        return hipSuccess;
-      });
-    });
-  });
-  return fused;
 }
 
 template <class F>
@@ -1148,7 +1087,7 @@ hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t, const 
         constexpr int O = decltype(oc)::value;
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
-          return launch(k_spread_x<P, KK, O, B>, dim3(KK * nq_of(KK)), dim3(kSpreadThreads),
+          return launch(k_spread_x<P, KK, O, B>, dim3(KK * nq_of(KK, P::fixed)), dim3(kSpreadThreads),
                         spread_lds_bytes<P, KK>(), s, t, a, bt);
         });
       });
@@ -1163,7 +1102,7 @@ hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t, const Batc
       constexpr int KK = decltype(kc)::value;
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
-        const int blocks = KK / 2 + 1 + (P::fixed ? 1 : 0);
+        const int blocks = KK / 2 + 2;  // columns and the counts/headroom workgroup
         return launch(k_conv<P, KK, B>, dim3(blocks), dim3(conv_threads<P, KK>()),
                       conv_lds_bytes<P, KK>(), s, t, a, bt);
       });
@@ -1185,8 +1124,7 @@ hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t, const Bat
         constexpr int O = decltype(oc)::value;
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
-          const int blocks = KK + ((a.reduce_ev || B) ? 1 : 0);
-          return launch(k_inv_x<P, KK, O, B>, dim3(blocks), dim3(kPlaneThreads),
+          return launch(k_inv_x<P, KK, O, B>, dim3(KK), dim3(kPlaneThreads),
                         inv_x_lds_bytes<P, KK>(), s, t, a, bt);
         });
       });
@@ -1201,37 +1139,20 @@ hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t, const Ba
       constexpr int KK = decltype(kc)::value;
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        if constexpr (!interp_fused<P, KK, O>()) {
-          return hipErrorInvalidValue;
-        } else {
-          return with_batch(bt, [&](auto bc) {
-            constexpr bool B = decltype(bc)::value;
-            const int blocks = KK * nq_of(KK) + ((a.reduce_ev || B) ? 1 : 0);
-            return launch(k_interp<P, KK, O, B>, dim3(blocks), dim3(kInterpThreads),
-                          interp_lds_bytes<P, KK, O>(), s, t, a, bt);
-          });
-        }
+        return with_batch(bt, [&](auto bc) {
+          constexpr bool B = decltype(bc)::value;
+          const int blocks = KK * nq_of(KK, P::fixed) + ((a.reduce_ev || B) ? 1 : 0);
+          return launch(k_interp<P, KK, O, B>, dim3(blocks), dim3(kInterpThreads),
+                        interp_lds_bytes<P, KK, O>(), s, t, a, bt);
+        });
       });
     });
   });
 }
 
-hipError_t launch_gather(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
-  if (a.N == 0) return skip(s, t);
-  return with_prec(a.precision, [&](auto pt) {
-    using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
-      return with_order(a.order, [&](auto oc) {
-        constexpr int O = decltype(oc)::value;
-        return with_batch(bt, [&](auto bc) {
-          constexpr bool B = decltype(bc)::value;
-          const int blocks = (a.N + kGatherThreads - 1) / kGatherThreads;
-          return launch(k_gather<P, KK, O, B>, dim3(blocks), dim3(kGatherThreads), 0, s, t, a, bt);
-        });
-      });
-    });
-  });
+hipError_t launch_clear_counts(const Args& a, hipStream_t s) {
+  k_clear_counts<<<dim3(1), dim3(1024), 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_clear_flags(const Args& a, hipStream_t s) {

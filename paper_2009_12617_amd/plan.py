@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import PME_FP32_FIXED, PME_FP64, check
 
-KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "inverse_x", "gather")
+KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "interpolate")
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64}
 
 
@@ -182,15 +182,9 @@ class Plan:
         """Synchronise; return the sticky flags and clear them (raises on none)."""
         flags = ctypes.c_uint(0)
         rc = self._lib.pme_check(self._h, ctypes.byref(flags))
-        if rc not in (0, 4, 6):
+        if rc not in (0, 4, 6, 7):
             check(rc, "pme_check")
         return int(flags.value)
-
-    @property
-    def interp_fused(self):
-        """True when the inverse x FFT and interpolation run as one launch
-        (timed in the "gather" slot; "inverse_x" stays empty)."""
-        return self._lib.pme_interp_fused(self._h) == 1
 
     def kernel_timing(self, enable=True):
         check(self._lib.pme_kernel_timing(self._h, int(bool(enable))), "pme_kernel_timing")

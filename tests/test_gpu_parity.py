@@ -185,6 +185,35 @@ def test_split_calls_match_step(P):
     assert torch.allclose(f2, f0 + 1.0, rtol=0, atol=1e-12)
 
 
+def test_bucket_overflow_and_call_order(P):
+    # half the atoms packed into a 0.6 A cube: their bins hold far more atoms
+    # than a bucket's capacity, so most of them travel through the overflow
+    # list; grid and forces must not notice
+    rng = np.random.default_rng(21)
+    L, n = 24.0, 3000
+    box = np.diag([L] * 3)
+    pos = rng.uniform(0.0, L, (n, 3))
+    pos[:1500] = 5.0 + rng.uniform(0.0, 0.6, (1500, 3))
+    q = rng.choice([-1.0, 1.0], n)
+    q -= q.mean()
+    plan = P.Plan(32, 4, 0.35, max_atoms=n)
+    plan.set_debug(True)
+    f0, e0 = (t.clone() for t in plan.step(dev(pos), dev(q), box))
+    assert np.array_equal(plan.debug_grid(0).cpu().numpy(), oracle.mirror_grid(pos, q, box, 32, 4)[0])
+    compare((f0, e0), oracle.spme(pos, q, box, 32, 4, 0.35), F32_FORCE, F32_ENERGY, F32_VIRIAL)
+    assert plan.check() == 0
+    # a spread left without its solve: the next spread starts from clean buckets
+    plan.spread(dev(pos[::-1].copy()), dev(q[::-1].copy()), box)
+    f1, e1 = plan.step(dev(pos), dev(q), box)
+    assert torch.equal(f1, f0) and torch.equal(e1, e0)
+    assert plan.check() == 0
+    # the convolution runs once per spread
+    from paper_2009_12617_amd._lib import SpmeError
+    with pytest.raises(SpmeError) as ei:
+        plan.solve()
+    assert ei.value.code == 7
+
+
 def test_edge_cases(P):
     box = np.diag([20.0] * 3)
     plan = P.Plan(32, 4, 0.35, max_atoms=5000)
