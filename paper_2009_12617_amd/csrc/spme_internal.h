@@ -64,14 +64,14 @@ struct Layout {
   size_t orec;     // records [max_atoms]: atoms that found their bucket full
   size_t spec;     // complex[K/2+1][K][K] half spectrum, columns [x'][z][y]
   size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
-  size_t partial;  // double[conv_blocks][8]: energy/virial partial sums
+  size_t partial;  // double[partial_rows][8]: energy/virial partial sums
   size_t dbg;      // int64 or double [K][K][K]: charge-grid copy (debug)
   size_t args;     // Args: device copy of the bound step arguments (batched runs)
   size_t total;
   int n_chunks_max;
   int cap;          // records per bucket
   int orec_max;     // overflow records (max_atoms)
-  int conv_blocks;  // K/2+1 columns, one partial row each
+  int partial_rows;  // energy/virial rows: one per wavefront of the convolution
   int phi_pitch;
 };
 

@@ -120,19 +120,24 @@ __device__ __forceinline__ void row_scan_add(double* v) {
   for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x118, 0xf>(v[c]);
 }
 
-// Sums of V doubles over the block in a fixed order: an inclusive DPP scan
-// over each wavefront (rows, then row_bcast 15 and 31), whose lane 63 holds
-// the wavefront's sums; then the wavefront sums in wavefront order by a row
-// scan in wavefront 0.  Thread 15 ends with the block sums in v.  Every
+// wave_sums: an inclusive DPP scan of V doubles over the wavefront (rows,
+// then row_bcast 15 and 31); lane 63 ends with the wavefront's sums.
+// block_sums: sums over the block in a fixed order -- wave_sums, then the
+// wavefront sums in wavefront order by a row scan in wavefront 0.  Thread 15 ends with the block sums in v.  Every
 // thread must call it (at most 16 wavefronts); wred needs 16 * 8 doubles; it
 // synchronises once and the caller synchronises before reusing wred.
 template <int V>
-__device__ __forceinline__ void block_sums(double* v, double* wred) {
+__device__ __forceinline__ void wave_sums(double* v) {
   row_scan_add<V>(v);
 #pragma unroll
   for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x142, 0xa>(v[c]);
 #pragma unroll
   for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x143, 0xc>(v[c]);
+}
+
+template <int V>
+__device__ __forceinline__ void block_sums(double* v, double* wred) {
+  wave_sums<V>(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 63) {
 #pragma unroll
@@ -552,6 +557,18 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   cplx<T>* col = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)xp * K * K;  // [z][y]
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
+  // the first chunk's loads are issued before the tables are computed
+  // (when they fit in a few registers)
+  constexpr int EPT = (C * K + NT - 1) / NT;
+  constexpr bool PREFETCH = EPT * sizeof(cplx<T>) <= 64;
+  cplx<T> first[PREFETCH ? EPT : 1];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = min(tid + k * NT, C * K - 1);
+      first[k] = col[i];
+    }
+  }
   for (int i = tid; i < K; i += NT) tw[i] = twg[i];
   {
     // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
@@ -570,9 +587,17 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   // --- forward y: one pencil per z
   for (int c = 0; c < NC; ++c) {
     const int z0 = c * C;
-    for (int i = tid; i < C * K; i += NT) {
-      const int zz = i / K, y = i - zz * K;
-      buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int i = tid + k * NT;
+        if (i < C * K) buf[(i / K) * PY + (i % K)] = first[k];
+      }
+    } else {
+      for (int i = tid; i < C * K; i += NT) {
+        const int zz = i / K, y = i - zz * K;
+        buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+      }
     }
     __syncthreads();
     for (int task = tid; task < C * TK; task += NT) {
@@ -623,33 +648,36 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     __syncthreads();
     TRACE(2, 2);
     const double A = pref * bs[xp];
-#pragma unroll 2
-    for (int i = tid; i < K * C; i += NT) {
+    constexpr int NIT = (K * C + NT - 1) / NT;
+#pragma unroll(NIT <= 4 ? NIT : 2)
+    for (int it = 0; it < NIT; ++it) {
+      const int i = tid + it * NT;
+      if ((K * C) % NT != 0 && i >= K * C) break;
       const int z = i / C, yy = i - z * C, y = y0 + yy;
       const int my = (y <= K / 2) ? y : y - K, mz = (z <= K / 2) ? z : z - K;
       const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
       const double ny = (2 * y == K) ? 0.0 : mvy, nz = (2 * z == K) ? 0.0 : mvz;
       const cplx<T> f = buf[z * PZ + yy];
-      double G = 0.0;
-      if (xp != 0 || y != 0 || z != 0) {
-        const double msq = fma(mvz, mvz, fma(mvy, mvy, mvx2));
-        // 1/msq: hardware reciprocal and two Newton steps
-        double r = __builtin_amdgcn_rcp(msq);
-        r = fma(r, fma(-msq, r, 1.0), r);
-        r = fma(r, fma(-msq, r, 1.0), r);
-        G = A * bs[K + y] * bs[2 * K + z] * r;
-        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-        const double e = wx * G * f2;
-        const double eu = e * (r + fac);
-        const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
-        acc[0] += e;
-        acc[1] = fma(eux, mvx, acc[1]);
-        acc[2] = fma(euy, mvy, acc[2]);
-        acc[3] = fma(eu * mvz, mvz, acc[3]);
-        acc[4] = fma(eun, ny, acc[4]);
-        acc[5] = fma(eun, nz, acc[5]);
-        acc[6] = fma(eu * ny, nz, acc[6]);
-      }
+      // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
+      // its G by 0, without a branch
+      const bool m0 = (xp == 0) && (y == 0) && (z == 0);
+      const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
+      // 1/msq: hardware reciprocal and two Newton steps
+      double r = __builtin_amdgcn_rcp(msq);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      const double G = m0 ? 0.0 : A * bs[K + y] * bs[2 * K + z] * r;
+      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+      const double e = wx * G * f2;
+      const double eu = e * (r + fac);
+      const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
+      acc[0] += e;
+      acc[1] = fma(eux, mvx, acc[1]);
+      acc[2] = fma(euy, mvy, acc[2]);
+      acc[3] = fma(eu * mvz, mvz, acc[3]);
+      acc[4] = fma(eun, ny, acc[4]);
+      acc[5] = fma(eun, nz, acc[5]);
+      acc[6] = fma(eu * ny, nz, acc[6]);
       const T g = (T)G;
       buf[z * PZ + yy] = {f.x * g, f.y * g};
     }
@@ -669,18 +697,6 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     }
   }
   TRACE(2, 5);
-  // Energy/virial: fixed-order block sums -- one partial row per column
-  // (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz), added in column order later.
-  block_sums<7>(acc, wred);
-  if (tid == 15) {
-    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + xp * 8;
-    row[0] = acc[0];
-#pragma unroll
-    for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
-#pragma unroll
-    for (int c = 4; c < 7; ++c) row[c] = -2.0 * acc[c];
-  }
-  TRACE(2, 4);
 
   // --- inverse y
   for (int c = 0; c < NC; ++c) {
@@ -703,18 +719,36 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     }
     if constexpr (NC > 1) __syncthreads();
   }
+  // Energy/virial: a fixed-order DPP sum over each wavefront, one partial
+  // row (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz) per wavefront, added in row order
+  // later; placed after the last stores so that it overlaps their completion.
+  wave_sums<7>(acc);
+  if ((tid & 63) == 63) {
+    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + (xp * (NT / 64) + (tid >> 6)) * 8;
+    row[0] = acc[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
+#pragma unroll
+    for (int c = 4; c < 7; ++c) row[c] = -2.0 * acc[c];
+  }
   TRACE(2, 15);
 }
 
-// Sum of the energy/virial partial rows in row order, one thread per value
-// (the same order whatever the workgroup).
+// Sum of the energy/virial partial rows in a fixed order by the first
+// wavefront of the calling workgroup (whatever its size): lane l adds rows
+// l, l+64, ..., then a DPP sum over the lanes.
 __device__ void reduce_ev(const Args& a) {
+  if (threadIdx.x >= 64) return;
   const double* partial = reinterpret_cast<const double*>(a.ws + a.lay.partial);
-  const int c = threadIdx.x;
-  if (c < 7) {
-    double s = 0.0;
-    for (int b = 0; b < a.lay.conv_blocks; ++b) s += partial[b * 8 + c];
-    a.ev[c] = s;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int r = threadIdx.x; r < a.lay.partial_rows; r += 64) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] += partial[r * 8 + c];
+  }
+  wave_sums<7>(v);
+  if (threadIdx.x == 63) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) a.ev[c] = v[c];
   }
 }
 
@@ -997,6 +1031,19 @@ bool grid_supported(int K) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Wavefronts per convolution workgroup (one energy/virial row each).
+static int conv_waves(int K, int precision) {
+  int w = 0;
+  (void)with_prec(precision, [&](auto pt) {
+    using P = decltype(pt);
+    return with_K(K, [&](auto kc) {
+      w = conv_threads<P, decltype(kc)::value>() / 64;
+      return hipSuccess;
+    });
+  });
+  return w;
+}
+
 bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   if (!grid_supported(K) || (order != 4 && order != 6) || max_atoms < 0) return false;
   if (precision != PME_FP32_FIXED && precision != PME_FP64) return false;
@@ -1022,8 +1069,8 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
   L.phi_pitch = phi_pitch_of(K, order);
   L.phi = o;       o = align256(o + (size_t)K * K * L.phi_pitch * real);
-  L.conv_blocks = (int)kh;
-  L.partial = o;   o = align256(o + (size_t)L.conv_blocks * 8 * sizeof(double));
+  L.partial_rows = (int)kh * conv_waves(K, precision);
+  L.partial = o;   o = align256(o + (size_t)L.partial_rows * 8 * sizeof(double));
   L.dbg = o;       o = align256(o + (size_t)K * K * K * 8);
   L.args = o;      o = align256(o + sizeof(Args));
   L.total = o;
