@@ -415,7 +415,9 @@ int orc_spme(const double *pos, const double *q, int N, const double box[9],
 /* The GPU path accumulates charge in 64-bit fixed point so that the   */
 /* grid does not depend on summation order.  Its result is reproducible*/
 /* bit for bit only under one fixed arithmetic recipe, restated here:  */
-/*  Q1 per axis s = x * (1.0/L) in FP64, s -= floor(s), u = K s,       */
+/*  Q1 per axis s = x * (1.0/L) in FP64 (diagonal box) or, for a      */
+/*     general cell, s = a*_a . r = (a*_a0 r0 + a*_a1 r1) + a*_a2 r2    */
+/*     with a*_a from box_recip; s -= floor(s), u = K s,               */
 /*     g = floor(u) mod K, w = u - floor(u) (exact), w32 = (float)w    */
 /*  Q2 q32 = (float)q                                                  */
 /*  Q3 single-precision B-spline recursion (orc_mirror_spline)         */
@@ -460,12 +462,16 @@ int orc_mirror_grid(const double *pos, const double *q, int N, const double box[
                     float *Q32) {
   if (N < 0 || K1 < 2 || K2 < 2 || K3 < 2 || p < 3 || p > ORC_MAXP) return -1;
   if (frac_bits < 1 || frac_bits > 52) return -1;
-  if (box[1] != 0.0 || box[2] != 0.0 || box[3] != 0.0 || box[5] != 0.0 || box[6] != 0.0 ||
-      box[7] != 0.0)
+  int diag = box[1] == 0.0 && box[2] == 0.0 && box[3] == 0.0 && box[5] == 0.0 &&
+             box[6] == 0.0 && box[7] == 0.0;
+  double invL[3] = {0.0, 0.0, 0.0}, rec[9], V;
+  if (diag) {
+    double L[3] = {box[0], box[4], box[8]};
+    if (!(L[0] > 0.0 && L[1] > 0.0 && L[2] > 0.0)) return -1;
+    for (int a = 0; a < 3; ++a) invL[a] = 1.0 / L[a];
+  } else if (box_recip(box, rec, &V)) {
     return -1;
-  double L[3] = {box[0], box[4], box[8]};
-  if (!(L[0] > 0.0 && L[1] > 0.0 && L[2] > 0.0)) return -1;
-  double invL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  }
   int K[3] = {K1, K2, K3};
   long ng = (long)K1 * K2 * K3;
   double scale = ldexp(1.0, frac_bits);
@@ -478,7 +484,7 @@ int orc_mirror_grid(const double *pos, const double *q, int N, const double box[
     for (int a = 0; a < 3; ++a) ok = ok && isfinite(pos[3 * i + a]);
     if (!ok) { status = -2; continue; }
     for (int a = 0; a < 3; ++a) {
-      double s = pos[3 * i + a] * invL[a];
+      double s = diag ? pos[3 * i + a] * invL[a] : dot3(rec + 3 * a, pos + 3 * i);
       s = s - floor(s);
       double u = s * (double)K[a];
       double fl = floor(u);

@@ -38,6 +38,27 @@ def test_mirror_grid_tracks_fp64_grid_and_charge_sum(orc):
         np.testing.assert_array_equal(Qf, (Qi.astype(np.float64) * 2.0 ** -32).astype(np.float32))
 
 
+def test_mirror_grid_general_cell(orc):
+    # a sheared cell: the mirror's fractional coordinates come from the same
+    # reciprocal vectors as the FP64 step, so its grid tracks the FP64 grid
+    pos, q, box = inputs.water_box(200, 14.0, 9)
+    box = np.array([[14.0, 0.0, 0.0], [3.5, 13.0, 0.0], [-2.0, 4.0, 12.5]])
+    for K, p in [(16, 4), (32, 6)]:
+        Qi, Qf = orc.mirror_grid(pos, q, box, K, p)
+        Q64 = orc.spme(pos, q, box, K, p, 0.35, want_grids=True)["Q"]
+        np.testing.assert_allclose(Qf, Q64, atol=2e-6)
+        tot = int(Qi.sum()) * 2.0 ** -32
+        assert tot == pytest.approx(q.sum(), abs=len(q) * p ** 3 * 1e-7)
+    # a diagonal box written as a general cell with one tiny shear moves the
+    # grid by no more than the shear does
+    box2 = np.diag([14.0, 14.0, 14.0])
+    a, _ = orc.mirror_grid(pos, q, box2, 16, 4)
+    box3 = box2.copy()
+    box3[1, 0] = 1e-12
+    b, _ = orc.mirror_grid(pos, q, box3, 16, 4)
+    assert np.abs(a - b).max() * 2.0 ** -32 < 1e-6
+
+
 def test_mirror_grid_is_order_free(orc):
     pos, q, box = inputs.water_box(300, 15.0, 8)
     perm = np.random.default_rng(1).permutation(len(q))
