@@ -38,8 +38,9 @@
  * the ABI.
  *
  * Supported on the GPU: cubic grids K1 = K2 = K3 = K with
- * K in {16, 24, 32, 48, 64, 96, 128}, spline order p in {4, 6}, orthorhombic
- * cells.  Anything else returns PME_EUNSUPPORTED.
+ * K in {16, 24, 32, 48, 64, 96, 128}, spline order p in {4, 6}, any
+ * non-degenerate cell (diagonal boxes take a separable fast path for the
+ * influence function).  Anything else returns PME_EUNSUPPORTED.
  */
 #ifndef SPME_H
 #define SPME_H
@@ -117,7 +118,10 @@ int pme_set_stream(pme_plan *plan, void *stream);
  *   pos  device [N][3] doubles (Angstrom, any image; wrapped internally)
  *   q    device [N] doubles
  *   N    0 <= N <= max_atoms
- *   box  HOST [9] doubles, rows a1, a2, a3; must be diagonal (orthorhombic)
+ *   box  HOST [9] doubles, rows a1, a2, a3 (Angstrom); any cell with nonzero
+ *        volume (PME_EINVAL otherwise).  Fractional coordinates are
+ *        x (1/L) per axis for a diagonal box, else r . a*_a with
+ *        a*_a = (a_b x a_c) / (a_1 . (a_2 x a_3)), no contraction
  * pos and q are read by the launches this call enqueues only.  A spread
  * that follows a spread without pme_solve in between first clears the
  * earlier one's atom buckets (one extra small launch). */

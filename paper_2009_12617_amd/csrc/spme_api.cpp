@@ -244,6 +244,31 @@ int pme_set_debug(pme_plan* p, int keep_charge_grid) {
 
 namespace {
 
+// Reciprocal vectors of a general cell, rec[3a + c] = component c of a*_a
+// with a*_a . a_b = delta_ab: the cross products of the other two box rows
+// over V = a_1 . (a_2 x a_3), each operation one rounding (no contraction),
+// in this order -- the same recipe as the fixed-point grid's reference, so
+// that fractional coordinates agree bit for bit.  False for a degenerate
+// cell.
+bool box_recip(const double* box, double* rec, double* vol) {
+#pragma clang fp contract(off)
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  double c[3];
+  cross(box + 3, box + 6, c);
+  const double V = box[0] * c[0] + box[1] * c[1] + box[2] * c[2];
+  if (!(std::fabs(V) > 0.0) || !std::isfinite(V)) return false;
+  cross(box + 3, box + 6, rec + 0);
+  cross(box + 6, box + 0, rec + 3);
+  cross(box + 0, box + 3, rec + 6);
+  for (int i = 0; i < 9; ++i) rec[i] /= V;
+  *vol = std::fabs(V);
+  return true;
+}
+
 // Validate one step's inputs and fill the per-step fields of a.
 int set_inputs(pme_plan* p, Args& a, const double* pos, const double* q, int N,
                const double box[9]) {
@@ -251,19 +276,31 @@ int set_inputs(pme_plan* p, Args& a, const double* pos, const double* q, int N,
   if (N > 0 && (pos == nullptr || q == nullptr)) return PME_EINVAL;
   for (int i = 0; i < 9; ++i)
     if (!is_fin(box[i])) return PME_EINVAL;
-  if (box[1] != 0.0 || box[2] != 0.0 || box[3] != 0.0 || box[5] != 0.0 || box[6] != 0.0 ||
-      box[7] != 0.0)
-    return PME_EUNSUPPORTED;  // triclinic cells are not supported on the GPU
-  if (!(box[0] > 0.0 && box[4] > 0.0 && box[8] > 0.0)) return PME_EINVAL;
+  const bool diag = box[1] == 0.0 && box[2] == 0.0 && box[3] == 0.0 && box[5] == 0.0 &&
+                    box[6] == 0.0 && box[7] == 0.0;
+  if (diag && !(box[0] > 0.0 && box[4] > 0.0 && box[8] > 0.0)) return PME_EINVAL;
+  double rec[9], vol = 0.0;
+  if (!diag && !box_recip(box, rec, &vol)) return PME_EINVAL;
   a.N = N;
   a.n_chunks = (N + spme::kChunk - 1) / spme::kChunk;
   a.pos = pos;
   a.q = q;
-  a.L[0] = box[0];
-  a.L[1] = box[4];
-  a.L[2] = box[8];
-  for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
-  a.volume = a.L[0] * a.L[1] * a.L[2];
+  a.triclinic = diag ? 0 : 1;
+  if (diag) {
+    a.L[0] = box[0];
+    a.L[1] = box[4];
+    a.L[2] = box[8];
+    for (int d = 0; d < 3; ++d) a.invL[d] = 1.0 / a.L[d];
+    a.volume = a.L[0] * a.L[1] * a.L[2];
+    for (int i = 0; i < 9; ++i) a.rec[i] = (i % 4 == 0) ? a.invL[i / 4] : 0.0;
+  } else {
+    for (int i = 0; i < 9; ++i) a.rec[i] = rec[i];
+    for (int d = 0; d < 3; ++d) {
+      a.invL[d] = rec[4 * d];  // unused for a general cell
+      a.L[d] = 1.0 / rec[4 * d];
+    }
+    a.volume = vol;
+  }
   a.keep_grid = p->keep_grid;
   a.forces = nullptr;
   a.ev = nullptr;

@@ -344,9 +344,19 @@ __device__ __forceinline__ void bspline(T w, T* th, T* dth) {
 // host-rounded 1/L, wrapped into [0,1), u = K s, g = floor(u) mod K and
 // w = u - floor(u), all in FP64 without contraction.  Returns false for a
 // non-finite coordinate.
-__device__ __forceinline__ bool grid_coord(double x, double invL, int K, int* g, double* w) {
+__device__ __forceinline__ bool grid_coord(double x, double invL, int K, int* g, double* w);
+
+// Fractional coordinate along a*_a of a general cell: the dot product
+// r . a*_a in the order (r_0 a_0 + r_1 a_1) + r_2 a_2, one rounding per
+// operation.
+__device__ __forceinline__ double frac_general(const double* r, const double* astar) {
 #pragma clang fp contract(off)
-  double s = x * invL;
+  return (r[0] * astar[0] + r[1] * astar[1]) + r[2] * astar[2];
+}
+
+// Base grid index and offset from a fractional coordinate s (any real).
+__device__ __forceinline__ bool grid_coord_s(double s, int K, int* g, double* w) {
+#pragma clang fp contract(off)
   s = s - floor(s);                        // NaN for a non-finite x
   const bool ok = (s >= 0.0) && (s <= 1.0);
   if (!ok) s = 0.0;
@@ -357,6 +367,12 @@ __device__ __forceinline__ bool grid_coord(double x, double invL, int K, int* g,
   *g = gi;
   *w = u - fl;
   return ok;
+}
+
+// Diagonal box: s = x (1/L) in one rounding.
+__device__ __forceinline__ bool grid_coord(double x, double invL, int K, int* g, double* w) {
+#pragma clang fp contract(off)
+  return grid_coord_s(x * invL, K, g, w);
 }
 
 // 64-bit fixed-point contribution: round-half-even of c 2^F.  c 2^F is exact

@@ -80,7 +80,9 @@ struct Args {
   int N, n_chunks;
   int accumulate, keep_grid;
   int reduce_ev;  // the last launch's extra workgroup adds the energy/virial rows
+  int triclinic;     // 0: diagonal box (L, invL); 1: general cell (rec)
   double L[3], invL[3];
+  double rec[9];     // rec[3a + c]: component c of reciprocal vector a*_a
   double beta, coulomb, volume;
   const double* pos;
   const double* q;

@@ -191,8 +191,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
     int g[3];
     double w[3];
     bool ok = true;
+    const double x3[3] = {a.pos[3 * (size_t)i], a.pos[3 * (size_t)i + 1], a.pos[3 * (size_t)i + 2]};
+    if (!a.triclinic) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ok &= grid_coord(a.pos[3 * (size_t)i + d], a.invL[d], K, &g[d], &w[d]);
+      for (int d = 0; d < 3; ++d) ok &= grid_coord(x3[d], a.invL[d], K, &g[d], &w[d]);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ok &= grid_coord_s(frac_general(x3, a.rec + 3 * d), K, &g[d], &w[d]);
+    }
     double qi = a.q[i];
     ok &= (qi - qi == 0.0);  // finite
     if (!ok) {
@@ -560,7 +566,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   // the first chunk's loads are issued before the tables are computed
   // (when they fit in a few registers)
   constexpr int EPT = (C * K + NT - 1) / NT;
-  constexpr bool PREFETCH = EPT * sizeof(cplx<T>) <= 64;
+  constexpr bool PREFETCH = P::fixed && EPT * sizeof(cplx<T>) <= 64;
   cplx<T> first[PREFETCH ? EPT : 1];
   if constexpr (PREFETCH) {
 #pragma unroll
@@ -580,7 +586,8 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
       // Args copy to scratch)
       const double il = ax == 0 ? a.invL[0] : ax == 1 ? a.invL[1] : a.invL[2];
       const double u = mt * il;
-      bs[i] = bsg[i] * exp(-fac * u * u);
+      // a general cell keeps the bare moduli: its Gaussian does not factor
+      bs[i] = a.triclinic ? bsg[i] : bsg[i] * exp(-fac * u * u);
     }
   }
 
@@ -648,6 +655,55 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     __syncthreads();
     TRACE(2, 2);
     const double A = pref * bs[xp];
+    if (a.triclinic) {
+      // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
+      // each Nyquist index is averaged over its two signs explicitly
+      for (int i = tid; i < K * C; i += NT) {
+        const int z = i / C, yy = i - z * C, y = y0 + yy;
+        const int ms0[3] = {xp, (y <= K / 2) ? y : y - K, (z <= K / 2) ? z : z - K};
+        const int ny3[3] = {2 * xp == K, 2 * y == K, 2 * z == K};
+        const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
+        const cplx<T> f = buf[z * PZ + yy];
+        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+        double G = 0.0;
+        if (xp != 0 || y != 0 || z != 0) {
+          const double Bw = A * bs[K + y] * bs[2 * K + z] / nvar;
+          for (int v = 0; v < nvar; ++v) {
+            double ms[3];
+            int bit = 0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+              ms[ax] = ms0[ax];
+              if (ny3[ax]) {
+                if ((v >> bit) & 1) ms[ax] = -ms[ax];
+                ++bit;
+              }
+            }
+            double mv[3];
+#pragma unroll
+            for (int c2 = 0; c2 < 3; ++c2)
+              mv[c2] = ms[0] * a.rec[c2] + ms[1] * a.rec[3 + c2] + ms[2] * a.rec[6 + c2];
+            const double msq = mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2];
+            double r = __builtin_amdgcn_rcp(msq);
+            r = fma(r, fma(-msq, r, 1.0), r);
+            r = fma(r, fma(-msq, r, 1.0), r);
+            const double Gv = Bw * exp(-fac * msq) * r;
+            const double e = wx * Gv * f2;
+            const double eu = e * (r + fac);
+            acc[0] += e;
+            acc[1] = fma(eu * mv[0], mv[0], acc[1]);
+            acc[2] = fma(eu * mv[1], mv[1], acc[2]);
+            acc[3] = fma(eu * mv[2], mv[2], acc[3]);
+            acc[4] = fma(eu * mv[0], mv[1], acc[4]);
+            acc[5] = fma(eu * mv[0], mv[2], acc[5]);
+            acc[6] = fma(eu * mv[1], mv[2], acc[6]);
+            G += Gv;
+          }
+        }
+        const T g = (T)G;
+        buf[z * PZ + yy] = {f.x * g, f.y * g};
+      }
+    } else {
     constexpr int NIT = (K * C + NT - 1) / NT;
 #pragma unroll(NIT <= 4 ? NIT : 2)
     for (int it = 0; it < NIT; ++it) {
@@ -680,6 +736,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
       acc[6] = fma(eu * ny, nz, acc[6]);
       const T g = (T)G;
       buf[z * PZ + yy] = {f.x * g, f.y * g};
+    }
     }
     __syncthreads();
     TRACE(2, 3);
@@ -849,8 +906,17 @@ __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec
     }
   }
   const double qk = -qi * (double)K;
-  const double f[3] = {qk * a.invL[0] * (double)sx, qk * a.invL[1] * (double)sy,
-                       qk * a.invL[2] * (double)sz};
+  double f[3];
+  if (!a.triclinic) {
+    f[0] = qk * a.invL[0] * (double)sx;
+    f[1] = qk * a.invL[1] * (double)sy;
+    f[2] = qk * a.invL[2] * (double)sz;
+  } else {
+    // F = -q K (s_1 a*_1 + s_2 a*_2 + s_3 a*_3)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      f[c] = qk * ((double)sx * a.rec[c] + (double)sy * a.rec[3 + c] + (double)sz * a.rec[6 + c]);
+  }
   double* out = a.forces + 3 * (size_t)r.idx;
   if (a.accumulate) {
     out[0] += f[0];

@@ -273,8 +273,29 @@ def test_call_order_and_arguments(P):
     with pytest.raises(SpmeError) as ei:
         plan.step(dev(pos), dev(q), box)
     assert ei.value.code == 1
-    tric = box.copy()
-    tric[1, 0] = 1.0
+    flat = box.copy()
+    flat[1] = flat[0]  # two equal cell vectors: no volume
     with pytest.raises(SpmeError) as ei:
-        plan.spread(dev(pos[:10]), dev(q[:10]), tric)
-    assert ei.value.code == 2
+        plan.spread(dev(pos[:10]), dev(q[:10]), flat)
+    assert ei.value.code == 1
+
+
+# a sheared cell: rows a1, a2, a3
+GENERAL_BOX = np.array([[30.0, 0.0, 0.0], [6.0, 28.0, 0.0], [-4.0, 5.0, 27.0]])
+
+
+@pytest.mark.parametrize("precision", ["fp32_fixed", "fp64"])
+@pytest.mark.parametrize("K,p", [(32, 4), (48, 6)])
+def test_general_cell(P, precision, K, p):
+    pos, q, _ = system("general", 700, 28.0)
+    box = GENERAL_BOX
+    plan = P.Plan(K, p, 0.35, max_atoms=len(q), precision=precision)
+    plan.set_debug(True)
+    res = plan.step(dev(pos), dev(q), box)
+    ref = oracle.spme(pos, q, box, K, p, 0.35)
+    if precision == "fp32_fixed":
+        grid = plan.debug_grid(0).cpu().numpy()
+        assert np.array_equal(grid, oracle.mirror_grid(pos, q, box, K, p)[0])
+        compare(res, ref, F32_FORCE, F32_ENERGY, F32_VIRIAL)
+    else:
+        compare(res, ref, F64_FORCE, F64_ENERGY, F64_ENERGY)
