@@ -175,6 +175,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--parity-frames", type=int, default=3)
+    ap.add_argument("--no-half", action="store_true", help="skip the binary16-spectrum variant")
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
@@ -356,6 +357,21 @@ def main():
                 "step_roofline_frac": step_bytes(N, K, True) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"# fp64: {ms64 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
+    half = None
+    plan16 = None
+    if not args.no_half:
+        # the reduced-precision variant: the half spectrum in binary16 between
+        # launches (bytes of both corner turns halved); accuracy below
+        plan16 = Plan(K, w.order, w.beta, max_atoms=N, precision="fp32_fixed_half", device=dev)
+        ms16, _, ok16 = run_graph(plan16, args.steps, args.warmup)
+        if not ok16:
+            print("bench.py: half-spectrum graph replay differs from host-launched steps", file=sys.stderr)
+            sys.exit(1)
+        kh = K // 2 + 1
+        half = {"us_per_step": ms16 * 1e3, "speedup_vs_fp32_fixed": ms_step / ms16,
+                "step_algorithmic_bytes": step_bytes(N, K) - 16 * K * K * kh}
+        print(f"# fp32_fixed_half: {ms16 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         from paper_2009_12617_amd import Batch
@@ -386,6 +402,13 @@ def main():
             errs.append((fr, er))
         parity = {"frames": pick, "force_rel_rms_max": max(x[0] for x in errs),
                   "energy_rel_max": max(x[1] for x in errs), "reference": "FP64 CPU oracle"}
+        if plan16 is not None:
+            f, e = plan16.step(d_frames[pick[0]], d_q, box)
+            ref = oracle.spme(frames[pick[0]], q, box, K, w.order, w.beta)
+            half["force_rel_rms"] = float(np.linalg.norm(f.cpu().numpy() - ref["forces"]) /
+                                          np.linalg.norm(ref["forces"]))
+            half["energy_rel"] = float(abs(e[0].item() - ref["E"]) / abs(ref["E"]))
+            half["parity_frame"] = pick[0]
     if not args.no_cpu_baseline:
         n = 0
         t0 = time.perf_counter()
@@ -428,6 +451,7 @@ def main():
         "step_roofline_frac": step_bytes(N, K) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_algorithmic_bytes": step_bytes(N, K),
         "fp64_path": fp64,
+        "half_spectrum_path": half,
         "batched": batched,
         "serving": serving,
         "parity": parity,

@@ -59,8 +59,13 @@ typedef struct pme_plan pme_plan;
  *   charge grid accumulated in 64-bit two's-complement fixed point with
  *   frac_bits fraction bits (order-free, so bit-identical run to run);
  *   B-spline moduli, influence function, energy and virial in FP64.
- * PME_FP64: every stage in FP64 (charge grid accumulated in FP64). */
-typedef enum { PME_FP64 = 0, PME_FP32_FIXED = 1 } pme_precision;
+ * PME_FP64: every stage in FP64 (charge grid accumulated in FP64).
+ * PME_FP32_FIXED_HALF: as PME_FP32_FIXED, but the half spectrum is stored
+ *   between launches in IEEE binary16 (round to nearest even), halving the
+ *   bytes of both corner turns; arithmetic stays FP32/FP64.  Accuracy is
+ *   bounded by binary16's 11-bit significand (force errors of order 1e-4
+ *   relative) and its range (|values| < 65504). */
+typedef enum { PME_FP64 = 0, PME_FP32_FIXED = 1, PME_FP32_FIXED_HALF = 2 } pme_precision;
 
 typedef enum {
   PME_OK = 0,
@@ -173,10 +178,11 @@ int pme_set_debug(pme_plan *plan, int keep_charge_grid);
  *            frac_bits fraction bits) or double (FP64); needs pme_set_debug(1)
  *            before the spread
  *   which 1: the half spectrum, stored as columns [K1/2+1][K3][K2] complex
- *            (float2 / double2; index m1 slowest, y fastest): after
+ *            (float2 / double2 / two binary16 for PME_FP32_FIXED_HALF; index
+ *            m1 slowest, y fastest): after
  *            pme_spread the forward transform of the charge grid along x;
  *            after pme_solve G F transformed back along z and y
- *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED) or double */
+ *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED, _HALF) or double */
 int pme_debug_grid(pme_plan *plan, int which, void *dst);
 
 /* Size in bytes of pme_debug_grid(which)'s output (0 for a bad which). */

@@ -142,7 +142,8 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   if (out == nullptr) return PME_EINVAL;
   *out = nullptr;
   if (K1 < 2 || K2 < 2 || K3 < 2 || order < 3 || !(beta > 0.0) || !is_fin(beta) ||
-      max_atoms < 0 || (precision != PME_FP64 && precision != PME_FP32_FIXED) ||
+      max_atoms < 0 ||
+      (precision != PME_FP64 && precision != PME_FP32_FIXED && precision != PME_FP32_FIXED_HALF) ||
       !is_fin(coulomb))
     return PME_EINVAL;
   if (frac_bits == 0) frac_bits = 32;
@@ -198,7 +199,7 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
     e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * 3 * K,
                        hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) {
-    if (precision == PME_FP32_FIXED)
+    if (precision != PME_FP64)
       e = hipMemcpyAsync(p->ws + L.tw, p->tw32.data(), sizeof(float) * 2 * K,
                          hipMemcpyHostToDevice, p->stream);
     else
@@ -489,10 +490,11 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
 size_t pme_debug_grid_bytes(pme_plan* p, int which) {
   if (p == nullptr) return 0;
   const size_t K = p->K, kh = K / 2 + 1;
-  const size_t real = p->precision == PME_FP32_FIXED ? 4 : 8;
+  const size_t real = p->precision != PME_FP64 ? 4 : 8;
+  const size_t spec_cpx = p->precision == PME_FP32_FIXED_HALF ? 4 : 2 * real;
   switch (which) {
     case 0: return K * K * K * 8;
-    case 1: return K * K * kh * 2 * real;
+    case 1: return K * K * kh * spec_cpx;
     case 2: return K * K * K * real;
     default: return 0;
   }
@@ -503,7 +505,7 @@ int pme_debug_grid(pme_plan* p, int which, void* dst) {
   const size_t bytes = pme_debug_grid_bytes(p, which);
   if (bytes == 0) return PME_EINVAL;
   const size_t K = p->K;
-  const size_t real = p->precision == PME_FP32_FIXED ? 4 : 8;
+  const size_t real = p->precision != PME_FP64 ? 4 : 8;
   hipError_t e;
   switch (which) {
     case 0:

@@ -51,16 +51,44 @@ __device__ unsigned long long* g_trace;
   } while (0)
 #endif
 
+// Half-spectrum storage between launches: complex float, complex double, or
+// (reduced-precision variant) a pair of IEEE binary16 values rounded to
+// nearest even.
+struct cplx_h {
+  _Float16 x, y;
+};
+__device__ __forceinline__ cplx<float> spec_ld(const cplx<float>* p) { return *p; }
+__device__ __forceinline__ cplx<double> spec_ld(const cplx<double>* p) { return *p; }
+__device__ __forceinline__ cplx<float> spec_ld(const cplx_h* p) {
+  const cplx_h h = *p;
+  return {(float)h.x, (float)h.y};
+}
+__device__ __forceinline__ void spec_st(cplx<float>* p, cplx<float> v) { *p = v; }
+__device__ __forceinline__ void spec_st(cplx<double>* p, cplx<double> v) { *p = v; }
+__device__ __forceinline__ void spec_st(cplx_h* p, cplx<float> v) {
+  *p = cplx_h{(_Float16)v.x, (_Float16)v.y};
+}
+
 struct PFixed {
   using real = float;
   using acc = unsigned long long;
   using rec = RecF;
+  using spec = cplx<float>;
+  static constexpr bool fixed = true;
+};
+// FP32/fixed with the half spectrum kept in FP16 between launches
+struct PHalf {
+  using real = float;
+  using acc = unsigned long long;
+  using rec = RecF;
+  using spec = cplx_h;
   static constexpr bool fixed = true;
 };
 struct PDouble {
   using real = double;
   using acc = double;
   using rec = RecD;
+  using spec = cplx<double>;
   static constexpr bool fixed = false;
 };
 
@@ -446,12 +474,13 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   TRACE(1, 3);
 
   // half spectrum columns [x'][z][y]: runs of R rows per x'
-  cplx<T>* spec = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)z * K + y0;
+  using S = typename P::spec;
+  S* spec = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)z * K + y0;
   constexpr int PC = P::fixed ? PITCH : PITCH / 2;
   const cplx<T>* tc = reinterpret_cast<const cplx<T>*>(tile);
   for (int i = tid; i < R * KH; i += kSpreadThreads) {
     const int x = i / R, y = i - x * R;
-    spec[(size_t)x * K * K + y] = tc[y * PC + x];
+    spec_st(&spec[(size_t)x * K * K + y], tc[y * PC + x]);
   }
   TRACE(1, 15);
 }
@@ -560,7 +589,8 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     return;
   }
   const int xp = blockIdx.x;  // m1
-  cplx<T>* col = reinterpret_cast<cplx<T>*>(a.ws + a.lay.spec) + (size_t)xp * K * K;  // [z][y]
+  using S = typename P::spec;
+  S* col = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)xp * K * K;  // [z][y]
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
   // the first chunk's loads are issued before the tables are computed
@@ -572,7 +602,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int i = min(tid + k * NT, C * K - 1);
-      first[k] = col[i];
+      first[k] = spec_ld(&col[i]);
     }
   }
   for (int i = tid; i < K; i += NT) tw[i] = twg[i];
@@ -603,7 +633,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     } else {
       for (int i = tid; i < C * K; i += NT) {
         const int zz = i / K, y = i - zz * K;
-        buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K + y]);
       }
     }
     __syncthreads();
@@ -615,7 +645,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     if constexpr (NC > 1) {
       for (int i = tid; i < C * K; i += NT) {
         const int zz = i / K, y = i - zz * K;
-        col[(size_t)(z0 + zz) * K + y] = buf[zz * PY + y];
+        spec_st(&col[(size_t)(z0 + zz) * K + y], buf[zz * PY + y]);
       }
       __syncthreads();
     }
@@ -644,7 +674,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     if constexpr (NC > 1) {
       for (int i = tid; i < K * C; i += NT) {
         const int z = i / C, yy = i - z * C;
-        buf[z * PZ + yy] = col[(size_t)z * K + y0 + yy];
+        buf[z * PZ + yy] = spec_ld(&col[(size_t)z * K + y0 + yy]);
       }
       __syncthreads();
     }
@@ -748,7 +778,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     if constexpr (NC > 1) {
       for (int i = tid; i < K * C; i += NT) {
         const int z = i / C, yy = i - z * C;
-        col[(size_t)z * K + y0 + yy] = buf[z * PZ + yy];
+        spec_st(&col[(size_t)z * K + y0 + yy], buf[z * PZ + yy]);
       }
       __syncthreads();
     }
@@ -761,7 +791,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     if constexpr (NC > 1) {
       for (int i = tid; i < C * K; i += NT) {
         const int zz = i / K, y = i - zz * K;
-        buf[zz * PY + y] = col[(size_t)(z0 + zz) * K + y];
+        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K + y]);
       }
       __syncthreads();
     }
@@ -772,7 +802,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     __syncthreads();
     for (int i = tid; i < C * K; i += NT) {
       const int zz = i / K, y = i - zz * K;
-      col[(size_t)(z0 + zz) * K + y] = buf[zz * PY + y];
+      spec_st(&col[(size_t)(z0 + zz) * K + y], buf[zz * PY + y]);
     }
     if constexpr (NC > 1) __syncthreads();
   }
@@ -834,10 +864,10 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
   cplx<T>* tw = pl + K * PC;
   const int tid = threadIdx.x;
   const int z = xcd_local(blockIdx.x, K);
-  const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
+  const typename P::spec* spec = reinterpret_cast<const typename P::spec*>(a.ws + a.lay.spec);
   for (int i = tid; i < KH * K; i += kPlaneThreads) {
     const int x = i / K, y = i - x * K;
-    pl[y * PC + x] = spec[((size_t)x * K + z) * K + y];
+    pl[y * PC + x] = spec_ld(&spec[((size_t)x * K + z) * K + y]);
   }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
@@ -955,7 +985,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   const int cap = a.lay.cap;
   const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
   const Rec* orec = reinterpret_cast<const Rec*>(a.ws + a.lay.orec);
-  const cplx<T>* spec = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.spec);
+  const typename P::spec* spec = reinterpret_cast<const typename P::spec*>(a.ws + a.lay.spec);
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   // the bin's buckets (z, qs, head) and (z, qs, body), with the counts the
   // convolution kept for this pass
@@ -973,7 +1003,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
     int zz = z - ORDER + 1 + jz, yy = y0 - ORDER + 1 + r;
     if (zz < 0) zz += K;
     if (yy < 0) yy += K;
-    buf[(jz * RR + r) * PC + x] = spec[((size_t)x * K + zz) * K + yy];
+    buf[(jz * RR + r) * PC + x] = spec_ld(&spec[((size_t)x * K + zz) * K + yy]);
   }
   if (tid < K) tw[tid] = twg[tid];
   __syncthreads();
@@ -1025,7 +1055,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
 // its convolution (one workgroup).
 __global__ void k_clear_counts(Args a) {
   unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
-  const int nbins = 2 * a.K * nq_of(a.K, a.precision == PME_FP32_FIXED);
+  const int nbins = 2 * a.K * nq_of(a.K, a.precision != PME_FP64);
   for (int b = threadIdx.x; b < nbins; b += blockDim.x) bcnt[b] = 0u;
   if (threadIdx.x == 0) reinterpret_cast<unsigned*>(a.ws + a.lay.ovf)[0] = 0u;
 }
@@ -1067,6 +1097,7 @@ template <class F>
 hipError_t with_prec(int prec, F&& f) {
   if (prec == PME_FP32_FIXED) return f(PFixed{});
   if (prec == PME_FP64) return f(PDouble{});
+  if (prec == PME_FP32_FIXED_HALF) return f(PHalf{});
   return hipErrorInvalidValue;
 }
 template <class F>
@@ -1112,9 +1143,11 @@ static int conv_waves(int K, int precision) {
 
 bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   if (!grid_supported(K) || (order != 4 && order != 6) || max_atoms < 0) return false;
-  if (precision != PME_FP32_FIXED && precision != PME_FP64) return false;
-  const bool fx = precision == PME_FP32_FIXED;
+  if (precision != PME_FP32_FIXED && precision != PME_FP64 && precision != PME_FP32_FIXED_HALF)
+    return false;
+  const bool fx = precision != PME_FP64;
   const size_t real = fx ? 4 : 8, cpx = 2 * real;
+  const size_t spec_cpx = precision == PME_FP32_FIXED_HALF ? 4 : cpx;
   const size_t kh = (size_t)K / 2 + 1;
   const int nch = (max_atoms + kChunk - 1) / kChunk;
   const size_t nbins = 2 * (size_t)K * nq_of(K, fx);
@@ -1132,7 +1165,7 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   L.rec = o;       o = align256(o + nbins * (size_t)L.cap * rsz);
   L.orec = o;      o = align256(o + (size_t)max_atoms * rsz);
   L.orec_max = max_atoms;
-  L.spec = o;      o = align256(o + (size_t)K * K * kh * cpx);
+  L.spec = o;      o = align256(o + (size_t)K * K * kh * spec_cpx);
   L.phi_pitch = phi_pitch_of(K, order);
   L.phi = o;       o = align256(o + (size_t)K * K * L.phi_pitch * real);
   L.partial_rows = (int)kh * conv_waves(K, precision);

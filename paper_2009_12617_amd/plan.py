@@ -10,10 +10,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PME_FP32_FIXED, PME_FP64, check
+from ._lib import PME_FP32_FIXED, PME_FP32_FIXED_HALF, PME_FP64, check
 
 KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "interpolate")
-PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64}
+PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64,
+              "fp32_fixed_half": PME_FP32_FIXED_HALF}
 
 
 def _box9(box):
@@ -40,7 +41,8 @@ class Plan:
     """One SPME reciprocal-space solver for a cubic K^3 grid.
 
     precision: "fp32_fixed" (FP32 splines/FFT/convolution, 64-bit fixed-point
-    charge grid, FP64 moduli/energy/virial) or "fp64".
+    charge grid, FP64 moduli/energy/virial), "fp32_fixed_half" (the same with
+    the half spectrum stored in binary16 between launches) or "fp64".
     """
 
     def __init__(self, K, order=4, beta=0.34, max_atoms=0, precision="fp32_fixed",
@@ -165,11 +167,13 @@ class Plan:
         spectrum (complex) as columns [x', z, y] of shape [K/2+1, K, K],
         2: potential phi [z, y, x]."""
         K, kh = self.K, self.K // 2 + 1
-        fx = self.precision == "fp32_fixed"
+        fx = self.precision != "fp64"
         if which == 0:
             out = torch.empty((K, K, K), dtype=torch.int64 if fx else torch.float64, device=self.device)
         elif which == 1:
-            out = torch.empty((kh, K, K), dtype=torch.complex64 if fx else torch.complex128, device=self.device)
+            dt = {"fp32_fixed": torch.complex64, "fp32_fixed_half": torch.complex32,
+                  "fp64": torch.complex128}[self.precision]
+            out = torch.empty((kh, K, K), dtype=dt, device=self.device)
         elif which == 2:
             out = torch.empty((K, K, K), dtype=torch.float32 if fx else torch.float64, device=self.device)
         else:

@@ -280,6 +280,26 @@ def test_call_order_and_arguments(P):
     assert ei.value.code == 1
 
 
+# binary16 half spectrum between launches: each stored value is rounded once
+# with relative error <= 2^-11 (two stores per step), so forces move by a few
+# 1e-4 relative; energy and virial come from the once-rounded spectrum
+F16_FORCE, F16_ENERGY, F16_VIRIAL = 1e-3, 2e-4, 2e-4
+
+
+@pytest.mark.parametrize("case", [c for c in SMALL if c[3] in (32, 64, 128)],
+                         ids=[c[0] for c in SMALL if c[3] in (32, 64, 128)])
+def test_step_half_spectrum(P, case):
+    name, nw, L, K, p, beta = case
+    pos, q, box = system(name, nw, L)
+    plan = P.Plan(K, p, beta, max_atoms=len(q), precision="fp32_fixed_half")
+    plan.set_debug(True)
+    res = plan.step(dev(pos), dev(q), box)
+    # spreading is unchanged: the fixed-point grid is still the mirror's
+    assert np.array_equal(plan.debug_grid(0).cpu().numpy(), oracle.mirror_grid(pos, q, box, K, p)[0])
+    ref = oracle.spme(pos, q, box, K, p, beta)
+    compare(res, ref, F16_FORCE, F16_ENERGY, F16_VIRIAL)
+
+
 # a sheared cell: rows a1, a2, a3
 GENERAL_BOX = np.array([[30.0, 0.0, 0.0], [6.0, 28.0, 0.0], [-4.0, 5.0, 27.0]])
 
