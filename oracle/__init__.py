@@ -41,8 +41,11 @@ def _load():
     lib.orc_mirror_spline.argtypes = [i, ctypes.c_float, _fp, _fp]
     lib.orc_ewald_recip.argtypes = [_dp, _dp, i, _dp, d, d, i, _dp, _dp]
     lib.orc_ewald_real.argtypes = [_dp, _dp, i, _dp, d, d, i, d, _dp, _dp, _dp]
+    _ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_ewald_excl.argtypes = [_dp, _dp, i, _dp, d, d, d, _ip, _ip, _dp, _dp]
     for name in ("orc_bspline", "orc_moduli", "orc_fft1d", "orc_fft3d", "orc_spme",
-                 "orc_mirror_grid", "orc_mirror_spline", "orc_ewald_recip", "orc_ewald_real"):
+                 "orc_mirror_grid", "orc_mirror_spline", "orc_ewald_recip", "orc_ewald_real",
+                 "orc_ewald_excl"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -194,3 +197,22 @@ def ewald_real(pos, q, box, beta, nimg=1, rcut=0.0, coulomb=1.0):
                                   int(nimg), float(rcut), _ptr(forces), _ptr(er), _ptr(es)),
            "orc_ewald_real")
     return {"forces": forces, "E_real": float(er[0]), "E_self": float(es[0])}
+
+
+def ewald_excl(pos, q, box, beta, excl_off, excl_idx, rcut=0.0, coulomb=1.0):
+    """Exclusion correction for symmetric CSR exclusion lists."""
+    pos = _f64(pos)
+    N = pos.shape[0]
+    pos = pos.reshape(N, 3)
+    q = _f64(q, (N,))
+    b = _box(box)
+    off = np.ascontiguousarray(excl_off, dtype=np.int32)
+    idx = np.ascontiguousarray(excl_idx, dtype=np.int32)
+    assert off.shape == (N + 1,)
+    forces = np.zeros((N, 3))
+    ee = np.zeros(1)
+    ip = ctypes.POINTER(ctypes.c_int)
+    _check(_load().orc_ewald_excl(_ptr(pos), _ptr(q), N, _ptr(b), float(beta), float(coulomb),
+                                  float(rcut), off.ctypes.data_as(ip), idx.ctypes.data_as(ip),
+                                  _ptr(forces), _ptr(ee)), "orc_ewald_excl")
+    return {"forces": forces, "E_excl": float(ee[0])}

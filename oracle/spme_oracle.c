@@ -631,3 +631,52 @@ int orc_ewald_real(const double *pos, const double *q, int N, const double box[9
   if (e_self) *e_self = -coulomb * beta / sqrt(ORC_PI) * S;
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Exclusion correction of the Ewald sum.  For a pair whose direct     */
+/* interaction is excluded (e.g. atoms of one molecule), the Ewald     */
+/* terms still carry it: erfc(beta r)/r in the real-space sum when     */
+/* r <= rcut, erf(beta r)/r in the reciprocal sum.  The correction     */
+/* removes both for the minimum-image distance r of the pair:          */
+/*   E_excl = -(c/2) sum_i sum_{j in excl(i)} q_i q_j                  */
+/*            [erf(beta r)/r + (r <= rcut ? erfc(beta r)/r : 0)]       */
+/* over symmetric lists (each pair appears in both atoms' lists).      */
+/* Orthorhombic (diagonal) boxes; rcut <= 0 means no cutoff.           */
+/* ------------------------------------------------------------------ */
+int orc_ewald_excl(const double *pos, const double *q, int N, const double box[9],
+                   double beta, double coulomb, double rcut, const int *excl_off,
+                   const int *excl_idx, double *forces, double *e_excl) {
+  if (N < 0 || !(beta > 0.0)) return -1;
+  if (box[1] != 0.0 || box[2] != 0.0 || box[3] != 0.0 || box[5] != 0.0 || box[6] != 0.0 ||
+      box[7] != 0.0)
+    return -1;
+  double L[3] = {box[0], box[4], box[8]};
+  double E = 0.0;
+  if (forces)
+    for (int i = 0; i < 3 * N; ++i) forces[i] = 0.0;
+  for (int i = 0; i < N; ++i) {
+    for (int k = excl_off[i]; k < excl_off[i + 1]; ++k) {
+      int j = excl_idx[k];
+      if (j < 0 || j >= N || j == i) return -1;
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        d[c] = pos[3 * i + c] - pos[3 * j + c];
+        d[c] -= L[c] * nearbyint(d[c] / L[c]);
+      }
+      double r = sqrt(dot3(d, d));
+      int inside = !(rcut > 0.0) || r <= rcut;
+      /* energy of the removed interaction, and -dE/dr of it */
+      double u = inside ? 1.0 / r : erf(beta * r) / r;
+      double du = inside ? -1.0 / (r * r)
+                         : (2.0 * beta / sqrt(ORC_PI) * exp(-beta * beta * r * r) - erf(beta * r) / r) / r;
+      E -= 0.5 * coulomb * q[i] * q[j] * u;
+      if (forces) {
+        /* F_i = -dE/dr_i with E_pair = -c q_i q_j u(r) (counted from i's list and j's) */
+        double a = coulomb * q[i] * q[j] * du / r;
+        for (int c = 0; c < 3; ++c) forces[3 * i + c] += a * d[c];
+      }
+    }
+  }
+  if (e_excl) *e_excl = E;
+  return 0;
+}

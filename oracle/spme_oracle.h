@@ -77,6 +77,14 @@ int orc_ewald_real(const double *pos, const double *q, int N,
                    int nimg, double rcut, double *forces, double *e_real,
                    double *e_self);
 
+/* Exclusion correction: removes, for every excluded pair listed in the
+ * symmetric CSR lists (excl_off[N+1], excl_idx), the erfc/r real-space part
+ * (r <= rcut) and the erf/r reciprocal part of its Ewald interaction at the
+ * minimum-image distance.  Diagonal boxes.  forces may be NULL. */
+int orc_ewald_excl(const double *pos, const double *q, int N, const double box[9],
+                   double beta, double coulomb, double rcut, const int *excl_off,
+                   const int *excl_idx, double *forces, double *e_excl);
+
 #ifdef __cplusplus
 }
 #endif

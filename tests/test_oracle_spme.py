@@ -257,3 +257,59 @@ def test_wigner_simple_cubic_constant(orc):
     xi = 2.0 * L * (rec + rs["E_real"] + rs["E_self"] + background)
     g = GOLD["wigner_simple_cubic"]
     assert abs(xi - g["value"]) <= g["tolerance"]
+
+
+def water_exclusions(n_atoms):
+    """Symmetric CSR lists excluding every pair within a water (O, H, H)."""
+    off, idx = [0], []
+    for i in range(n_atoms):
+        m = i // 3
+        idx += [3 * m + k for k in range(3) if 3 * m + k != i]
+        off.append(len(idx))
+    return np.array(off, dtype=np.int32), np.array(idx, dtype=np.int32)
+
+
+def test_exclusion_correction_of_one_water_is_its_coulomb_energy(orc):
+    # inside the cutoff the correction removes the whole 1/r interaction:
+    # closed form from the TIP3P-like geometry (0.9572 A, 104.52 degrees)
+    pos, q, _ = inputs.water_box(1, 20.0, 3)
+    box = np.diag([20.0] * 3)
+    off, idx = water_exclusions(3)
+    r = orc.ewald_excl(pos, q, box, 0.35, off, idx, rcut=9.0, coulomb=2.0)
+    d_oh = 0.9572
+    d_hh = 2 * d_oh * np.sin(np.radians(104.52 / 2))
+    want = -2.0 * (2 * q[0] * q[1] / d_oh + q[1] * q[2] / d_hh)
+    assert r["E_excl"] == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("rcut", [9.0, 1.2])
+def test_exclusion_forces_are_minus_gradient(orc, rcut):
+    # rcut = 1.2 A puts the H-H pair (1.51 A) outside: its erf branch
+    pos, q, box = inputs.water_box(4, 12.0, 5)
+    off, idx = water_exclusions(len(q))
+    beta, h = 0.4, 1e-6
+    r = orc.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut)
+    for i, c in [(0, 0), (1, 2), (5, 1), (11, 0)]:
+        pp = pos.copy()
+        pp[i, c] += h
+        pm = pos.copy()
+        pm[i, c] -= h
+        fd = -(orc.ewald_excl(pp, q, box, beta, off, idx, rcut=rcut)["E_excl"] -
+               orc.ewald_excl(pm, q, box, beta, off, idx, rcut=rcut)["E_excl"]) / (2 * h)
+        assert r["forces"][i, c] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_total_with_exclusions_is_beta_independent(orc):
+    # excluded pairs inside the cutoff lose 1/r, the one outside loses erf/r
+    # (its erfc/r is already cut); with beta*rcut >= 4.5 the cut real-space
+    # tail is below 1e-8, so the total energy must not depend on beta
+    pos, q, box = inputs.water_box(3, 9.0, 11)
+    off, idx = water_exclusions(len(q))
+    rcut = 1.2  # O-H inside, H-H outside
+    tot = []
+    for beta in (3.8, 4.2):
+        rec = orc.ewald_recip(pos, q, box, beta, 60)["E"]
+        rs = orc.ewald_real(pos, q, box, beta, nimg=1, rcut=rcut)
+        ex = orc.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut)
+        tot.append(rec + rs["E_real"] + rs["E_self"] + ex["E_excl"])
+    assert tot[0] == pytest.approx(tot[1], rel=1e-9)
