@@ -205,6 +205,44 @@ int pme_check(pme_plan *plan, unsigned *flags);
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
 
+/* ------------------------------------------------------------------------
+ * Real-space part of the Ewald sum (the short-range electrostatics beside the
+ * reciprocal pipeline, §II, §V.A): with it, pme_step's energy + E_real +
+ * E_self + E_excl is the full Ewald energy, and the forces add up likewise.
+ *   E_real = (c/2) sum_i sum_{j != i, |r_ij| <= rcut} q_i q_j erfc(beta r_ij)/r_ij
+ *            (minimum image; rcut <= L/3 on every axis)
+ *   E_self = -c beta/sqrt(pi) sum_i q_i^2
+ *   E_excl = -(c/2) sum_i sum_{j in excl(i)} q_i q_j [erf(beta r)/r
+ *            + (r <= rcut ? erfc(beta r)/r : 0)]   (removes excluded pairs
+ *            from both the pair sum and the reciprocal sum)
+ * Forces are -grad of E_real + E_excl.  FP64 throughout; diagonal boxes
+ * only (PME_EUNSUPPORTED otherwise, or when rcut > L/3 on some axis).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace for pme_real with at most max_atoms atoms and
+ * max_cells cells of the neighbour grid (>= 27); 0 for bad arguments. */
+size_t pme_real_workspace_bytes(int max_atoms, int max_cells);
+
+/* One real-space evaluation, enqueued on `stream` (hipStream_t).
+ *   pos, q       device [N][3], [N] doubles (any image)
+ *   box          HOST [9] doubles, diagonal
+ *   beta, rcut   Ewald splitting parameter (1/A) and pair cutoff (A), > 0
+ *   coulomb      Coulomb constant c (0 selects 1.0)
+ *   excl_off     device [N+1] ints, or NULL for no exclusions: atom i's
+ *                excluded partners are excl_idx[excl_off[i] .. excl_off[i+1]);
+ *                the lists must be symmetric and hold indices in [0, N)
+ *   forces       device [N][3] doubles, overwritten (accumulate 0) or added to
+ *   energies     device [3] doubles: E_real, E_self, E_excl (overwritten)
+ *   workspace    device, 256-byte aligned, >= pme_real_workspace_bytes(
+ *                max_atoms, max_cells); the cell grid is the finest with
+ *                edges >= rcut, coarsened to fit max_cells
+ * Cells hold atoms in an order set by atomics, so forces reproduce to FP64
+ * rounding rather than bit for bit. */
+int pme_real(const double *pos, const double *q, int N, const double box[9], double beta,
+             double rcut, double coulomb, const int *excl_off, const int *excl_idx,
+             double *forces, int accumulate, double *energies, void *workspace,
+             size_t workspace_bytes, int max_atoms, int max_cells, void *stream);
+
 /* Human-readable text for a pme_status. */
 const char *pme_strerror(int code);
 

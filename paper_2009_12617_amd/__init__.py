@@ -9,11 +9,14 @@ PyTorch only provides device memory and streams.  Submodules are imported
 lazily so that `paper_2009_12617_amd.inputs` works without torch or a GPU.
 """
 
-__all__ = ["Plan", "Batch", "KERNEL_NAMES"]
+__all__ = ["Plan", "Batch", "KERNEL_NAMES", "RealSpace"]
 
 
 def __getattr__(name):
     if name in ("Plan", "Batch", "KERNEL_NAMES"):
         from . import plan as _plan
         return getattr(_plan, name)
+    if name == "RealSpace":
+        from . import realspace as _rs
+        return _rs.RealSpace
     raise AttributeError(name)

@@ -85,6 +85,10 @@ def load():
     lib.pme_kernel_timing.argtypes = [vp, i]
     lib.pme_kernel_times.restype = i
     lib.pme_kernel_times.argtypes = [vp, dp, i, ctypes.POINTER(ctypes.c_int)]
+    lib.pme_real_workspace_bytes.restype = sz
+    lib.pme_real_workspace_bytes.argtypes = [i, i]
+    lib.pme_real.restype = i
+    lib.pme_real.argtypes = [vp, vp, i, dp, d, d, d, vp, vp, vp, i, vp, vp, sz, i, i, vp]
     _lib = lib
     return lib
 

@@ -25,7 +25,7 @@ COMMON = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["spme_kernels.hip", "spme_api.cpp"]
+SOURCES = ["spme_kernels.hip", "spme_real.hip", "spme_api.cpp"]
 
 
 def _compile(src, verbose):

@@ -122,64 +122,6 @@ __device__ __forceinline__ T pick(const T* a, int i) {
   return v;
 }
 
-// One DPP move of a double within the wavefront (each half moved with the
-// same control); lanes without a source, or outside row_mask, read 0.0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo =
-      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
-  const unsigned hi =
-      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Inclusive prefix sums of V doubles across the 16 lanes of each DPP row
-// (row_shr 1, 2, 4, 8).
-template <int V>
-__device__ __forceinline__ void row_scan_add(double* v) {
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x111, 0xf>(v[c]);
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x112, 0xf>(v[c]);
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x114, 0xf>(v[c]);
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x118, 0xf>(v[c]);
-}
-
-// wave_sums: an inclusive DPP scan of V doubles over the wavefront (rows,
-// then row_bcast 15 and 31); lane 63 ends with the wavefront's sums.
-// block_sums: sums over the block in a fixed order -- wave_sums, then the
-// wavefront sums in wavefront order by a row scan in wavefront 0.  Thread 15 ends with the block sums in v.  Every
-// thread must call it (at most 16 wavefronts); wred needs 16 * 8 doubles; it
-// synchronises once and the caller synchronises before reusing wred.
-template <int V>
-__device__ __forceinline__ void wave_sums(double* v) {
-  row_scan_add<V>(v);
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x142, 0xa>(v[c]);
-#pragma unroll
-  for (int c = 0; c < V; ++c) v[c] += dpp_f64<0x143, 0xc>(v[c]);
-}
-
-template <int V>
-__device__ __forceinline__ void block_sums(double* v, double* wred) {
-  wave_sums<V>(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 63) {
-#pragma unroll
-    for (int c = 0; c < V; ++c) wred[wave * 8 + c] = v[c];
-  }
-  __syncthreads();
-  if (wave == 0) {
-    const int nw = blockDim.x >> 6;
-#pragma unroll
-    for (int c = 0; c < V; ++c) v[c] = lane < nw ? wred[lane * 8 + c] : 0.0;
-    row_scan_add<V>(v);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // k_bin: one chunk of kChunk atoms per workgroup, one atom per thread.  Each
 // atom goes to the bucket of its bin (base z, y slice, head/body); a bucket
@@ -735,7 +677,8 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
       }
     } else {
     constexpr int NIT = (K * C + NT - 1) / NT;
-#pragma unroll(NIT <= 4 ? NIT : 2)
+constexpr int UNR = NIT <= 4 ? NIT : 2;
+#pragma unroll UNR
     for (int it = 0; it < NIT; ++it) {
       const int i = tid + it * NT;
       if ((K * C) % NT != 0 && i >= K * C) break;

@@ -167,3 +167,14 @@ def random_neutral(n, L, seed, qscale=1.0):
     q = rng.uniform(-qscale, qscale, size=n)
     q[-1] = -q[:-1].sum()
     return pos, q, np.diag([float(L)] * 3)
+
+
+def water_exclusions(n_atoms):
+    """Symmetric exclusion lists (CSR offsets [n+1], partners) that exclude
+    every pair inside a water molecule, atoms ordered O, H, H."""
+    off, idx = [0], []
+    for i in range(n_atoms):
+        m = i // 3
+        idx += [3 * m + k for k in range(3) if 3 * m + k != i and 3 * m + k < n_atoms]
+        off.append(len(idx))
+    return np.array(off, dtype=np.int32), np.array(idx, dtype=np.int32)

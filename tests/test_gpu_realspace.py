@@ -1,0 +1,101 @@
+"""GPU real-space Ewald term (pme_real) against the CPU oracle's brute-force
+real-space sum, self term and exclusion correction, and the full Ewald
+energy of a rock-salt lattice on the GPU against the Madelung constant."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2009_12617_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "constants.json")))
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2009_12617_amd as P
+    from paper_2009_12617_amd import _lib
+    _lib.load()
+    return P
+
+
+def dev(a, dtype=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to("cuda")
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("max_cells", [1 << 15, 27])
+@pytest.mark.parametrize("with_excl", [False, True])
+def test_real_space_matches_brute_force(P, with_excl, max_cells):
+    # 400 waters in a 24 A box, rcut 7.9 A (three cells per axis, or the
+    # coarsest grid when max_cells = 27), beta 0.35
+    pos, q, box = I.water_box(400, 24.0, 31)
+    pos[::5] += np.array([24.0, -48.0, 72.0])  # other images
+    beta, rcut, c = 0.35, 7.9, 332.0637
+    rs = P.RealSpace(len(q), max_cells=max_cells)
+    excl = None
+    if with_excl:
+        off, idx = I.water_exclusions(len(q))
+        excl = (dev(off, np.int32), dev(idx, np.int32))
+    f, e = rs(dev(pos), dev(q), box, beta, rcut, exclusions=excl, coulomb=c)
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    # the brute-force sum reaches images |n| <= 1 only, so it is given the
+    # positions wrapped into the cell (the sum is periodic in each position)
+    wrapped = np.mod(pos, 24.0)
+    ref = oracle.ewald_real(wrapped, q, box, beta, nimg=1, rcut=rcut, coulomb=c)
+    want_f = ref["forces"].copy()
+    want_excl = 0.0
+    if with_excl:
+        ex = oracle.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut, coulomb=c)
+        want_f += ex["forces"]
+        want_excl = ex["E_excl"]
+    print(f"force_rel_rms={rel_rms(f, want_f):.2e} E_real={e[0]:.10f} ref={ref['E_real']:.10f}", flush=True)
+    assert rel_rms(f, want_f) <= 1e-11
+    assert e[0] == pytest.approx(ref["E_real"], rel=1e-12)
+    assert e[1] == pytest.approx(ref["E_self"], rel=1e-13)
+    assert e[2] == pytest.approx(want_excl, rel=1e-12, abs=1e-12)
+
+
+def test_real_space_accumulates_and_rejects_bad_geometry(P):
+    from paper_2009_12617_amd._lib import SpmeError
+    pos, q, box = I.water_box(100, 16.0, 32)
+    rs = P.RealSpace(len(q))
+    f0, _ = rs(dev(pos), dev(q), box, 0.4, 5.0)
+    f1 = torch.ones_like(f0)
+    rs(dev(pos), dev(q), box, 0.4, 5.0, forces=f1, accumulate=True)
+    assert torch.allclose(f1, f0 + 1.0, rtol=0, atol=1e-12)
+    with pytest.raises(SpmeError) as ei:
+        rs(dev(pos), dev(q), box, 0.4, 6.0)  # rcut > L/3
+    assert ei.value.code == 2
+    sheared = box.copy()
+    sheared[1, 0] = 1.0
+    with pytest.raises(SpmeError) as ei:
+        rs(dev(pos), dev(q), sheared, 0.4, 5.0)
+    assert ei.value.code == 2
+
+
+@pytest.mark.parametrize("offset", [(0.0, 0.0, 0.0), (0.37, 1.13, 2.71)])
+def test_madelung_constant_on_gpu(P, offset):
+    # full Ewald energy of a 4^3-ion rock-salt lattice with all
+    # three terms on the GPU: reciprocal (FP64 SPME, K = 64, p = 6), real
+    # space (rcut 3.7 A, beta 1.0), self
+    M, r0, beta = 4, 2.8, 1.0
+    pos, q, box = I.rock_salt(M, r0, offset)
+    plan = P.Plan(64, 6, beta, max_atoms=len(q), precision="fp64")
+    _, ev = plan.step(dev(pos), dev(q), box)
+    rs = P.RealSpace(len(q))
+    _, e = rs(dev(pos), dev(q), box, beta, 3.7)
+    E = ev[0].item() + e[0].item() + e[1].item()
+    madelung = -2.0 * E * r0 / len(q)
+    g = GOLD["madelung_nacl"]
+    print(f"madelung={madelung:.9f}", flush=True)
+    assert abs(madelung - g["value"]) <= g["tolerance"]

@@ -259,22 +259,12 @@ def test_wigner_simple_cubic_constant(orc):
     assert abs(xi - g["value"]) <= g["tolerance"]
 
 
-def water_exclusions(n_atoms):
-    """Symmetric CSR lists excluding every pair within a water (O, H, H)."""
-    off, idx = [0], []
-    for i in range(n_atoms):
-        m = i // 3
-        idx += [3 * m + k for k in range(3) if 3 * m + k != i]
-        off.append(len(idx))
-    return np.array(off, dtype=np.int32), np.array(idx, dtype=np.int32)
-
-
 def test_exclusion_correction_of_one_water_is_its_coulomb_energy(orc):
     # inside the cutoff the correction removes the whole 1/r interaction:
     # closed form from the TIP3P-like geometry (0.9572 A, 104.52 degrees)
     pos, q, _ = inputs.water_box(1, 20.0, 3)
     box = np.diag([20.0] * 3)
-    off, idx = water_exclusions(3)
+    off, idx = inputs.water_exclusions(3)
     r = orc.ewald_excl(pos, q, box, 0.35, off, idx, rcut=9.0, coulomb=2.0)
     d_oh = 0.9572
     d_hh = 2 * d_oh * np.sin(np.radians(104.52 / 2))
@@ -286,7 +276,7 @@ def test_exclusion_correction_of_one_water_is_its_coulomb_energy(orc):
 def test_exclusion_forces_are_minus_gradient(orc, rcut):
     # rcut = 1.2 A puts the H-H pair (1.51 A) outside: its erf branch
     pos, q, box = inputs.water_box(4, 12.0, 5)
-    off, idx = water_exclusions(len(q))
+    off, idx = inputs.water_exclusions(len(q))
     beta, h = 0.4, 1e-6
     r = orc.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut)
     for i, c in [(0, 0), (1, 2), (5, 1), (11, 0)]:
@@ -304,7 +294,7 @@ def test_total_with_exclusions_is_beta_independent(orc):
     # (its erfc/r is already cut); with beta*rcut >= 4.5 the cut real-space
     # tail is below 1e-8, so the total energy must not depend on beta
     pos, q, box = inputs.water_box(3, 9.0, 11)
-    off, idx = water_exclusions(len(q))
+    off, idx = inputs.water_exclusions(len(q))
     rcut = 1.2  # O-H inside, H-H outside
     tot = []
     for beta in (3.8, 4.2):
