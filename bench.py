@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--parity-frames", type=int, default=3)
     ap.add_argument("--no-half", action="store_true", help="skip the binary16-spectrum variant")
+    ap.add_argument("--no-real", action="store_true", help="skip the real-space term")
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
@@ -372,6 +373,34 @@ def main():
                 "step_algorithmic_bytes": step_bytes(N, K) - 16 * K * K * kh}
         print(f"# fp32_fixed_half: {ms16 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
+    real = None
+    if not args.no_real:
+        # the real-space term beside the step, same frames: erfc pair sum
+        # (rcut 9 A, beta 0.34: erfc(beta rcut) ~ 1e-5), self term and the
+        # intramolecular exclusions of every water
+        from paper_2009_12617_amd import RealSpace
+        rcut = 9.0
+        rs = RealSpace(N, device=dev)
+        off, idx = I.water_exclusions(N)
+        excl = (torch.from_numpy(off).to(dev), torch.from_numpy(idx).to(dev))
+        fr = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        for t in range(5):
+            rs(d_frames[t % F], d_q, box, w.beta, rcut, exclusions=excl, forces=fr)
+        torch.cuda.synchronize()
+        nrep = 50
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for t in range(nrep):
+            rs(d_frames[t % F], d_q, box, w.beta, rcut, exclusions=excl, forces=fr)
+        stop.record()
+        torch.cuda.synchronize()
+        ms_rs = start.elapsed_time(stop) / nrep
+        nc = int(np.floor(box[0, 0] / rcut))
+        real = {"us_per_eval": ms_rs * 1e3, "rcut_A": rcut, "beta": w.beta, "cells": [nc] * 3,
+                "launches": 6, "what": "pme_real: FP64 erfc pair sum, self term, water exclusions"}
+        print(f"# real space: {ms_rs * 1e3:.1f} us per evaluation", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         from paper_2009_12617_amd import Batch
@@ -452,6 +481,7 @@ def main():
         "step_algorithmic_bytes": step_bytes(N, K),
         "fp64_path": fp64,
         "half_spectrum_path": half,
+        "real_space": real,
         "batched": batched,
         "serving": serving,
         "parity": parity,

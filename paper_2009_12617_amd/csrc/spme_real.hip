@@ -12,9 +12,10 @@
 //                per workgroup (self term)
 //   k_rs_scan    one workgroup: exclusive prefix sum of the counts
 //   k_rs_fill    atoms into cell order (position, charge, original index)
-//   k_rs_pairs   one cell per workgroup: its atoms, one per thread, against
-//                the atoms of the 27 neighbour cells staged in LDS; then each
-//                atom's excluded partners; forces to the caller's order
+//   k_rs_pairs   one cell per workgroup: its atoms, two threads each, against
+//                the atoms of the 27 neighbour cells staged in LDS with their
+//                periodic shifts applied; then each atom's excluded
+//                partners; forces to the caller's order
 //   k_rs_reduce  energies from the per-workgroup rows, in a fixed order
 // Arithmetic is FP64 throughout.  The order of atoms inside a cell depends
 // on atomic ordering, so forces are reproducible to FP64 rounding, not bit
@@ -31,7 +32,8 @@
 namespace spme {
 namespace {
 
-constexpr int kRsThreads = 256;     // home atoms per pass of a cell workgroup
+constexpr int kRsThreads = 256;     // threads of a cell workgroup
+constexpr int kRsHome = kRsThreads / 2;  // home atoms per pass (two threads each)
 constexpr int kRsStage = 2048;      // neighbour atoms staged in LDS per pass
 constexpr int kRsCountThreads = 256;
 constexpr int kRsScanThreads = 1024;
@@ -141,15 +143,33 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
   __shared__ double4 stage[kRsStage];
   __shared__ int sidx[kRsStage];
   __shared__ int nb_start[27], nb_pre[28];
+  __shared__ double nb_shift[27][3];
+  __shared__ double fpart[kRsHome][3];
   __shared__ double wred[16 * 8];
   const int tid = threadIdx.x;
   const int cell = blockIdx.x;
   const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
   if (tid < 27) {
-    const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
-    const int x = (cx + dx + a.nc[0]) % a.nc[0], y = (cy + dy + a.nc[1]) % a.nc[1],
-              z = (cz + dz + a.nc[2]) % a.nc[2];
-    const int nbc = (z * a.nc[1] + y) * a.nc[0] + x;
+    // neighbour cell and the periodic shift that brings its atoms next to
+    // this cell (at least three cells per axis: each neighbour appears once)
+    const int dd[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+    const int cc[3] = {cx, cy, cz};
+    int n3[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int v = cc[d] + dd[d];
+      double sh = 0.0;
+      if (v < 0) {
+        v += a.nc[d];
+        sh = -a.L[d];
+      } else if (v >= a.nc[d]) {
+        v -= a.nc[d];
+        sh = a.L[d];
+      }
+      n3[d] = v;
+      nb_shift[tid][d] = sh;
+    }
+    const int nbc = (n3[2] * a.nc[1] + n3[1]) * a.nc[0] + n3[0];
     nb_start[tid] = (int)a.start[nbc];
     nb_pre[tid + 1] = (int)(a.start[nbc + 1] - a.start[nbc]);
   }
@@ -163,8 +183,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
   const int h0 = (int)a.start[cell], h1 = (int)a.start[cell + 1];
   const double two_over_sqrtpi = 1.12837916709551257390;
   double e_pair = 0.0, e_excl = 0.0;
-  for (int hb = h0; hb < h1; hb += kRsThreads) {
-    const int h = hb + tid;
+  // each home atom takes two threads, which split its candidates (even and
+  // odd staged entries); their forces are added in a fixed order
+  const int slot = tid % kRsHome, part = tid / kRsHome;
+  for (int hb = h0; hb < h1; hb += kRsHome) {
+    const int h = hb + slot;
     const bool mine = h < h1;
     double4 ri = make_double4(0.0, 0.0, 0.0, 0.0);
     int ii = -1;
@@ -181,16 +204,15 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
         int k = 0;
         while (nb_pre[k + 1] <= g) ++k;
         const int src = nb_start[k] + (g - nb_pre[k]);
-        stage[t] = a.rec[src];
+        const double4 r = a.rec[src];
+        stage[t] = make_double4(r.x + nb_shift[k][0], r.y + nb_shift[k][1], r.z + nb_shift[k][2], r.w);
         sidx[t] = a.ridx[src];
       }
       __syncthreads();
       if (mine) {
-        for (int t = 0; t < sn; ++t) {
+        for (int t = part; t < sn; t += 2) {
           const double4 rj = stage[t];
-          double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
-#pragma unroll
-          for (int c = 0; c < 3; ++c) d[c] -= a.L[c] * rint(d[c] * a.invL[c]);
+          const double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
           const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           if (r2 <= a.rc2 && sidx[t] != ii) {
             const double r = sqrt(r2), br = a.beta * r;
@@ -204,7 +226,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
         }
       }
     }
-    if (mine && a.excl_off != nullptr) {
+    if (mine && part == 0 && a.excl_off != nullptr) {
       // excluded partners: remove the erfc/r the pair sum took (inside the
       // cutoff) and the erf/r the reciprocal sum carries
       const double* pi = a.pos + 3 * (size_t)ii;
@@ -232,16 +254,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
         for (int c = 0; c < 3; ++c) f[c] += g * d[c];
       }
     }
-    if (mine) {
+    __syncthreads();
+    if (part == 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) fpart[slot][c] = f[c];
+    }
+    __syncthreads();
+    if (mine && part == 0) {
       double* out = a.forces + 3 * (size_t)ii;
-      if (a.accumulate) {
-        out[0] += f[0];
-        out[1] += f[1];
-        out[2] += f[2];
-      } else {
-        out[0] = f[0];
-        out[1] = f[1];
-        out[2] = f[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double fc = f[c] + fpart[slot][c];
+        out[c] = a.accumulate ? out[c] + fc : fc;
       }
     }
   }
