@@ -33,7 +33,7 @@ enum State { kCreated = 0, kSpread = 1, kSolved = 2, kDirty = 3 };
 }  // namespace
 
 struct pme_plan {
-  int K = 0, order = 0, precision = 0, frac_bits = 32, max_atoms = 0;
+  int K1 = 0, K2 = 0, K3 = 0, order = 0, precision = 0, frac_bits = 32, max_atoms = 0;
   double beta = 0.0, coulomb = 1.0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -130,9 +130,9 @@ const char* pme_strerror(int code) {
 }
 
 size_t pme_workspace_bytes(int K1, int K2, int K3, int order, int max_atoms, int precision) {
-  if (K1 != K2 || K2 != K3 || max_atoms < 0 || max_atoms > kMaxAtoms) return 0;
+  if (max_atoms < 0 || max_atoms > kMaxAtoms) return 0;
   Layout L;
-  if (!spme::layout_for(K1, order, max_atoms, precision, &L)) return 0;
+  if (!spme::layout_for(K1, K2, K3, order, max_atoms, precision, &L)) return 0;
   return L.total;
 }
 
@@ -149,18 +149,19 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   if (frac_bits == 0) frac_bits = 32;
   if (frac_bits < 16 || frac_bits > 40) return PME_EINVAL;
   if (coulomb == 0.0) coulomb = 1.0;
-  if (K1 != K2 || K2 != K3 || !spme::grid_supported(K1) || (order != 4 && order != 6) ||
-      max_atoms > kMaxAtoms)
+  if (!spme::grid_supported(K1, K2, K3) || (order != 4 && order != 6) || max_atoms > kMaxAtoms)
     return PME_EUNSUPPORTED;
   Layout L;
-  if (!spme::layout_for(K1, order, max_atoms, precision, &L)) return PME_EUNSUPPORTED;
+  if (!spme::layout_for(K1, K2, K3, order, max_atoms, precision, &L)) return PME_EUNSUPPORTED;
   if (workspace == nullptr || workspace_bytes < L.total ||
       (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
     return PME_EWORKSPACE;
 
   pme_plan* p = new (std::nothrow) pme_plan();
   if (p == nullptr) return PME_EDEVICE;
-  p->K = K1;
+  p->K1 = K1;
+  p->K2 = K2;
+  p->K3 = K3;
   p->order = order;
   p->precision = precision;
   p->frac_bits = frac_bits;
@@ -172,38 +173,39 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   p->stream = static_cast<hipStream_t>(stream);
   p->lay = L;
 
-  // Tables: moduli for the three axes (cubic grid: the same K), twiddles
-  // exp(-2 pi i k / K) rounded once from FP64.
-  const int K = K1;
-  p->bsq.resize(3 * (size_t)K);
-  moduli(order, K, p->bsq.data());
-  std::memcpy(p->bsq.data() + K, p->bsq.data(), sizeof(double) * K);
-  std::memcpy(p->bsq.data() + 2 * K, p->bsq.data(), sizeof(double) * K);
+  // Tables per axis, x then y then z: moduli |b_a(m)|^2 and twiddles
+  // exp(-2 pi i k / K_a), rounded once from FP64.
+  const int Ks[3] = {K1, K2, K3};
+  const int ksum = K1 + K2 + K3;
   const double pi = 3.14159265358979323846;
-  p->tw64.resize(2 * (size_t)K);
-  for (int k = 0; k < K; ++k) {
-    const double ang = 2.0 * pi * (double)k / (double)K;
-    p->tw64[2 * k] = std::cos(ang);
-    p->tw64[2 * k + 1] = -std::sin(ang);
+  p->bsq.resize((size_t)ksum);
+  p->tw64.resize(2 * (size_t)ksum);
+  for (int ax = 0, off = 0; ax < 3; off += Ks[ax], ++ax) {
+    moduli(order, Ks[ax], p->bsq.data() + off);
+    for (int k = 0; k < Ks[ax]; ++k) {
+      const double ang = 2.0 * pi * (double)k / (double)Ks[ax];
+      p->tw64[2 * (off + k)] = std::cos(ang);
+      p->tw64[2 * (off + k) + 1] = -std::sin(ang);
+    }
   }
-  p->tw32.resize(2 * (size_t)K);
-  for (int i = 0; i < 2 * K; ++i) p->tw32[i] = (float)p->tw64[i];
+  p->tw32.resize(2 * (size_t)ksum);
+  for (int i = 0; i < 2 * ksum; ++i) p->tw32[i] = (float)p->tw64[i];
 
-  hipError_t e = spme::prepare_kernels(K, order, precision);
+  hipError_t e = spme::prepare_kernels(K1, K2, K3, order, precision);
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ctrl, 0, 64 * sizeof(unsigned), p->stream);
   // bucket and overflow counts start at zero; each step's convolution
   // clears them again for the next
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.bcnt, 0, L.bcnt2 - L.bcnt, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ovf, 0, 4 * sizeof(unsigned), p->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * 3 * K,
+    e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * ksum,
                        hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) {
     if (precision != PME_FP64)
-      e = hipMemcpyAsync(p->ws + L.tw, p->tw32.data(), sizeof(float) * 2 * K,
+      e = hipMemcpyAsync(p->ws + L.tw, p->tw32.data(), sizeof(float) * 2 * ksum,
                          hipMemcpyHostToDevice, p->stream);
     else
-      e = hipMemcpyAsync(p->ws + L.tw, p->tw64.data(), sizeof(double) * 2 * K,
+      e = hipMemcpyAsync(p->ws + L.tw, p->tw64.data(), sizeof(double) * 2 * ksum,
                          hipMemcpyHostToDevice, p->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -212,7 +214,9 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
     return PME_EDEVICE;
   }
   Args& a = p->cur;
-  a.K = K;
+  a.K1 = K1;
+  a.K2 = K2;
+  a.K3 = K3;
   a.order = order;
   a.precision = precision;
   a.frac_bits = frac_bits;
@@ -394,7 +398,7 @@ int pme_bind(pme_plan* p, const double* pos, const double* q, int N, const doubl
              double* forces, int accumulate, double* ev) {
   if (p == nullptr) return PME_EINVAL;
   if (N > 0 && forces == nullptr) return PME_EINVAL;
-  Args b = p->cur;  // plan constants (K, order, precision, tables, layout)
+  Args b = p->cur;  // plan constants (grid, order, precision, tables, layout)
   int rc = set_inputs(p, b, pos, q, N, box);
   if (rc != PME_OK) return rc;
   b.forces = forces;
@@ -415,21 +419,24 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     if (!plans[i]->is_bound) return PME_ESTATE;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // groups of at most kMaxBatch plans sharing (precision, K, order)
+  // groups of at most kMaxBatch plans sharing (precision, grid, order)
   std::vector<std::vector<int>> groups;
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const Args &a = plans[x]->bound, &b = plans[y]->bound;
     if (a.precision != b.precision) return a.precision < b.precision;
-    if (a.K != b.K) return a.K < b.K;
+    if (a.K1 != b.K1) return a.K1 < b.K1;
+    if (a.K2 != b.K2) return a.K2 < b.K2;
+    if (a.K3 != b.K3) return a.K3 < b.K3;
     return a.order < b.order;
   });
   for (int i : order) {
     const Args& a = plans[i]->bound;
     if (!groups.empty()) {
       const Args& g = plans[groups.back()[0]]->bound;
-      if (g.precision == a.precision && g.K == a.K && g.order == a.order &&
+      if (g.precision == a.precision && g.K1 == a.K1 && g.K2 == a.K2 && g.K3 == a.K3 &&
+          g.order == a.order &&
           (int)groups.back().size() < spme::kMaxBatch) {
         groups.back().push_back(i);
         continue;
@@ -489,13 +496,13 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
 
 size_t pme_debug_grid_bytes(pme_plan* p, int which) {
   if (p == nullptr) return 0;
-  const size_t K = p->K, kh = K / 2 + 1;
+  const size_t n = (size_t)p->K1 * p->K2 * p->K3, kh = (size_t)p->K1 / 2 + 1;
   const size_t real = p->precision != PME_FP64 ? 4 : 8;
   const size_t spec_cpx = p->precision == PME_FP32_FIXED_HALF ? 4 : 2 * real;
   switch (which) {
-    case 0: return K * K * K * 8;
-    case 1: return K * K * kh * spec_cpx;
-    case 2: return K * K * K * real;
+    case 0: return n * 8;
+    case 1: return (size_t)p->K2 * p->K3 * kh * spec_cpx;
+    case 2: return n * real;
     default: return 0;
   }
 }
@@ -504,7 +511,7 @@ int pme_debug_grid(pme_plan* p, int which, void* dst) {
   if (p == nullptr || dst == nullptr) return PME_EINVAL;
   const size_t bytes = pme_debug_grid_bytes(p, which);
   if (bytes == 0) return PME_EINVAL;
-  const size_t K = p->K;
+  const size_t K1 = p->K1;
   const size_t real = p->precision != PME_FP64 ? 4 : 8;
   hipError_t e;
   switch (which) {
@@ -523,8 +530,8 @@ int pme_debug_grid(pme_plan* p, int which, void* dst) {
       a.reduce_ev = 0;
       e = spme::launch_inv_x(a, p->stream);
       if (e != hipSuccess) break;
-      e = hipMemcpy2DAsync(dst, K * real, p->ws + p->lay.phi + (p->order - 1) * real,
-                           (size_t)p->lay.phi_pitch * real, K * real, K * K,
+      e = hipMemcpy2DAsync(dst, K1 * real, p->ws + p->lay.phi + (p->order - 1) * real,
+                           (size_t)p->lay.phi_pitch * real, K1 * real, (size_t)p->K2 * p->K3,
                            hipMemcpyDeviceToDevice, p->stream);
       break;
     }

@@ -9,26 +9,27 @@ namespace spme {
 
 constexpr int kChunk = 1024;         // atoms per binning workgroup
 constexpr int kBinThreads = 1024;    // one atom per thread
-constexpr int kMaxBins = 2048;       // (z, y slice, head/body) bins: 2 K nq <= 2048
+constexpr int kMaxBins = 2048;       // (z, y slice, head/body) bins: 2 K3 nq <= 2048
 constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
 constexpr int kPlaneThreads = 512;   // one z-plane per workgroup (debug potential copy)
 constexpr int kInterpThreads = 512;  // one (z-plane, y slice) bin per workgroup
 constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kNumKernels = 4;       // bin, spread+x, yz convolution, inverse x + interpolation
 
-// y slices per z-plane (rows per slice >= 8 > p - 1, so an atom's support
-// reaches at most one slice below its own); FP64 at K = 128 uses narrower
-// slices so that the interpolation tile fits in LDS.
-__host__ __device__ constexpr int nq_of(int K, bool fixed) {
-  return (!fixed && K == 128) ? 8 : K >= 32 ? 4 : K / 8;
+// y slices per z-plane for K2 points along y (rows per slice >= 8 > p - 1,
+// so an atom's support reaches at most one slice below its own); FP64 at
+// K2 = 128 uses narrower slices so that the interpolation tile fits in LDS.
+__host__ __device__ constexpr int nq_of(int K2, bool fixed) {
+  return (!fixed && K2 == 128) ? 8 : K2 >= 32 ? 4 : K2 / 8;
 }
 __host__ __device__ constexpr int phi_pitch_of(int K, int order) {
   return (K + order - 1 + 3) / 4 * 4;
 }
-// Records per bucket: twice the mean number of atoms per (z, slice) plus a
-// margin; fuller buckets spill to the overflow list.
-__host__ __device__ constexpr int bucket_cap(int K, int nq, int max_atoms) {
-  return (int)(((2 * (long long)max_atoms / (K * nq) + 64 + 31) / 32) * 32);
+// Records per bucket: twice the mean number of atoms per (z-plane, slice)
+// of a grid with K3 planes, plus a margin; fuller buckets spill to the
+// overflow list.
+__host__ __device__ constexpr int bucket_cap(int K3, int nq, int max_atoms) {
+  return (int)(((2 * (long long)max_atoms / (K3 * nq) + 64 + 31) / 32) * 32);
 }
 
 // Sorted atom record of the FP32/fixed path (32 bytes): packed base grid
@@ -54,18 +55,18 @@ struct RecD {
 // Byte offsets of the workspace regions (each 256-byte aligned).
 struct Layout {
   size_t ctrl;     // unsigned[64]: [0] sticky flags
-  size_t bsq;      // double[3][K]: squared B-spline moduli per axis
-  size_t tw;       // complex[K]: exp(-2 pi i k/K), float2 or double2
-  size_t bcnt;     // unsigned[2 K nq]: atoms binned so far per bucket (zero between steps)
-  size_t bcnt2;    // unsigned[2 K nq]: this step's counts, kept for the interpolation
+  size_t bsq;      // double[K1 + K2 + K3]: squared B-spline moduli per axis, x then y then z
+  size_t tw;       // complex[K1 + K2 + K3]: exp(-2 pi i k/K_a) per axis, float2 or double2
+  size_t bcnt;     // unsigned[2 K3 nq]: atoms binned so far per bucket (zero between steps)
+  size_t bcnt2;    // unsigned[2 K3 nq]: this step's counts, kept for the interpolation
   size_t ovf;      // unsigned[4]: [0] overflow records so far, [1] this step's, kept
   size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
-  size_t rec;      // records [2 K nq][cap] (RecF or RecD): one bucket per bin
+  size_t rec;      // records [2 K3 nq][cap] (RecF or RecD): one bucket per bin
   size_t orec;     // records [max_atoms]: atoms that found their bucket full
-  size_t spec;     // complex[K/2+1][K][K] half spectrum, columns [x'][z][y]
-  size_t phi;      // real[K][K][phi_pitch]: potential rows with a (p-1) wrap halo in front
+  size_t spec;     // complex[K1/2+1][K3][K2] half spectrum, columns [x'][z][y]
+  size_t phi;      // real[K3][K2][phi_pitch]: potential rows with a (p-1) wrap halo in front
   size_t partial;  // double[partial_rows][8]: energy/virial partial sums
-  size_t dbg;      // int64 or double [K][K][K]: charge-grid copy (debug)
+  size_t dbg;      // int64 or double [K3][K2][K1]: charge-grid copy (debug)
   size_t args;     // Args: device copy of the bound step arguments (batched runs)
   size_t total;
   int n_chunks_max;
@@ -76,7 +77,8 @@ struct Layout {
 };
 
 struct Args {
-  int K, order, precision, frac_bits;
+  int K1, K2, K3;  // grid points along x, y, z
+  int order, precision, frac_bits;
   int N, n_chunks;
   int accumulate, keep_grid;
   int reduce_ev;  // the last launch's extra workgroup adds the energy/virial rows
@@ -93,7 +95,7 @@ struct Args {
 };
 
 // Batched launches: device copies of the Args of up to kMaxBatch systems of
-// one (precision, K, order) group; workgroup (x, y) works on system y.
+// one (precision, grid, order) group; workgroup (x, y) works on system y.
 constexpr int kMaxBatch = 128;
 struct BatchArgs {
   int n;
@@ -105,11 +107,11 @@ struct Timing {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
-bool grid_supported(int K);
-bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay);
+bool grid_supported(int K1, int K2, int K3);
+bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision, Layout* lay);
 
 // Raise dynamic-LDS limits of the kernels a plan will launch.
-hipError_t prepare_kernels(int K, int order, int precision);
+hipError_t prepare_kernels(int K1, int K2, int K3, int order, int precision);
 
 hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t = Timing(),
                       const BatchArgs* bt = nullptr);

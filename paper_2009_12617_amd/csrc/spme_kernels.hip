@@ -92,8 +92,15 @@ struct PDouble {
   static constexpr bool fixed = false;
 };
 
-// Row pitch of an LDS grid tile in 8-byte units.  Fixed point: at least K
-// int64 values per row (the half spectrum of K/2+1 float2 fits in place).
+// Grid shape as a type: K1, K2, K3 points along x, y, z.
+template <int A, int B, int C>
+struct Grid {
+  static constexpr int K1 = A, K2 = B, K3 = C;
+};
+
+// Row pitch of an LDS grid tile (one x row of K points) in 8-byte units.
+// Fixed point: at least K int64 values per row (the half spectrum of K/2+1
+// float2 fits in place).
 // FP64: room for K/2+1 double2.  The padding skews rows across LDS banks.
 template <class P>
 __host__ __device__ constexpr int tile_pitch(int K) {
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   __shared__ int hist[kMaxBins];
   __shared__ double wred[16 * 8];
   TRACE(0, 0);
-  const int K = a.K, nq = nq_of(a.K, P::fixed), rows = K / nq, nbins = 2 * K * nq;
+  const int nq = nq_of(a.K2, P::fixed), rows = a.K2 / nq, nbins = 2 * a.K3 * nq;
   const int cap = a.lay.cap;
   const int c = blockIdx.x, tid = threadIdx.x;
   unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
@@ -164,10 +171,16 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
     const double x3[3] = {a.pos[3 * (size_t)i], a.pos[3 * (size_t)i + 1], a.pos[3 * (size_t)i + 2]};
     if (!a.triclinic) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= grid_coord(x3[d], a.invL[d], K, &g[d], &w[d]);
+      for (int d = 0; d < 3; ++d) {
+        const int Kd = d == 0 ? a.K1 : d == 1 ? a.K2 : a.K3;
+        ok &= grid_coord(x3[d], a.invL[d], Kd, &g[d], &w[d]);
+      }
     } else {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= grid_coord_s(frac_general(x3, a.rec + 3 * d), K, &g[d], &w[d]);
+      for (int d = 0; d < 3; ++d) {
+        const int Kd = d == 0 ? a.K1 : d == 1 ? a.K2 : a.K3;
+        ok &= grid_coord_s(frac_general(x3, a.rec + 3 * d), Kd, &g[d], &w[d]);
+      }
     }
     double qi = a.q[i];
     ok &= (qi - qi == 0.0);  // finite
@@ -219,17 +232,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
 // k_spread_x: charge spreading of one y slice of one z-plane, then the x
 // real-to-complex FFT of its rows.
 // ---------------------------------------------------------------------------
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr size_t spread_lds_bytes() {
-  return (size_t)(K / nq_of(K, P::fixed)) * tile_pitch<P>(K) * 8 +
-         (size_t)K * sizeof(cplx<typename P::real>) + 64 * sizeof(int);
+  return (size_t)(G::K2 / nq_of(G::K2, P::fixed)) * tile_pitch<P>(G::K1) * 8 +
+         (size_t)G::K1 * sizeof(cplx<typename P::real>) + 64 * sizeof(int);
 }
 
 // Contributions of one atom to the plane of support point jz (z order) of
 // the tile holding rows y0 .. y0+R-1: its p x p (y, x) points in the slice,
 // in the product order z, y, x; fixed point: rounded to integers and added
 // with 64-bit LDS atomics.
-template <class P, int K, int ORDER, int R, int PITCH>
+template <class P, int K1, int K2, int ORDER, int R, int PITCH>
 __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typename P::rec& r, int jz,
                                             int y0, double scale) {
   using T = typename P::real;
@@ -243,7 +256,7 @@ __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typenam
 #pragma unroll
   for (int jx = 0; jx < ORDER; ++jx) {
     const int x = gx - ORDER + 1 + jx;
-    xs[jx] = x < 0 ? x + K : x;
+    xs[jx] = x < 0 ? x + K1 : x;
   }
   if constexpr (P::fixed) {
 #pragma clang fp contract(off)
@@ -251,7 +264,7 @@ __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typenam
 #pragma unroll
     for (int jy = 0; jy < ORDER; ++jy) {
       int dy = gy - ORDER + 1 + jy - y0;
-      if (dy < 0) dy += K;
+      if (dy < 0) dy += K2;
       if (dy >= R) continue;
       Acc* row = tile + dy * PITCH;
       const float cy = cz * ty[jy];
@@ -264,7 +277,7 @@ __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typenam
 #pragma unroll
     for (int jy = 0; jy < ORDER; ++jy) {
       int dy = gy - ORDER + 1 + jy - y0;
-      if (dy < 0) dy += K;
+      if (dy < 0) dy += K2;
       if (dy >= R) continue;
       Acc* row = tile + dy * PITCH;
       const double cy = cz * ty[jy];
@@ -274,26 +287,27 @@ __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typenam
   }
 }
 
-template <class P, int K, int ORDER, bool BATCH>
+template <class P, class G, int ORDER, bool BATCH>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   using Acc = typename P::acc;
   using Rec = typename P::rec;
-  constexpr int M = K / 2, KH = K / 2 + 1;
-  constexpr int NQ = nq_of(K, P::fixed), R = K / NQ;
-  constexpr int PITCH = tile_pitch<P>(K);
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr int M = K1 / 2, KH = K1 / 2 + 1;
+  constexpr int NQ = nq_of(K2, P::fixed), R = K2 / NQ;
+  constexpr int PITCH = tile_pitch<P>(K1);
   constexpr int NBK = 3 * ORDER;  // buckets read per tile
   extern __shared__ __align__(16) unsigned char smem[];
   Acc* tile = reinterpret_cast<Acc*>(smem);
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + (size_t)R * PITCH * 8);
-  int* bk_pre = reinterpret_cast<int*>(tw + K);  // [NBK + 1] item offsets
+  int* bk_pre = reinterpret_cast<int*>(tw + K1);  // [NBK + 1] item offsets
   int* bk_base = bk_pre + 24;                     // [NBK] first record
   int* bk_n = bk_base + 20;                       // [NBK] counts, then the overflow count
 
   TRACE(1, 0);
-  static_assert((K * NQ) % kXcds == 0, "spreading tiles do not split over the XCDs");
-  const int tile_id = xcd_local(blockIdx.x, K * NQ);
+  static_assert((K3 * NQ) % kXcds == 0, "spreading tiles do not split over the XCDs");
+  const int tile_id = xcd_local(blockIdx.x, K3 * NQ);
   const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
   const int tid = threadIdx.x;
   const int cap = a.lay.cap;
@@ -301,7 +315,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
   const Rec* orec = reinterpret_cast<const Rec*>(a.ws + a.lay.orec);
   // The tile (rows y0 .. y0+R-1 of plane z) receives the atoms whose base z
-  // index b lies in z .. z+p-1 (mod K) -- for b = z + j the plane is support
+  // index b lies in z .. z+p-1 (mod K3) -- for b = z + j the plane is support
   // point jz = p-1-j -- and whose base y index lies in this slice, or in the
   // head (first p-1 rows) of the next slice: an atom touches rows
   // g_y-p+1 .. g_y.  Bucket k = 3j + d: d = 0 own head, 1 own body, 2 next
@@ -309,7 +323,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   if (tid < NBK) {
     const int j = tid / 3, d = tid - 3 * j;
     int bz = z + j;
-    if (bz >= K) bz -= K;
+    if (bz >= K3) bz -= K3;
     int by = qs + (d == 2 ? 1 : 0);
     if (by >= NQ) by -= NQ;
     const int b = (bz * NQ + by) * 2 + (d == 1 ? 1 : 0);
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
                          (unsigned)a.lay.orec_max);
   }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  for (int i = tid; i < K; i += kSpreadThreads) tw[i] = twg[i];
+  for (int i = tid; i < K1; i += kSpreadThreads) tw[i] = twg[i];
   for (int i = tid; i < R * PITCH; i += kSpreadThreads) tile[i] = Acc(0);
   const double scale = ldexp(1.0, a.frac_bits);
   __syncthreads();
@@ -363,7 +377,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
       if (jz[u] >= 0) r[u] = rec[idx[u]];
 #pragma unroll
     for (int u = 0; u < kItems; ++u)
-      if (jz[u] >= 0) spread_atom<P, K, ORDER, R, PITCH>(tile, r[u], jz[u], y0, scale);
+      if (jz[u] >= 0) spread_atom<P, K1, K2, ORDER, R, PITCH>(tile, r[u], jz[u], y0, scale);
   }
   // atoms of full buckets: the whole overflow list, each atom taken if it
   // belongs to this tile
@@ -372,19 +386,19 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
     const Rec r = orec[o];
     const int gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
     int j = gz - z;
-    if (j < 0) j += K;
+    if (j < 0) j += K3;
     const int sl = gy / R;
     int nsl = qs + 1;
     if (nsl >= NQ) nsl -= NQ;
     if (j < ORDER && (sl == qs || (sl == nsl && gy - sl * R < ORDER - 1)))
-      spread_atom<P, K, ORDER, R, PITCH>(tile, r, ORDER - 1 - j, y0, scale);
+      spread_atom<P, K1, K2, ORDER, R, PITCH>(tile, r, ORDER - 1 - j, y0, scale);
   }
   __syncthreads();
   TRACE(1, 2);
 
   if (a.keep_grid) {
-    Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + ((size_t)z * K + y0) * K;
-    for (int i = tid; i < R * K; i += kSpreadThreads) dbg[i] = tile[(i / K) * PITCH + (i % K)];
+    Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + ((size_t)z * K2 + y0) * K1;
+    for (int i = tid; i < R * K1; i += kSpreadThreads) dbg[i] = tile[(i / K1) * PITCH + (i % K1)];
     __syncthreads();  // the x transform below overwrites the tile in place
   }
 
@@ -397,7 +411,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
       // int64 -> float in place: x_j at float slot j, so the row reads as the
       // packed complex sequence z_n = x_{2n} + i x_{2n+1}
       const double inv_scale = ldexp(1.0, -a.frac_bits);
-      constexpr int PER = K / TM;
+      constexpr int PER = K1 / TM;
       float v[PER];
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
@@ -410,19 +424,19 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
       lds_order();
     }
     fft_pencil<T, M, -1>(row, 1, l, tw, 2);
-    r2c_post<T, K>(row, l, tw);
+    r2c_post<T, K1>(row, l, tw);
   }
   __syncthreads();
   TRACE(1, 3);
 
   // half spectrum columns [x'][z][y]: runs of R rows per x'
   using S = typename P::spec;
-  S* spec = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)z * K + y0;
+  S* spec = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)z * K2 + y0;
   constexpr int PC = P::fixed ? PITCH : PITCH / 2;
   const cplx<T>* tc = reinterpret_cast<const cplx<T>*>(tile);
   for (int i = tid; i < R * KH; i += kSpreadThreads) {
     const int x = i / R, y = i - x * R;
-    spec_st(&spec[(size_t)x * K * K + y], tc[y * PC + x]);
+    spec_st(&spec[(size_t)x * K3 * K2 + y], tc[y * PC + x]);
   }
   TRACE(1, 15);
 }
@@ -433,73 +447,78 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
 // energy/virial partials, inverse z and y transforms (§III.A.2: the slab
 // transforms, the multiplication by Green's function data and the inverse
 // transforms, with the two corner turns folded into this one column).  When
-// the K x K column does not fit in LDS (FP64, K = 128) it is staged through
+// the K3 x K2 column does not fit in LDS (FP64, 128^3) it is staged through
 // the workspace in halves.
 // ---------------------------------------------------------------------------
-// Threads per column: 1024, or 512 where the FP64 radix stages of K = 128
-// need more than the 128 registers a 1024-thread workgroup leaves per lane.
-template <class P, int K>
+// Threads per column: 1024, or 512 where the FP64 radix stages of 128-point
+// pencils need more than the 128 registers a 1024-thread workgroup leaves
+// per lane.
+template <class P, class G>
 __host__ __device__ constexpr int conv_threads() {
-  return (sizeof(typename P::real) == 8 && K >= 128) ? 512 : 1024;
+  return (sizeof(typename P::real) == 8 && (G::K2 >= 128 || G::K3 >= 128)) ? 512 : 1024;
 }
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr size_t conv_tables_bytes() {
-  // twiddles, per-axis factors, one energy/virial row per wavefront
-  return (size_t)K * sizeof(cplx<typename P::real>) + 3 * (size_t)K * sizeof(double) +
-         16 * 8 * sizeof(double);
+  // y and z twiddles, per-axis factors, one energy/virial row per wavefront
+  return (size_t)(G::K2 + G::K3) * sizeof(cplx<typename P::real>) +
+         (size_t)(G::K1 + G::K2 + G::K3) * sizeof(double) + 16 * 8 * sizeof(double);
 }
-// Row pitch (complex elements) of the column in LDS: rows are y pencils,
-// columns z pencils; chosen with a bank model of the Stockham stages over
-// both (64-lane wavefront, 4-byte banks).
-template <class P, int K>
-__host__ __device__ constexpr int conv_pitch() {
+// Row pitch (complex elements) of the column in LDS: rows are y pencils of
+// K points, columns z pencils; chosen with a bank model of the Stockham
+// stages over both (64-lane wavefront, 4-byte banks).
+template <class P>
+__host__ __device__ constexpr int conv_pitch(int K) {
   return sizeof(typename P::real) == 4
              ? (K == 16 ? 18 : K == 32 ? 38 : K == 48 ? 50 : K == 64 ? 71 : K == 96 ? 100
                 : K == 128 ? 135 : K + 1)
              : (K == 64 ? 71 : K == 96 ? 102 : K == 128 ? 131 : K + 1);
 }
-// z-planes (y pass) or y rows (z pass) per LDS chunk
-template <class P, int K>
-__host__ __device__ constexpr int conv_chunk() {
-  return (size_t)K * conv_pitch<P, K>() * sizeof(cplx<typename P::real>) +
-                     conv_tables_bytes<P, K>() <= kMaxLds
-             ? K
-             : K / 2;
+// LDS chunks of the column: 1 when all K3 rows fit, else 2 (halves of the
+// z-planes in the y passes, halves of the y rows in the z pass)
+template <class P, class G>
+__host__ __device__ constexpr int conv_nchunks() {
+  return (size_t)G::K3 * conv_pitch<P>(G::K2) * sizeof(cplx<typename P::real>) +
+                     conv_tables_bytes<P, G>() <= kMaxLds
+             ? 1
+             : 2;
 }
 // z pass row pitch when the column is staged in chunks
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr int conv_zpitch() {
-  return conv_chunk<P, K>() == K ? conv_pitch<P, K>() : conv_chunk<P, K>() + 3;
+  return conv_nchunks<P, G>() == 1 ? conv_pitch<P>(G::K2) : G::K2 / 2 + 3;
 }
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr size_t conv_buf_bytes() {
-  constexpr size_t C = conv_chunk<P, K>();
-  constexpr size_t ny = C * conv_pitch<P, K>(), nz = (size_t)K * conv_zpitch<P, K>();
+  constexpr size_t NC = conv_nchunks<P, G>();
+  constexpr size_t ny = (G::K3 / NC) * conv_pitch<P>(G::K2), nz = (size_t)G::K3 * conv_zpitch<P, G>();
   return (ny > nz ? ny : nz) * sizeof(cplx<typename P::real>);
 }
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr size_t conv_lds_bytes() {
-  return conv_buf_bytes<P, K>() + conv_tables_bytes<P, K>();
+  return conv_buf_bytes<P, G>() + conv_tables_bytes<P, G>();
 }
 
-template <class P, int K, bool BATCH>
-__global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, BatchArgs bt) {
+template <class P, class G, bool BATCH>
+__global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
-  constexpr int KH = K / 2 + 1;
-  constexpr int C = conv_chunk<P, K>();
-  constexpr int NC = K / C;
-  constexpr int PY = conv_pitch<P, K>();      // y pass: one row of pitch PY per z
-  constexpr int PZ = conv_zpitch<P, K>();     // z pass: one row of pitch PZ per z
-  constexpr int TK = fft_lanes(K);
-  constexpr int NT = conv_threads<P, K>();
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr int KH = K1 / 2 + 1;
+  constexpr int NC = conv_nchunks<P, G>();
+  constexpr int CZ = K3 / NC;                  // z-planes per chunk (y passes)
+  constexpr int CY = K2 / NC;                  // y rows per chunk (z pass)
+  constexpr int PY = conv_pitch<P>(K2);        // y pass: one row of pitch PY per z
+  constexpr int PZ = conv_zpitch<P, G>();      // z pass: one row of pitch PZ per z
+  constexpr int TY = fft_lanes(K2), TZ = fft_lanes(K3);
+  constexpr int NT = conv_threads<P, G>();
   constexpr double PI = 3.14159265358979323846;
-  static_assert(conv_lds_bytes<P, K>() <= kMaxLds, "convolution column does not fit in LDS");
+  static_assert(conv_lds_bytes<P, G>() <= kMaxLds, "convolution column does not fit in LDS");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + conv_buf_bytes<P, K>());
-  double* bs = reinterpret_cast<double*>(tw + K);
-  double* wred = bs + 3 * K;
+  cplx<T>* twy = reinterpret_cast<cplx<T>*>(smem + conv_buf_bytes<P, G>());
+  cplx<T>* twz = twy + K2;
+  double* bs = reinterpret_cast<double*>(twz + K3);  // x, y, z factors
+  double* wred = bs + K1 + K2 + K3;
   TRACE(2, 0);
   const int tid = threadIdx.x;
   if (blockIdx.x == KH) {
@@ -509,7 +528,7 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
     unsigned* bcnt2 = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt2);
     unsigned* ovf = reinterpret_cast<unsigned*>(a.ws + a.lay.ovf);
-    constexpr int NBINS = 2 * K * nq_of(K, P::fixed);
+    constexpr int NBINS = 2 * K3 * nq_of(K2, P::fixed);
     for (int b = tid; b < NBINS; b += NT) {
       bcnt2[b] = bcnt[b];
       bcnt[b] = 0u;
@@ -532,28 +551,31 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   }
   const int xp = blockIdx.x;  // m1
   using S = typename P::spec;
-  S* col = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)xp * K * K;  // [z][y]
+  S* col = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)xp * K3 * K2;  // [z][y]
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
   const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
   // the first chunk's loads are issued before the tables are computed
   // (when they fit in a few registers)
-  constexpr int EPT = (C * K + NT - 1) / NT;
+  constexpr int EPT = (CZ * K2 + NT - 1) / NT;
   constexpr bool PREFETCH = P::fixed && EPT * sizeof(cplx<T>) <= 64;
   cplx<T> first[PREFETCH ? EPT : 1];
   if constexpr (PREFETCH) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
-      const int i = min(tid + k * NT, C * K - 1);
+      const int i = min(tid + k * NT, CZ * K2 - 1);
       first[k] = spec_ld(&col[i]);
     }
   }
-  for (int i = tid; i < K; i += NT) tw[i] = twg[i];
+  // the y and z twiddle tables follow the x table
+  for (int i = tid; i < K2 + K3; i += NT) twy[i] = twg[K1 + i];
   {
     // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
     const double fac = PI * PI / (a.beta * a.beta);
-    for (int i = tid; i < 3 * K; i += NT) {
-      const int ax = i / K, m = i - ax * K;
-      const int mt = (m <= K / 2) ? m : m - K;
+    for (int i = tid; i < K1 + K2 + K3; i += NT) {
+      const int ax = i < K1 ? 0 : i < K1 + K2 ? 1 : 2;
+      const int Ka = ax == 0 ? K1 : ax == 1 ? K2 : K3;
+      const int m = i - (ax == 0 ? 0 : ax == 1 ? K1 : K1 + K2);
+      const int mt = (2 * m <= Ka) ? m : m - Ka;
       // (a select, not a[ax]: a dynamic index would move a batched run's
       // Args copy to scratch)
       const double il = ax == 0 ? a.invL[0] : ax == 1 ? a.invL[1] : a.invL[2];
@@ -565,29 +587,29 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
 
   // --- forward y: one pencil per z
   for (int c = 0; c < NC; ++c) {
-    const int z0 = c * C;
+    const int z0 = c * CZ;
     if constexpr (PREFETCH) {
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int i = tid + k * NT;
-        if (i < C * K) buf[(i / K) * PY + (i % K)] = first[k];
+        if (i < CZ * K2) buf[(i / K2) * PY + (i % K2)] = first[k];
       }
     } else {
-      for (int i = tid; i < C * K; i += NT) {
-        const int zz = i / K, y = i - zz * K;
-        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K + y]);
+      for (int i = tid; i < CZ * K2; i += NT) {
+        const int zz = i / K2, y = i - zz * K2;
+        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K2 + y]);
       }
     }
     __syncthreads();
-    for (int task = tid; task < C * TK; task += NT) {
-      const int zz = task / TK, l = task - zz * TK;
-      fft_pencil<T, K, -1>(buf + zz * PY, 1, l, tw, 1);
+    for (int task = tid; task < CZ * TY; task += NT) {
+      const int zz = task / TY, l = task - zz * TY;
+      fft_pencil<T, K2, -1>(buf + zz * PY, 1, l, twy, 1);
     }
     __syncthreads();
     if constexpr (NC > 1) {
-      for (int i = tid; i < C * K; i += NT) {
-        const int zz = i / K, y = i - zz * K;
-        spec_st(&col[(size_t)(z0 + zz) * K + y], buf[zz * PY + y]);
+      for (int i = tid; i < CZ * K2; i += NT) {
+        const int zz = i / K2, y = i - zz * K2;
+        spec_st(&col[(size_t)(z0 + zz) * K2 + y], buf[zz * PY + y]);
       }
       __syncthreads();
     }
@@ -597,32 +619,32 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
   // --- z: forward transform, influence function, inverse transform.
   // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) with
   // B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3) in an orthorhombic
-  // cell.  The half spectrum counts every m1 = 1 .. K/2-1 twice (its
-  // Hermitian partner), m1 = 0 and m1 = K/2 once.  Per mode, with
+  // cell.  The half spectrum counts every m1 = 1 .. K1/2-1 twice (its
+  // Hermitian partner), m1 = 0 and m1 = K1/2 once.  Per mode, with
   // e = w G |F|^2 and u = 1/|m|^2 + pi^2/beta^2:
   //   E += e,  P_ab += e (delta_ab - 2 u m_a m_b),
   // accumulated as S0 = sum e and S_ab = sum e u m_a m_b, so that
-  // P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A Nyquist index aliases +K/2
-  // and -K/2 equally, so its sign-odd (off-diagonal) products vanish.
+  // P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A Nyquist index aliases +K_a/2
+  // and -K_a/2 equally, so its sign-odd (off-diagonal) products vanish.
   const double pref = a.coulomb / (PI * a.volume);
   const double fac = PI * PI / (a.beta * a.beta);
   const double mvx = xp * a.invL[0];
-  const double nx = (2 * xp == K) ? 0.0 : mvx;
-  const double wx = (xp == 0 || 2 * xp == K) ? 0.5 : 1.0;
+  const double nx = (2 * xp == K1) ? 0.0 : mvx;
+  const double wx = (xp == 0 || 2 * xp == K1) ? 0.5 : 1.0;
   const double mvx2 = mvx * mvx;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // S0, Sxx, Syy, Szz, Sxy, Sxz, Syz
   for (int c = 0; c < NC; ++c) {
-    const int y0 = c * C;
+    const int y0 = c * CY;
     if constexpr (NC > 1) {
-      for (int i = tid; i < K * C; i += NT) {
-        const int z = i / C, yy = i - z * C;
-        buf[z * PZ + yy] = spec_ld(&col[(size_t)z * K + y0 + yy]);
+      for (int i = tid; i < K3 * CY; i += NT) {
+        const int z = i / CY, yy = i - z * CY;
+        buf[z * PZ + yy] = spec_ld(&col[(size_t)z * K2 + y0 + yy]);
       }
       __syncthreads();
     }
-    for (int task = tid; task < C * TK; task += NT) {
-      const int yy = task / TK, l = task - yy * TK;
-      fft_pencil<T, K, -1>(buf + yy, PZ, l, tw, 1);
+    for (int task = tid; task < CY * TZ; task += NT) {
+      const int yy = task / TZ, l = task - yy * TZ;
+      fft_pencil<T, K3, -1>(buf + yy, PZ, l, twz, 1);
     }
     __syncthreads();
     TRACE(2, 2);
@@ -630,16 +652,16 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
     if (a.triclinic) {
       // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
       // each Nyquist index is averaged over its two signs explicitly
-      for (int i = tid; i < K * C; i += NT) {
-        const int z = i / C, yy = i - z * C, y = y0 + yy;
-        const int ms0[3] = {xp, (y <= K / 2) ? y : y - K, (z <= K / 2) ? z : z - K};
-        const int ny3[3] = {2 * xp == K, 2 * y == K, 2 * z == K};
+      for (int i = tid; i < K3 * CY; i += NT) {
+        const int z = i / CY, yy = i - z * CY, y = y0 + yy;
+        const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
+        const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
         const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
         const cplx<T> f = buf[z * PZ + yy];
         const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-        double G = 0.0;
+        double gm = 0.0;  // G(m), averaged over the Nyquist signs
         if (xp != 0 || y != 0 || z != 0) {
-          const double Bw = A * bs[K + y] * bs[2 * K + z] / nvar;
+          const double Bw = A * bs[K1 + y] * bs[K1 + K2 + z] / nvar;
           for (int v = 0; v < nvar; ++v) {
             double ms[3];
             int bit = 0;
@@ -669,59 +691,59 @@ __global__ __launch_bounds__((conv_threads<P, K>())) void k_conv(Args a_in, Batc
             acc[4] = fma(eu * mv[0], mv[1], acc[4]);
             acc[5] = fma(eu * mv[0], mv[2], acc[5]);
             acc[6] = fma(eu * mv[1], mv[2], acc[6]);
-            G += Gv;
+            gm += Gv;
           }
         }
-        const T g = (T)G;
+        const T g = (T)gm;
         buf[z * PZ + yy] = {f.x * g, f.y * g};
       }
     } else {
-    constexpr int NIT = (K * C + NT - 1) / NT;
-constexpr int UNR = NIT <= 4 ? NIT : 2;
+      constexpr int NIT = (K3 * CY + NT - 1) / NT;
+      constexpr int UNR = NIT <= 4 ? NIT : 2;
 #pragma unroll UNR
-    for (int it = 0; it < NIT; ++it) {
-      const int i = tid + it * NT;
-      if ((K * C) % NT != 0 && i >= K * C) break;
-      const int z = i / C, yy = i - z * C, y = y0 + yy;
-      const int my = (y <= K / 2) ? y : y - K, mz = (z <= K / 2) ? z : z - K;
-      const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
-      const double ny = (2 * y == K) ? 0.0 : mvy, nz = (2 * z == K) ? 0.0 : mvz;
-      const cplx<T> f = buf[z * PZ + yy];
-      // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
-      // its G by 0, without a branch
-      const bool m0 = (xp == 0) && (y == 0) && (z == 0);
-      const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
-      // 1/msq: hardware reciprocal and two Newton steps
-      double r = __builtin_amdgcn_rcp(msq);
-      r = fma(r, fma(-msq, r, 1.0), r);
-      r = fma(r, fma(-msq, r, 1.0), r);
-      const double G = m0 ? 0.0 : A * bs[K + y] * bs[2 * K + z] * r;
-      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-      const double e = wx * G * f2;
-      const double eu = e * (r + fac);
-      const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
-      acc[0] += e;
-      acc[1] = fma(eux, mvx, acc[1]);
-      acc[2] = fma(euy, mvy, acc[2]);
-      acc[3] = fma(eu * mvz, mvz, acc[3]);
-      acc[4] = fma(eun, ny, acc[4]);
-      acc[5] = fma(eun, nz, acc[5]);
-      acc[6] = fma(eu * ny, nz, acc[6]);
-      const T g = (T)G;
-      buf[z * PZ + yy] = {f.x * g, f.y * g};
-    }
+      for (int it = 0; it < NIT; ++it) {
+        const int i = tid + it * NT;
+        if ((K3 * CY) % NT != 0 && i >= K3 * CY) break;
+        const int z = i / CY, yy = i - z * CY, y = y0 + yy;
+        const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
+        const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
+        const double ny = (2 * y == K2) ? 0.0 : mvy, nz = (2 * z == K3) ? 0.0 : mvz;
+        const cplx<T> f = buf[z * PZ + yy];
+        // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
+        // its G by 0, without a branch
+        const bool m0 = (xp == 0) && (y == 0) && (z == 0);
+        const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
+        // 1/msq: hardware reciprocal and two Newton steps
+        double r = __builtin_amdgcn_rcp(msq);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        const double gm = m0 ? 0.0 : A * bs[K1 + y] * bs[K1 + K2 + z] * r;  // G(m)
+        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+        const double e = wx * gm * f2;
+        const double eu = e * (r + fac);
+        const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
+        acc[0] += e;
+        acc[1] = fma(eux, mvx, acc[1]);
+        acc[2] = fma(euy, mvy, acc[2]);
+        acc[3] = fma(eu * mvz, mvz, acc[3]);
+        acc[4] = fma(eun, ny, acc[4]);
+        acc[5] = fma(eun, nz, acc[5]);
+        acc[6] = fma(eu * ny, nz, acc[6]);
+        const T g = (T)gm;
+        buf[z * PZ + yy] = {f.x * g, f.y * g};
+      }
     }
     __syncthreads();
     TRACE(2, 3);
-    for (int task = tid; task < C * TK; task += NT) {
-      const int yy = task / TK, l = task - yy * TK;
-      fft_pencil<T, K, 1>(buf + yy, PZ, l, tw, 1);
+    for (int task = tid; task < CY * TZ; task += NT) {
+      const int yy = task / TZ, l = task - yy * TZ;
+      fft_pencil<T, K3, 1>(buf + yy, PZ, l, twz, 1);
     }
     __syncthreads();
     if constexpr (NC > 1) {
-      for (int i = tid; i < K * C; i += NT) {
-        const int z = i / C, yy = i - z * C;
-        spec_st(&col[(size_t)z * K + y0 + yy], buf[z * PZ + yy]);
+      for (int i = tid; i < K3 * CY; i += NT) {
+        const int z = i / CY, yy = i - z * CY;
+        spec_st(&col[(size_t)z * K2 + y0 + yy], buf[z * PZ + yy]);
       }
       __syncthreads();
     }
@@ -730,22 +752,22 @@ constexpr int UNR = NIT <= 4 ? NIT : 2;
 
   // --- inverse y
   for (int c = 0; c < NC; ++c) {
-    const int z0 = c * C;
+    const int z0 = c * CZ;
     if constexpr (NC > 1) {
-      for (int i = tid; i < C * K; i += NT) {
-        const int zz = i / K, y = i - zz * K;
-        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K + y]);
+      for (int i = tid; i < CZ * K2; i += NT) {
+        const int zz = i / K2, y = i - zz * K2;
+        buf[zz * PY + y] = spec_ld(&col[(size_t)(z0 + zz) * K2 + y]);
       }
       __syncthreads();
     }
-    for (int task = tid; task < C * TK; task += NT) {
-      const int zz = task / TK, l = task - zz * TK;
-      fft_pencil<T, K, 1>(buf + zz * PY, 1, l, tw, 1);
+    for (int task = tid; task < CZ * TY; task += NT) {
+      const int zz = task / TY, l = task - zz * TY;
+      fft_pencil<T, K2, 1>(buf + zz * PY, 1, l, twy, 1);
     }
     __syncthreads();
-    for (int i = tid; i < C * K; i += NT) {
-      const int zz = i / K, y = i - zz * K;
-      spec_st(&col[(size_t)(z0 + zz) * K + y], buf[zz * PY + y]);
+    for (int i = tid; i < CZ * K2; i += NT) {
+      const int zz = i / K2, y = i - zz * K2;
+      spec_st(&col[(size_t)(z0 + zz) * K2 + y], buf[zz * PY + y]);
     }
     if constexpr (NC > 1) __syncthreads();
   }
@@ -790,45 +812,46 @@ __global__ __launch_bounds__(64) void k_reduce_ev(Args a) { reduce_ev(a); }
 // the fused interpolation below does not fit in LDS, and for the debug copy
 // of the potential; one extra workgroup adds the energy/virial rows.
 // ---------------------------------------------------------------------------
-template <class P, int K>
+template <class P, class G>
 __host__ __device__ constexpr size_t inv_x_lds_bytes() {
-  return (size_t)K * (K / 2 + 2) * sizeof(cplx<typename P::real>) +
-         (size_t)K * sizeof(cplx<typename P::real>);
+  return (size_t)G::K2 * (G::K1 / 2 + 2) * sizeof(cplx<typename P::real>) +
+         (size_t)G::K1 * sizeof(cplx<typename P::real>);
 }
 
-template <class P, int K, int ORDER, bool BATCH>
+template <class P, class G, int ORDER, bool BATCH>
 __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
-  constexpr int M = K / 2, KH = K / 2 + 1, PC = KH + 1;
-  constexpr int PP = phi_pitch_of(K, ORDER);
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr int M = K1 / 2, KH = K1 / 2 + 1, PC = KH + 1;
+  constexpr int PP = phi_pitch_of(K1, ORDER);
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = pl + K * PC;
+  cplx<T>* tw = pl + K2 * PC;
   const int tid = threadIdx.x;
-  const int z = xcd_local(blockIdx.x, K);
+  const int z = xcd_local(blockIdx.x, K3);
   const typename P::spec* spec = reinterpret_cast<const typename P::spec*>(a.ws + a.lay.spec);
-  for (int i = tid; i < KH * K; i += kPlaneThreads) {
-    const int x = i / K, y = i - x * K;
-    pl[y * PC + x] = spec_ld(&spec[((size_t)x * K + z) * K + y]);
+  for (int i = tid; i < KH * K2; i += kPlaneThreads) {
+    const int x = i / K2, y = i - x * K2;
+    pl[y * PC + x] = spec_ld(&spec[((size_t)x * K3 + z) * K2 + y]);
   }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  for (int i = tid; i < K; i += kPlaneThreads) tw[i] = twg[i];
+  for (int i = tid; i < K1; i += kPlaneThreads) tw[i] = twg[i];
   __syncthreads();
   constexpr int TM = fft_lanes(M);
-  for (int task = tid; task < K * TM; task += kPlaneThreads) {
+  for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
     const int y = task / TM, l = task - y * TM;
     cplx<T>* row = pl + y * PC;
-    c2r_pre<T, K>(row, l, tw);
+    c2r_pre<T, K1>(row, l, tw);
     fft_pencil<T, M, 1>(row, 1, l, tw, 2);
   }
   __syncthreads();
-  T* phi = reinterpret_cast<T*>(a.ws + a.lay.phi) + (size_t)z * K * PP;
-  for (int i = tid; i < K * PP; i += kPlaneThreads) {
+  T* phi = reinterpret_cast<T*>(a.ws + a.lay.phi) + (size_t)z * K2 * PP;
+  for (int i = tid; i < K2 * PP; i += kPlaneThreads) {
     const int y = i / PP, xh = i - y * PP;
     int x = xh - (ORDER - 1);
-    if (x < 0) x += K;
-    if (x >= K) x -= K;
+    if (x < 0) x += K1;
+    if (x >= K1) x -= K1;
     phi[i] = reinterpret_cast<const T*>(pl + y * PC)[x];
   }
 }
@@ -841,11 +864,11 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
 // interpolates those atoms from LDS, one per thread; forces go to the
 // caller's atom order.
 // ---------------------------------------------------------------------------
-template <class P, int K, int ORDER>
+template <class P, class G, int ORDER>
 __host__ __device__ constexpr size_t interp_lds_bytes() {
-  constexpr size_t R = K / nq_of(K, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
-  constexpr size_t PC = K / 2 + 2;
-  return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)K * sizeof(cplx<typename P::real>) +
+  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
+  constexpr size_t PC = G::K1 / 2 + 2;
+  return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)G::K1 * sizeof(cplx<typename P::real>) +
          4 * sizeof(int);
 }
 
@@ -853,7 +876,7 @@ __host__ __device__ constexpr size_t interp_lds_bytes() {
 // row of support point (jz, jy) and xs[jx] at the x index of point jx.
 template <class P, int ORDER, class Rows>
 __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec& r, Rows rows,
-                                            const int* xs, int K) {
+                                            const int* xs) {
   using T = typename P::real;
   const double qi = r.qd;
   T thx[ORDER], thy[ORDER], thz[ORDER], dthx[ORDER], dthy[ORDER], dthz[ORDER];
@@ -878,17 +901,19 @@ __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec
       sz += thy[jy] * dthz[jz] * s0;
     }
   }
-  const double qk = -qi * (double)K;
+  // derivatives with respect to the scaled coordinates u_a = K_a s_a
+  const double d1 = (double)a.K1 * (double)sx, d2 = (double)a.K2 * (double)sy,
+               d3 = (double)a.K3 * (double)sz;
   double f[3];
   if (!a.triclinic) {
-    f[0] = qk * a.invL[0] * (double)sx;
-    f[1] = qk * a.invL[1] * (double)sy;
-    f[2] = qk * a.invL[2] * (double)sz;
+    f[0] = -qi * (d1 * a.invL[0]);
+    f[1] = -qi * (d2 * a.invL[1]);
+    f[2] = -qi * (d3 * a.invL[2]);
   } else {
-    // F = -q K (s_1 a*_1 + s_2 a*_2 + s_3 a*_3)
+    // F = -q (K_1 s_1 a*_1 + K_2 s_2 a*_2 + K_3 s_3 a*_3)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      f[c] = qk * ((double)sx * a.rec[c] + (double)sy * a.rec[3 + c] + (double)sz * a.rec[6 + c]);
+      f[c] = -qi * (d1 * a.rec[c] + d2 * a.rec[3 + c] + d3 * a.rec[6 + c]);
   }
   double* out = a.forces + 3 * (size_t)r.idx;
   if (a.accumulate) {
@@ -902,28 +927,30 @@ __device__ __forceinline__ void interpolate(const Args& a, const typename P::rec
   }
 }
 
-template <class P, int K, int ORDER, bool BATCH>
+template <class P, class G, int ORDER, bool BATCH>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   using Rec = typename P::rec;
-  constexpr int M = K / 2, KH = M + 1, PC = KH + 1;
-  constexpr int NQ = nq_of(K, P::fixed), R = K / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr int M = K1 / 2, KH = M + 1, PC = KH + 1;
+  constexpr int NQ = nq_of(K2, P::fixed), R = K2 / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
   constexpr int NT = kInterpThreads;
-  static_assert(interp_lds_bytes<P, K, ORDER>() <= kMaxLds, "interpolation tile does not fit in LDS");
+  static_assert(interp_lds_bytes<P, G, ORDER>() <= kMaxLds, "interpolation tile does not fit in LDS");
+  static_assert(K1 <= NT, "twiddle table load assumes K1 <= workgroup size");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + NROW * PC;
-  int* nb = reinterpret_cast<int*>(tw + K);  // head count, body count, overflow count
+  int* nb = reinterpret_cast<int*>(tw + K1);  // head count, body count, overflow count
   TRACE(3, 0);
   const int tid = threadIdx.x;
-  if (blockIdx.x == K * NQ) {
+  if (blockIdx.x == K3 * NQ) {
     if (a.reduce_ev) reduce_ev(a);
     return;
   }
   if (a.N == 0) return;
-  static_assert((K * NQ) % kXcds == 0, "interpolation tiles do not split over the XCDs");
-  const int tile_id = xcd_local(blockIdx.x, K * NQ);
+  static_assert((K3 * NQ) % kXcds == 0, "interpolation tiles do not split over the XCDs");
+  const int tile_id = xcd_local(blockIdx.x, K3 * NQ);
   const int z = tile_id / NQ, qs = tile_id - z * NQ, y0 = qs * R;
   const int cap = a.lay.cap;
   const Rec* rec = reinterpret_cast<const Rec*>(a.ws + a.lay.rec);
@@ -944,11 +971,11 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   for (int e = tid; e < NE; e += NT) {
     const int r = e % RR, t2 = e / RR, jz = t2 % ORDER, x = t2 / ORDER;
     int zz = z - ORDER + 1 + jz, yy = y0 - ORDER + 1 + r;
-    if (zz < 0) zz += K;
-    if (yy < 0) yy += K;
-    buf[(jz * RR + r) * PC + x] = spec_ld(&spec[((size_t)x * K + zz) * K + yy]);
+    if (zz < 0) zz += K3;
+    if (yy < 0) yy += K2;
+    buf[(jz * RR + r) * PC + x] = spec_ld(&spec[((size_t)x * K3 + zz) * K2 + yy]);
   }
-  if (tid < K) tw[tid] = twg[tid];
+  if (tid < K1) tw[tid] = twg[tid];
   __syncthreads();
   TRACE(3, 1);
   const int n0 = nb[0], total = n0 + nb[1], novf = nb[2];
@@ -959,7 +986,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   constexpr int TM = fft_lanes(M);
   for (int task = tid; task < NROW * TM; task += NT) {
     const int row = task / TM, l = task - row * TM;
-    c2r_pre<T, K>(buf + row * PC, l, tw);
+    c2r_pre<T, K1>(buf + row * PC, l, tw);
     fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
   }
   __syncthreads();
@@ -970,13 +997,13 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
 #pragma unroll
     for (int jx = 0; jx < ORDER; ++jx) {
       const int x = gx - ORDER + 1 + jx;
-      xs[jx] = x < 0 ? x + K : x;
+      xs[jx] = x < 0 ? x + K1 : x;
     }
     const int ry = gy - y0;
     interpolate<P, ORDER>(
         a, rr,
         [&](int jz, int jy) { return reinterpret_cast<const T*>(buf + (jz * RR + ry + jy) * PC); },
-        xs, K);
+        xs);
   };
   for (int t = tid; t < total; t += NT) {
     Rec rn;
@@ -998,7 +1025,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
 // its convolution (one workgroup).
 __global__ void k_clear_counts(Args a) {
   unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
-  const int nbins = 2 * a.K * nq_of(a.K, a.precision != PME_FP64);
+  const int nbins = 2 * a.K3 * nq_of(a.K2, a.precision != PME_FP64);
   for (int b = threadIdx.x; b < nbins; b += blockDim.x) bcnt[b] = 0u;
   if (threadIdx.x == 0) reinterpret_cast<unsigned*>(a.ws + a.lay.ovf)[0] = 0u;
 }
@@ -1008,7 +1035,7 @@ __global__ void k_clear_flags(unsigned* ctrl) {
 }
 
 // ---------------------------------------------------------------------------
-// Host-side dispatch over (precision, K, order).
+// Host-side dispatch over (precision, grid shape, order).
 // ---------------------------------------------------------------------------
 template <int V>
 using ic = std::integral_constant<int, V>;
@@ -1043,18 +1070,26 @@ hipError_t with_prec(int prec, F&& f) {
   if (prec == PME_FP32_FIXED_HALF) return f(PHalf{});
   return hipErrorInvalidValue;
 }
+// Supported grids: cubic K = 16, 24, 32, 48, 64, 96, 128, and the non-cubic
+// shapes 32 x 32 x 64, 64 x 64 x 128 and 48 x 32 x 64 (x, y, z).
 template <class F>
-hipError_t with_K(int K, F&& f) {
-  switch (K) {
-    case 16: return f(ic<16>{});
-    case 24: return f(ic<24>{});
-    case 32: return f(ic<32>{});
-    case 48: return f(ic<48>{});
-    case 64: return f(ic<64>{});
-    case 96: return f(ic<96>{});
-    case 128: return f(ic<128>{});
-    default: return hipErrorInvalidValue;
+hipError_t with_grid(int K1, int K2, int K3, F&& f) {
+  if (K1 == K2 && K2 == K3) {
+    switch (K1) {
+      case 16: return f(Grid<16, 16, 16>{});
+      case 24: return f(Grid<24, 24, 24>{});
+      case 32: return f(Grid<32, 32, 32>{});
+      case 48: return f(Grid<48, 48, 48>{});
+      case 64: return f(Grid<64, 64, 64>{});
+      case 96: return f(Grid<96, 96, 96>{});
+      case 128: return f(Grid<128, 128, 128>{});
+      default: return hipErrorInvalidValue;
+    }
   }
+  if (K1 == 32 && K2 == 32 && K3 == 64) return f(Grid<32, 32, 64>{});
+  if (K1 == 64 && K2 == 64 && K3 == 128) return f(Grid<64, 64, 128>{});
+  if (K1 == 48 && K2 == 32 && K3 == 64) return f(Grid<48, 32, 64>{});
+  return hipErrorInvalidValue;
 }
 template <class F>
 hipError_t with_order(int p, F&& f) {
@@ -1065,55 +1100,57 @@ hipError_t with_order(int p, F&& f) {
   }
 }
 
-bool grid_supported(int K) {
-  return K == 16 || K == 24 || K == 32 || K == 48 || K == 64 || K == 96 || K == 128;
+bool grid_supported(int K1, int K2, int K3) {
+  return with_grid(K1, K2, K3, [](auto) { return hipSuccess; }) == hipSuccess;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Wavefronts per convolution workgroup (one energy/virial row each).
-static int conv_waves(int K, int precision) {
+static int conv_waves(int K1, int K2, int K3, int precision) {
   int w = 0;
   (void)with_prec(precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(K, [&](auto kc) {
-      w = conv_threads<P, decltype(kc)::value>() / 64;
+    return with_grid(K1, K2, K3, [&](auto gc) {
+      w = conv_threads<P, decltype(gc)>() / 64;
       return hipSuccess;
     });
   });
   return w;
 }
 
-bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
-  if (!grid_supported(K) || (order != 4 && order != 6) || max_atoms < 0) return false;
+bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision, Layout* lay) {
+  if (!grid_supported(K1, K2, K3) || (order != 4 && order != 6) || max_atoms < 0) return false;
   if (precision != PME_FP32_FIXED && precision != PME_FP64 && precision != PME_FP32_FIXED_HALF)
     return false;
   const bool fx = precision != PME_FP64;
   const size_t real = fx ? 4 : 8, cpx = 2 * real;
   const size_t spec_cpx = precision == PME_FP32_FIXED_HALF ? 4 : cpx;
-  const size_t kh = (size_t)K / 2 + 1;
+  const size_t kh = (size_t)K1 / 2 + 1, ksum = (size_t)K1 + K2 + K3;
+  const size_t plane = (size_t)K2 * K3;  // (y, z) points
   const int nch = (max_atoms + kChunk - 1) / kChunk;
-  const size_t nbins = 2 * (size_t)K * nq_of(K, fx);
+  const int nq = nq_of(K2, fx);
+  const size_t nbins = 2 * (size_t)K3 * nq;
   const size_t rsz = fx ? sizeof(RecF) : sizeof(RecD);
   Layout L{};
   size_t o = 0;
   L.ctrl = o;      o = align256(o + 64 * sizeof(unsigned));
-  L.bsq = o;       o = align256(o + 3 * (size_t)K * sizeof(double));
-  L.tw = o;        o = align256(o + (size_t)K * cpx);
+  L.bsq = o;       o = align256(o + ksum * sizeof(double));
+  L.tw = o;        o = align256(o + ksum * cpx);
   L.bcnt = o;      o = align256(o + nbins * sizeof(unsigned));
   L.bcnt2 = o;     o = align256(o + nbins * sizeof(unsigned));
   L.ovf = o;       o = align256(o + 4 * sizeof(unsigned));
   L.absq = o;      o = align256(o + (size_t)nch * sizeof(double));
-  L.cap = bucket_cap(K, nq_of(K, fx), max_atoms);
+  L.cap = bucket_cap(K3, nq, max_atoms);
   L.rec = o;       o = align256(o + nbins * (size_t)L.cap * rsz);
   L.orec = o;      o = align256(o + (size_t)max_atoms * rsz);
   L.orec_max = max_atoms;
-  L.spec = o;      o = align256(o + (size_t)K * K * kh * spec_cpx);
-  L.phi_pitch = phi_pitch_of(K, order);
-  L.phi = o;       o = align256(o + (size_t)K * K * L.phi_pitch * real);
-  L.partial_rows = (int)kh * conv_waves(K, precision);
+  L.spec = o;      o = align256(o + plane * kh * spec_cpx);
+  L.phi_pitch = phi_pitch_of(K1, order);
+  L.phi = o;       o = align256(o + plane * L.phi_pitch * real);
+  L.partial_rows = (int)kh * conv_waves(K1, K2, K3, precision);
   L.partial = o;   o = align256(o + (size_t)L.partial_rows * 8 * sizeof(double));
-  L.dbg = o;       o = align256(o + (size_t)K * K * K * 8);
+  L.dbg = o;       o = align256(o + plane * K1 * 8);
   L.args = o;      o = align256(o + sizeof(Args));
   L.total = o;
   L.n_chunks_max = nch;
@@ -1121,30 +1158,30 @@ bool layout_for(int K, int order, int max_atoms, int precision, Layout* lay) {
   return true;
 }
 
-template <class P, int KK, int O, bool B>
+template <class P, class G, int O, bool B>
 hipError_t raise_lds_limits() {
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
-  hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, KK, O, B>, attr,
-                                     (int)spread_lds_bytes<P, KK>());
+  hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, G, O, B>, attr,
+                                     (int)spread_lds_bytes<P, G>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_conv<P, KK, B>, attr, (int)conv_lds_bytes<P, KK>());
+    e = hipFuncSetAttribute((const void*)k_conv<P, G, B>, attr, (int)conv_lds_bytes<P, G>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_inv_x<P, KK, O, B>, attr, (int)inv_x_lds_bytes<P, KK>());
+    e = hipFuncSetAttribute((const void*)k_inv_x<P, G, O, B>, attr, (int)inv_x_lds_bytes<P, G>());
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_interp<P, KK, O, B>, attr,
-                            (int)interp_lds_bytes<P, KK, O>());
+    e = hipFuncSetAttribute((const void*)k_interp<P, G, O, B>, attr,
+                            (int)interp_lds_bytes<P, G, O>());
   return e;
 }
 
-hipError_t prepare_kernels(int K, int order, int precision) {
+hipError_t prepare_kernels(int K1, int K2, int K3, int order, int precision) {
   return with_prec(precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
+    return with_grid(K1, K2, K3, [&](auto gc) {
+      using G = decltype(gc);
       return with_order(order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
-        hipError_t e = raise_lds_limits<P, KK, O, false>();
-        return e == hipSuccess ? raise_lds_limits<P, KK, O, true>() : e;
+        hipError_t e = raise_lds_limits<P, G, O, false>();
+        return e == hipSuccess ? raise_lds_limits<P, G, O, true>() : e;
       });
     });
   });
@@ -1170,14 +1207,14 @@ hipError_t launch_bin(const Args& a, hipStream_t s, const Timing& t, const Batch
 hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
+    return with_grid(a.K1, a.K2, a.K3, [&](auto gc) {
+      using G = decltype(gc);
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
-          return launch(k_spread_x<P, KK, O, B>, dim3(KK * nq_of(KK, P::fixed)), dim3(kSpreadThreads),
-                        spread_lds_bytes<P, KK>(), s, t, a, bt);
+          return launch(k_spread_x<P, G, O, B>, dim3(G::K3 * nq_of(G::K2, P::fixed)),
+                        dim3(kSpreadThreads), spread_lds_bytes<P, G>(), s, t, a, bt);
         });
       });
     });
@@ -1187,13 +1224,13 @@ hipError_t launch_spread_x(const Args& a, hipStream_t s, const Timing& t, const 
 hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
+    return with_grid(a.K1, a.K2, a.K3, [&](auto gc) {
+      using G = decltype(gc);
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
-        const int blocks = KK / 2 + 2;  // columns and the counts/headroom workgroup
-        return launch(k_conv<P, KK, B>, dim3(blocks), dim3(conv_threads<P, KK>()),
-                      conv_lds_bytes<P, KK>(), s, t, a, bt);
+        const int blocks = G::K1 / 2 + 2;  // columns and the counts/headroom workgroup
+        return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_threads<P, G>()),
+                      conv_lds_bytes<P, G>(), s, t, a, bt);
       });
     });
   });
@@ -1207,14 +1244,14 @@ hipError_t launch_reduce_ev(const Args& a, hipStream_t s) {
 hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
+    return with_grid(a.K1, a.K2, a.K3, [&](auto gc) {
+      using G = decltype(gc);
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
-          return launch(k_inv_x<P, KK, O, B>, dim3(KK), dim3(kPlaneThreads),
-                        inv_x_lds_bytes<P, KK>(), s, t, a, bt);
+          return launch(k_inv_x<P, G, O, B>, dim3(G::K3), dim3(kPlaneThreads),
+                        inv_x_lds_bytes<P, G>(), s, t, a, bt);
         });
       });
     });
@@ -1224,15 +1261,15 @@ hipError_t launch_inv_x(const Args& a, hipStream_t s, const Timing& t, const Bat
 hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t, const BatchArgs* bt) {
   return with_prec(a.precision, [&](auto pt) {
     using P = decltype(pt);
-    return with_K(a.K, [&](auto kc) {
-      constexpr int KK = decltype(kc)::value;
+    return with_grid(a.K1, a.K2, a.K3, [&](auto gc) {
+      using G = decltype(gc);
       return with_order(a.order, [&](auto oc) {
         constexpr int O = decltype(oc)::value;
         return with_batch(bt, [&](auto bc) {
           constexpr bool B = decltype(bc)::value;
-          const int blocks = KK * nq_of(KK, P::fixed) + ((a.reduce_ev || B) ? 1 : 0);
-          return launch(k_interp<P, KK, O, B>, dim3(blocks), dim3(kInterpThreads),
-                        interp_lds_bytes<P, KK, O>(), s, t, a, bt);
+          const int blocks = G::K3 * nq_of(G::K2, P::fixed) + ((a.reduce_ev || B) ? 1 : 0);
+          return launch(k_interp<P, G, O, B>, dim3(blocks), dim3(kInterpThreads),
+                        interp_lds_bytes<P, G, O>(), s, t, a, bt);
         });
       });
     });

@@ -37,8 +37,19 @@ def _dev_f64(t, shape, name):
     return t
 
 
+def grid3(K):
+    """(K1, K2, K3) from a cubic K or a 3-sequence of grid points along x, y, z."""
+    if np.ndim(K) == 0:
+        return (int(K),) * 3
+    k = tuple(int(v) for v in K)
+    if len(k) != 3:
+        raise ValueError("K must be an int or three grid sizes (K1, K2, K3)")
+    return k
+
+
 class Plan:
-    """One SPME reciprocal-space solver for a cubic K^3 grid.
+    """One SPME reciprocal-space solver on a K1 x K2 x K3 grid (K: an int for
+    a cubic grid, or (K1, K2, K3) along x, y, z).
 
     precision: "fp32_fixed" (FP32 splines/FFT/convolution, 64-bit fixed-point
     charge grid, FP64 moduli/energy/virial), "fp32_fixed_half" (the same with
@@ -50,7 +61,8 @@ class Plan:
         lib = _lib.load()
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
-        self.K, self.order, self.beta = int(K), int(order), float(beta)
+        self.grid = grid3(K)  # (K1, K2, K3)
+        self.order, self.beta = int(order), float(beta)
         self.max_atoms, self.precision = int(max_atoms), precision
         self.frac_bits = int(frac_bits)
         self.coulomb = float(coulomb)
@@ -58,7 +70,7 @@ class Plan:
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.type != "cuda":
             raise ValueError("the SPME step runs on a GPU device")
-        nbytes = lib.pme_workspace_bytes(self.K, self.K, self.K, self.order, self.max_atoms, prec)
+        nbytes = lib.pme_workspace_bytes(*self.grid, self.order, self.max_atoms, prec)
         if nbytes == 0:
             raise _lib.SpmeError(2, f"pme_workspace_bytes(K={K}, order={order})")
         self.workspace_bytes = nbytes
@@ -66,7 +78,7 @@ class Plan:
         base = (self._ws.data_ptr() + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        check(lib.pme_create(ctypes.byref(h), self.K, self.K, self.K, self.order, self.beta,
+        check(lib.pme_create(ctypes.byref(h), *self.grid, self.order, self.beta,
                              self.max_atoms, prec, self.frac_bits, self.coulomb, base, nbytes,
                              ctypes.c_void_p(self.stream.cuda_stream)), "pme_create")
         self._h = h
@@ -78,7 +90,7 @@ class Plan:
     def workspace_bytes_for(K, order, max_atoms, precision="fp32_fixed"):
         """Device workspace a plan with these parameters needs (0 if unsupported)."""
         lib = _lib.load()
-        return int(lib.pme_workspace_bytes(int(K), int(K), int(K), int(order), int(max_atoms),
+        return int(lib.pme_workspace_bytes(*grid3(K), int(order), int(max_atoms),
                                            PRECISIONS[precision]))
 
     # -- lifetime -----------------------------------------------------------
@@ -164,18 +176,21 @@ class Plan:
 
     def debug_grid(self, which):
         """0: charge grid (int64 fixed point or float64) [z, y, x], 1: half
-        spectrum (complex) as columns [x', z, y] of shape [K/2+1, K, K],
+        spectrum (complex) as columns [x', z, y] of shape [K1/2+1, K3, K2],
         2: potential phi [z, y, x]."""
-        K, kh = self.K, self.K // 2 + 1
+        K1, K2, K3 = self.grid
+        kh = K1 // 2 + 1
         fx = self.precision != "fp64"
         if which == 0:
-            out = torch.empty((K, K, K), dtype=torch.int64 if fx else torch.float64, device=self.device)
+            out = torch.empty((K3, K2, K1), dtype=torch.int64 if fx else torch.float64,
+                              device=self.device)
         elif which == 1:
             dt = {"fp32_fixed": torch.complex64, "fp32_fixed_half": torch.complex32,
                   "fp64": torch.complex128}[self.precision]
-            out = torch.empty((kh, K, K), dtype=dt, device=self.device)
+            out = torch.empty((kh, K3, K2), dtype=dt, device=self.device)
         elif which == 2:
-            out = torch.empty((K, K, K), dtype=torch.float32 if fx else torch.float64, device=self.device)
+            out = torch.empty((K3, K2, K1), dtype=torch.float32 if fx else torch.float64,
+                              device=self.device)
         else:
             raise ValueError("which must be 0, 1 or 2")
         assert out.numel() * out.element_size() == self._lib.pme_debug_grid_bytes(self._h, which)

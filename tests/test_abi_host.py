@@ -36,7 +36,14 @@ def test_workspace_bytes(lib):
     w64 = lib.pme_workspace_bytes(64, 64, 64, 4, 65535, 0)
     assert w64 > 64 * 64 * 33 * 16 + 64 ** 3 * 8
     assert lib.pme_workspace_bytes(50, 50, 50, 4, 100, 1) == 0      # radix 5
-    assert lib.pme_workspace_bytes(64, 64, 32, 4, 100, 1) == 0      # non-cubic
+    assert lib.pme_workspace_bytes(64, 64, 32, 4, 100, 1) == 0      # shape without kernels
+    assert lib.pme_workspace_bytes(64, 32, 64, 4, 100, 1) == 0
+    # non-cubic shapes with kernels: the spectrum [K1/2+1][K3][K2] and the
+    # potential rows [K3][K2] scale with the shape
+    wn = lib.pme_workspace_bytes(64, 64, 128, 4, 65535, 1)
+    assert wn > 64 * 128 * 33 * 8 + 64 * 64 * 128 * 4
+    assert lib.pme_workspace_bytes(32, 32, 64, 6, 1000, 0) > 0
+    assert lib.pme_workspace_bytes(48, 32, 64, 4, 1000, 2) > 0
     assert lib.pme_workspace_bytes(64, 64, 64, 5, 100, 1) == 0      # odd order
     assert lib.pme_workspace_bytes(64, 64, 64, 4, -1, 1) == 0
     assert lib.pme_workspace_bytes(64, 64, 64, 4, 100, 7) == 0

@@ -303,3 +303,46 @@ def test_total_with_exclusions_is_beta_independent(orc):
         ex = orc.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut)
         tot.append(rec + rs["E_real"] + rs["E_self"] + ex["E_excl"])
     assert tot[0] == pytest.approx(tot[1], rel=1e-9)
+
+
+def elongated_system(seed=5, n=10, box=(10.0, 12.0, 20.0)):
+    pos, q, _ = inputs.random_neutral(n, 1.0, seed)
+    return pos * np.asarray(box), q, np.diag(box)
+
+
+def test_non_cubic_grid_converges_to_exact_ewald(orc):
+    # K1 != K2 != K3 on an orthorhombic cell of unequal edges: each axis has
+    # its own moduli and FFT length (section II, the SPME structure factor)
+    pos, q, box = elongated_system()
+    beta = 0.35
+    ex = orc.ewald_recip(pos, q, box, beta, 16)
+    errs = []
+    for K, p in [((12, 16, 24), 4), ((24, 32, 48), 6), ((48, 64, 96), 8)]:
+        r = orc.spme(pos, q, box, K, p, beta)
+        errs.append((abs(r["E"] - ex["E"]) / abs(ex["E"]),
+                     np.linalg.norm(r["forces"] - ex["forces"]) / np.linalg.norm(ex["forces"])))
+    assert errs[0][0] > errs[1][0] > errs[2][0]
+    assert errs[0][1] > errs[1][1] > errs[2][1]
+    assert errs[2][0] < 1e-10 and errs[2][1] < 1e-9
+    r = orc.spme(pos, q, box, (48, 64, 96), 8, beta)
+    np.testing.assert_allclose(r["virial"], ex["virial"], atol=1e-9 * abs(ex["E"]))
+
+
+def test_axis_permutation_symmetry(orc):
+    # relabelling the axes (x, y, z) -> (y, z, x) together with the box edges
+    # and grid sizes permutes forces and virial and leaves the energy: a
+    # transposed axis, or one axis's K used for another, breaks it
+    pos, q, box = elongated_system(seed=9, n=12)
+    K, p, beta = (24, 32, 48), 6, 0.35
+    r = orc.spme(pos, q, box, K, p, beta)
+    perm = [1, 2, 0]
+    rp = orc.spme(pos[:, perm], q, np.diag(np.diag(box)[perm]), tuple(K[i] for i in perm), p, beta)
+    assert rp["E"] == pytest.approx(r["E"], rel=1e-12)
+    np.testing.assert_allclose(rp["forces"], r["forces"][:, perm], rtol=0,
+                               atol=1e-11 * np.abs(r["forces"]).max())
+    # virial (xx, yy, zz, xy, xz, yz) under the relabelling
+    v = r["virial"]
+    full = np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+    fp = full[np.ix_(perm, perm)]
+    want = np.array([fp[0, 0], fp[1, 1], fp[2, 2], fp[0, 1], fp[0, 2], fp[1, 2]])
+    np.testing.assert_allclose(rp["virial"], want, rtol=0, atol=1e-11 * abs(r["E"]))
