@@ -34,15 +34,17 @@ def algorithmic_bytes(N, K, kernel, fp64=False):
     (8 or 16 B/point) across the two corner turns (written by the forward
     slab pass, read and written by the pencil pass, read by the inverse slab
     pass); the potential written and read.  Each term is charged to the
-    kernel that performs that step."""
-    kh = K // 2 + 1
+    kernel that performs that step.  K: an int (cubic grid) or (K1, K2, K3)."""
+    K1, K2, K3 = (K, K, K) if np.ndim(K) == 0 else tuple(K)
+    pts = K1 * K2 * K3                 # grid points
+    half = K2 * K3 * (K1 // 2 + 1)     # half-spectrum points
     cs = 16 if fp64 else 8       # complex bytes
     rs = 8 if fp64 else 4        # potential bytes
     return {
         "bin": 32 * N,
-        "spread_x": 16 * K ** 3 + cs * K * K * kh,
-        "convolve_yz": 2 * cs * K * K * kh,
-        "interpolate": cs * K * K * kh + 2 * rs * K ** 3 + 56 * N,
+        "spread_x": 16 * pts + cs * half,
+        "convolve_yz": 2 * cs * half,
+        "interpolate": cs * half + 2 * rs * pts + 56 * N,
     }[kernel]
 
 
@@ -133,6 +135,65 @@ def bench_batched(torch, dev, Plan, Batch, I, reps=200):
     }
 
 
+def bench_noncubic(torch, dev, Plan, I, steps, warmup, parity):
+    """The headline density on an elongated cell: two independent 86.8 A water
+    boxes stacked along z (131,070 atoms, 86.8 x 86.8 x 173.6 A) on a
+    64 x 64 x 128 grid (the same 1.36 A spacing), FP32/fixed path, timed as
+    the replay of one graph of `steps` steps over jittered frames."""
+    L = 86.8
+    K = (64, 64, 128)
+    a = I.water_box(21845, L, 2101)
+    b = I.water_box(21845, L, 2102)
+    pos = np.concatenate([a[0], b[0] + np.array([0.0, 0.0, L])])
+    q = np.concatenate([a[1], b[1]])
+    box = np.diag([L, L, 2 * L])
+    N = len(q)
+    F = 16
+    frames = I.jitter_stream(pos, F, I.HEADLINE_JITTER_SIGMA, 2103)
+    d_frames = torch.from_numpy(frames).to(dev)
+    d_q = torch.from_numpy(q).to(dev)
+    plan = Plan(K, 4, 0.34, max_atoms=N, device=dev)
+    forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    ev = torch.empty(7, dtype=torch.float64, device=dev)
+    for t in range(warmup):
+        plan.step(d_frames[t % F], d_q, box, forces=forces, ev=ev)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream(device=dev)
+    with torch.cuda.graph(g, stream=cs):
+        plan.set_stream(torch.cuda.current_stream(dev))
+        for t in range(steps):
+            plan.step(d_frames[t % F], d_q, box, forces=forces, ev=ev)
+    plan.set_stream(torch.cuda.current_stream(dev))
+    g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    g.replay()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    last = (steps - 1) % F
+    fg, eg = forces.clone(), ev.clone()
+    fe, ee = plan.step(d_frames[last], d_q, box)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(fg, fe)) and bool(torch.equal(eg, ee))
+    out = {"workload": "water_131070_k64x64x128", "atoms": N, "grid": list(K), "order": 4,
+           "beta": 0.34, "box_A": [L, L, 2 * L], "us_per_step": ms * 1e3,
+           "step_algorithmic_bytes": int(step_bytes(N, K)),
+           "step_roofline_frac": step_bytes(N, K) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "replay_same_as_eager": same}
+    if parity:
+        import oracle
+        ref = oracle.spme(frames[last], q, box, K, 4, 0.34)
+        out["force_rel_rms"] = float(np.linalg.norm(fe.cpu().numpy() - ref["forces"]) /
+                                     np.linalg.norm(ref["forces"]))
+        out["energy_rel"] = float(abs(ee[0].item() - ref["E"]) / abs(ref["E"]))
+    return out
+
+
 def bench_serving(torch, dev, I, n_requests, rate, budget_gib):
     """Open-loop Poisson arrivals over the batch mix plus four 128^3 boxes."""
     from paper_2009_12617_amd.serve import PoolSystem, Server
@@ -180,6 +241,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
+    ap.add_argument("--no-noncubic", action="store_true", help="skip the 64 x 64 x 128 grid run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -401,6 +463,13 @@ def main():
                 "launches": 6, "what": "pme_real: FP64 erfc pair sum, self term, water exclusions"}
         print(f"# real space: {ms_rs * 1e3:.1f} us per evaluation", file=sys.stderr, flush=True)
 
+    noncubic = None
+    if not args.no_noncubic:
+        noncubic = bench_noncubic(torch, dev, Plan, I, min(args.steps, 200), min(args.warmup, 20),
+                                  args.parity_frames > 0)
+        print(f"# non-cubic 64x64x128, 131,070 atoms: {noncubic['us_per_step']:.2f} us/step, "
+              f"replay == eager: {noncubic['replay_same_as_eager']}", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         from paper_2009_12617_amd import Batch
@@ -482,6 +551,7 @@ def main():
         "fp64_path": fp64,
         "half_spectrum_path": half,
         "real_space": real,
+        "non_cubic_grid": noncubic,
         "batched": batched,
         "serving": serving,
         "parity": parity,
