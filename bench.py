@@ -135,24 +135,18 @@ def bench_batched(torch, dev, Plan, Batch, I, reps=200):
     }
 
 
-def bench_noncubic(torch, dev, Plan, I, steps, warmup, parity):
-    """The headline density on an elongated cell: two independent 86.8 A water
-    boxes stacked along z (131,070 atoms, 86.8 x 86.8 x 173.6 A) on a
-    64 x 64 x 128 grid (the same 1.36 A spacing), FP32/fixed path, timed as
-    the replay of one graph of `steps` steps over jittered frames."""
-    L = 86.8
-    K = (64, 64, 128)
-    a = I.water_box(21845, L, 2101)
-    b = I.water_box(21845, L, 2102)
-    pos = np.concatenate([a[0], b[0] + np.array([0.0, 0.0, L])])
-    q = np.concatenate([a[1], b[1]])
-    box = np.diag([L, L, 2 * L])
+def bench_system(torch, dev, Plan, I, pos, q, box, K, order, beta, steps, warmup, parity, name,
+                 jitter_seed):
+    """One more single-system workload, FP32/fixed path: the replay of one graph
+    of `steps` steps over 16 jittered frames, per-kernel times from events on
+    the dispatches (host-launched steps), each kernel's algorithmic GB/s
+    against 8 TB/s, and the oracle's verdict on one frame."""
     N = len(q)
     F = 16
-    frames = I.jitter_stream(pos, F, I.HEADLINE_JITTER_SIGMA, 2103)
+    frames = I.jitter_stream(pos, F, I.HEADLINE_JITTER_SIGMA, jitter_seed)
     d_frames = torch.from_numpy(frames).to(dev)
     d_q = torch.from_numpy(q).to(dev)
-    plan = Plan(K, 4, 0.34, max_atoms=N, device=dev)
+    plan = Plan(K, order, beta, max_atoms=N, device=dev)
     forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
     ev = torch.empty(7, dtype=torch.float64, device=dev)
     for t in range(warmup):
@@ -180,18 +174,39 @@ def bench_noncubic(torch, dev, Plan, I, steps, warmup, parity):
     fe, ee = plan.step(d_frames[last], d_q, box)
     torch.cuda.synchronize()
     same = bool(torch.equal(fg, fe)) and bool(torch.equal(eg, ee))
-    out = {"workload": "water_131070_k64x64x128", "atoms": N, "grid": list(K), "order": 4,
-           "beta": 0.34, "box_A": [L, L, 2 * L], "us_per_step": ms * 1e3,
+    del g
+    plan.kernel_timing(True)
+    for t in range(steps):
+        plan.step(d_frames[t % F], d_q, box, forces=forces, ev=ev)
+    kms, ksteps = plan.kernel_times()
+    plan.kernel_timing(False)
+    kus = {k: v / max(ksteps, 1) * 1e3 for k, v in kms.items()}
+    kfrac = {k: algorithmic_bytes(N, K, k) / (kus[k] * 1e-6) / 1e9 / HBM_PEAK_GBS for k in kus}
+    K3 = list(K) if np.ndim(K) else [int(K)] * 3
+    out = {"workload": name, "atoms": N, "grid": K3, "order": order, "beta": beta,
+           "box_A": [float(box[i, i]) for i in range(3)], "us_per_step": ms * 1e3,
+           "kernels_us": kus, "kernels_roofline_frac": kfrac,
            "step_algorithmic_bytes": int(step_bytes(N, K)),
            "step_roofline_frac": step_bytes(N, K) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "replay_same_as_eager": same}
     if parity:
         import oracle
-        ref = oracle.spme(frames[last], q, box, K, 4, 0.34)
+        ref = oracle.spme(frames[last], q, box, K, order, beta)
         out["force_rel_rms"] = float(np.linalg.norm(fe.cpu().numpy() - ref["forces"]) /
                                      np.linalg.norm(ref["forces"]))
         out["energy_rel"] = float(abs(ee[0].item() - ref["E"]) / abs(ref["E"]))
     return out
+
+
+def stacked_water(I):
+    """The headline density on an elongated cell: two independent 86.8 A water
+    boxes stacked along z (131,070 atoms, 86.8 x 86.8 x 173.6 A)."""
+    L = 86.8
+    a = I.water_box(21845, L, 2101)
+    b = I.water_box(21845, L, 2102)
+    pos = np.concatenate([a[0], b[0] + np.array([0.0, 0.0, L])])
+    q = np.concatenate([a[1], b[1]])
+    return pos, q, np.diag([L, L, 2 * L])
 
 
 def bench_serving(torch, dev, I, n_requests, rate, budget_gib):
@@ -242,6 +257,7 @@ def main():
                     help="short run for a profiler: fixed steps, no oracle legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
     ap.add_argument("--no-noncubic", action="store_true", help="skip the 64 x 64 x 128 grid run")
+    ap.add_argument("--no-large", action="store_true", help="skip the 128^3 (209,715-atom) runs")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -463,12 +479,25 @@ def main():
                 "launches": 6, "what": "pme_real: FP64 erfc pair sum, self term, water exclusions"}
         print(f"# real space: {ms_rs * 1e3:.1f} us per evaluation", file=sys.stderr, flush=True)
 
-    noncubic = None
+    more = {}
+    legs = []
     if not args.no_noncubic:
-        noncubic = bench_noncubic(torch, dev, Plan, I, min(args.steps, 200), min(args.warmup, 20),
-                                  args.parity_frames > 0)
-        print(f"# non-cubic 64x64x128, 131,070 atoms: {noncubic['us_per_step']:.2f} us/step, "
-              f"replay == eager: {noncubic['replay_same_as_eager']}", file=sys.stderr, flush=True)
+        # 64 x 64 x 128 grid (the headline's 1.36 A spacing) on the stacked cell
+        pos2, q2, box2 = stacked_water(I)
+        legs.append(("water_131070_k64x64x128", pos2, q2, box2, (64, 64, 128), 4, 0.34, 2103))
+    if not args.no_large:
+        for wl in (I.LARGE_128_P4, I.LARGE_128_P6):
+            pos2, q2, box2 = wl.make()
+            legs.append((wl.name, pos2, q2, box2, wl.K, wl.order, wl.beta, 2104))
+    for name, pos2, q2, box2, K2, p2, b2, js in legs:
+        more[name] = bench_system(torch, dev, Plan, I, pos2, q2, box2, K2, p2, b2,
+                                  min(args.steps, 200), min(args.warmup, 20),
+                                  args.parity_frames > 0, name, js)
+        r = more[name]
+        print(f"# {name}: {r['us_per_step']:.2f} us/step, step at {100 * r['step_roofline_frac']:.1f}% "
+              f"of HBM roofline; per kernel " +
+              ", ".join(f"{k}={v:.1f} us ({100 * r['kernels_roofline_frac'][k]:.0f}%)"
+                        for k, v in r["kernels_us"].items()), file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -551,7 +580,7 @@ def main():
         "fp64_path": fp64,
         "half_spectrum_path": half,
         "real_space": real,
-        "non_cubic_grid": noncubic,
+        "more_workloads": more,
         "batched": batched,
         "serving": serving,
         "parity": parity,

@@ -12,14 +12,15 @@
 //                per workgroup (self term)
 //   k_rs_scan    one workgroup: exclusive prefix sum of the counts
 //   k_rs_fill    atoms into cell order (position, charge, original index)
-//   k_rs_pairs   one cell per workgroup: its atoms, two threads each, against
+//   k_rs_pairs   one cell per workgroup: its atoms, two lanes each, against
 //                the atoms of the 27 neighbour cells staged in LDS with their
-//                periodic shifts applied; then each atom's excluded
-//                partners; forces to the caller's order
+//                periodic shifts applied; pairs inside the cutoff are queued
+//                per wavefront and evaluated in batches of 64; then each
+//                atom's excluded partners; forces to the caller's order
 //   k_rs_reduce  energies from the per-workgroup rows, in a fixed order
-// Arithmetic is FP64 throughout.  The order of atoms inside a cell depends
-// on atomic ordering, so forces are reproducible to FP64 rounding, not bit
-// for bit.
+// Arithmetic is FP64 throughout.  The order of atoms inside a cell and of
+// the force additions depends on atomic ordering, so forces are
+// reproducible to FP64 rounding, not bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,14 +33,20 @@
 namespace spme {
 namespace {
 
-constexpr int kRsThreads = 256;     // threads of a cell workgroup
-constexpr int kRsHome = kRsThreads / 2;  // home atoms per pass (two threads each)
-constexpr int kRsStage = 2048;      // neighbour atoms staged in LDS per pass
+constexpr int kRsThreads = 128;     // threads of a pair workgroup (two wavefronts)
+constexpr int kRsHome = kRsThreads / 2;  // home atoms per pass (two lanes each)
+constexpr int kRsBlocks = 2;        // pair workgroups per cell (home atoms dealt out in passes)
+constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (< 2^24)
+constexpr int kRsUnroll = 2;        // candidates each lane tests per step
+static_assert(kRsStage % (2 * kRsUnroll) == 0, "the padded stage must fit");
+constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
+                                    // followed by one discard slot per lane
 constexpr int kRsCountThreads = 256;
 constexpr int kRsScanThreads = 1024;
 
 struct RsArgs {
   int N, nc[3], ncell, n_count_blocks;
+  int nrow;             // pair workgroups: ncell * kRsBlocks
   double L[3], invL[3], cell_inv[3];
   double beta, rc2, rcut, coulomb;
   const double* pos;
@@ -55,7 +62,7 @@ struct RsArgs {
   unsigned* cursor;     // [ncell]
   double4* rec;         // [N] wrapped position and charge, in cell order
   int* ridx;            // [N] original index, in cell order
-  double* rows;         // [ncell][2] pair and exclusion energies; then [n_count_blocks] q^2 sums
+  double* rows;         // [nrow][2] pair and exclusion energies; then [n_count_blocks] q^2 sums
 };
 
 __device__ __forceinline__ double wrap(double x, double L, double invL) {
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(kRsCountThreads) void k_rs_count(RsArgs a) {
     v[0] = a.q[i] * a.q[i];
   }
   block_sums<1>(v, wred);
-  if (threadIdx.x == 15) a.rows[2 * (size_t)a.ncell + blockIdx.x] = v[0];
+  if (threadIdx.x == 15) a.rows[2 * (size_t)a.nrow + blockIdx.x] = v[0];
 }
 
 // Exclusive prefix sum of the counts by one workgroup, in chunks of its size.
@@ -139,15 +146,36 @@ __global__ __launch_bounds__(256) void k_rs_fill(RsArgs a) {
   a.ridx[slot] = i;
 }
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
+// One candidate pair taken from a wavefront's queue: entry = (staged index
+// << 7) | home slot.  Adds the pair's energy to e and its force on the home
+// atom to hf (LDS atomics: a home atom's pairs are spread over lanes and
+// wavefronts).
+__device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, const double4* home,
+                                        double (*hf)[3], int entry, double& e) {
+  const double two_over_sqrtpi = 1.12837916709551257390;
+  const int t = entry >> 7, s = entry & 127;
+  const double4 rj = stage[t], ri = home[s];
+  const double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const double r = sqrt(r2), br = a.beta * r;
+  const double ec = erfc(br) / r;
+  const double qq = a.coulomb * ri.w * rj.w;
+  e += 0.5 * qq * ec;
+  const double g = qq * (ec + two_over_sqrtpi * a.beta * exp(-br * br)) / r2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) atomicAdd(&hf[s][c], g * d[c]);
+}
+
+__global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   __shared__ double4 stage[kRsStage];
-  __shared__ int sidx[kRsStage];
   __shared__ int nb_start[27], nb_pre[28];
   __shared__ double nb_shift[27][3];
-  __shared__ double fpart[kRsHome][3];
+  __shared__ double4 home[kRsHome];
+  __shared__ double hf[kRsHome][3];
+  __shared__ int queue[kRsThreads / 64][kRsQueue + 64];
   __shared__ double wred[16 * 8];
-  const int tid = threadIdx.x;
-  const int cell = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cell = blockIdx.x, blk = blockIdx.y;
   const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
   if (tid < 27) {
     // neighbour cell and the periodic shift that brings its atoms next to
@@ -183,50 +211,81 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
   const int h0 = (int)a.start[cell], h1 = (int)a.start[cell + 1];
   const double two_over_sqrtpi = 1.12837916709551257390;
   double e_pair = 0.0, e_excl = 0.0;
-  // each home atom takes two threads, which split its candidates (even and
-  // odd staged entries); their forces are added in a fixed order
-  const int slot = tid % kRsHome, part = tid / kRsHome;
-  for (int hb = h0; hb < h1; hb += kRsHome) {
-    const int h = hb + slot;
-    const bool mine = h < h1;
-    double4 ri = make_double4(0.0, 0.0, 0.0, 0.0);
-    int ii = -1;
-    if (mine) {
-      ri = a.rec[h];
-      ii = a.ridx[h];
+  int* wq = queue[wave];
+  // Home atoms of the cell in passes of up to kRsHome, pass i going to
+  // workgroup i mod kRsBlocks; two lanes per home atom (lane L: home L mod
+  // nh, candidates of parity L / nh).  Each lane tests its candidates in
+  // step with the wavefront (every lane reads the same staged atom); pairs
+  // inside the cutoff go to the wavefront's queue, and the erfc work runs
+  // only on full batches of 64 queued pairs, one per lane.
+  for (int hb = h0 + blk * kRsHome; hb < h1; hb += kRsBlocks * kRsHome) {
+    const int nh = min(kRsHome, h1 - hb);
+    const bool active = tid < 2 * nh;
+    const int slot = active ? tid % nh : 0, split = active ? tid / nh : 0;
+    __syncthreads();  // the previous pass is done with home and hf
+    if (tid < nh) {
+      home[tid] = a.rec[hb + tid];
+      hf[tid][0] = hf[tid][1] = hf[tid][2] = 0.0;
     }
-    double f[3] = {0.0, 0.0, 0.0};
+    // an idle lane sits far from every atom and never finds a pair
+    double4 ri = make_double4(-1e30, -1e30, -1e30, 0.0);
+    int ii = -1;
+    if (active) {
+      ri = a.rec[hb + slot];
+      ii = a.ridx[hb + slot];
+    }
     for (int s0 = 0; s0 < total; s0 += kRsStage) {
       const int sn = min(kRsStage, total - s0);
+      // padded to whole steps with atoms far away (never inside the cutoff)
+      const int snp = (sn + 2 * kRsUnroll - 1) / (2 * kRsUnroll) * (2 * kRsUnroll);
       __syncthreads();
-      for (int t = tid; t < sn; t += kRsThreads) {
+      for (int t = tid; t < snp; t += kRsThreads) {
+        if (t >= sn) {
+          stage[t] = make_double4(1e30, 1e30, 1e30, 0.0);
+          continue;
+        }
         const int g = s0 + t;
         int k = 0;
         while (nb_pre[k + 1] <= g) ++k;
         const int src = nb_start[k] + (g - nb_pre[k]);
         const double4 r = a.rec[src];
         stage[t] = make_double4(r.x + nb_shift[k][0], r.y + nb_shift[k][1], r.z + nb_shift[k][2], r.w);
-        sidx[t] = a.ridx[src];
       }
       __syncthreads();
-      if (mine) {
-        for (int t = part; t < sn; t += 2) {
-          const double4 rj = stage[t];
-          const double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
-          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-          if (r2 <= a.rc2 && sidx[t] != ii) {
-            const double r = sqrt(r2), br = a.beta * r;
-            const double ec = erfc(br) / r;
-            const double qq = a.coulomb * ri.w * rj.w;
-            e_pair += 0.5 * qq * ec;
-            const double g = qq * (ec + two_over_sqrtpi * a.beta * exp(-br * br)) / r2;
+      if (wave * 64 >= 2 * nh) continue;  // no active lane in this wavefront
+      // ring of queued pairs: head qh, length qn (uniform over the wavefront)
+      int qh = 0, qn = 0;
+      const int entry0 = (split << 7) | slot;
+      for (int t0 = 0; t0 < sn; t0 += 2 * kRsUnroll) {
+        // kRsUnroll candidates per lane, loads issued together
+        double4 rj[kRsUnroll];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f[c] += g * d[c];
-          }
+        for (int u = 0; u < kRsUnroll; ++u) rj[u] = stage[t0 + 2 * u + split];
+#pragma unroll
+        for (int u = 0; u < kRsUnroll; ++u) {
+          // branch-free: every lane writes, a miss into its discard slot.
+          // The home atom's own staged copy is at distance exactly 0.
+          const double d0 = ri.x - rj[u].x, d1 = ri.y - rj[u].y, d2 = ri.z - rj[u].z;
+          const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+          const bool hit = (r2 <= a.rc2) & (r2 > 0.0);
+          const unsigned long long m = __ballot(hit);
+          const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+          wq[hit ? ((qh + qn + below) & (kRsQueue - 1)) : kRsQueue + lane] =
+              entry0 + ((t0 + 2 * u) << 7);
+          qn += __popcll(m);
+        }
+        while (qn >= 64) {
+          lds_order();
+          rs_pair(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
+          qh += 64;
+          qn -= 64;
         }
       }
+      lds_order();
+      if (lane < qn) rs_pair(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
     }
-    if (mine && part == 0 && a.excl_off != nullptr) {
+    if (active && split == 0 && a.excl_off != nullptr) {
       // excluded partners: remove the erfc/r the pair sum took (inside the
       // cutoff) and the erf/r the reciprocal sum carries
       const double* pi = a.pos + 3 * (size_t)ii;
@@ -251,40 +310,33 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pairs(RsArgs a) {
         e_excl -= 0.5 * qq * u;
         const double g = qq * du / r;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) f[c] += g * d[c];
+        for (int c = 0; c < 3; ++c) atomicAdd(&hf[slot][c], g * d[c]);
       }
     }
     __syncthreads();
-    if (part == 1) {
+    if (tid < nh) {
+      double* out = a.forces + 3 * (size_t)a.ridx[hb + tid];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) fpart[slot][c] = f[c];
-    }
-    __syncthreads();
-    if (mine && part == 0) {
-      double* out = a.forces + 3 * (size_t)ii;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double fc = f[c] + fpart[slot][c];
-        out[c] = a.accumulate ? out[c] + fc : fc;
-      }
+      for (int c = 0; c < 3; ++c) out[c] = a.accumulate ? out[c] + hf[tid][c] : hf[tid][c];
     }
   }
   double v[2] = {e_pair, e_excl};
   block_sums<2>(v, wred);
   if (tid == 15) {
-    a.rows[2 * (size_t)cell] = v[0];
-    a.rows[2 * (size_t)cell + 1] = v[1];
+    const size_t row = (size_t)cell * kRsBlocks + blk;
+    a.rows[2 * row] = v[0];
+    a.rows[2 * row + 1] = v[1];
   }
 }
 
 // Energies in a fixed order by one wavefront: E_real, E_self, E_excl.
 __global__ __launch_bounds__(64) void k_rs_reduce(RsArgs a) {
   double v[3] = {0.0, 0.0, 0.0};
-  for (int r = threadIdx.x; r < a.ncell; r += 64) {
+  for (int r = threadIdx.x; r < a.nrow; r += 64) {
     v[0] += a.rows[2 * (size_t)r];
     v[2] += a.rows[2 * (size_t)r + 1];
   }
-  for (int r = threadIdx.x; r < a.n_count_blocks; r += 64) v[1] += a.rows[2 * (size_t)a.ncell + r];
+  for (int r = threadIdx.x; r < a.n_count_blocks; r += 64) v[1] += a.rows[2 * (size_t)a.nrow + r];
   wave_sums<3>(v);
   if (threadIdx.x == 63) {
     a.energies[0] = v[0];
@@ -308,7 +360,7 @@ RsLayout rs_layout(int max_atoms, int max_cells) {
   L.cursor = o;  o = align256(o + (size_t)max_cells * sizeof(unsigned));
   L.rec = o;     o = align256(o + (size_t)max_atoms * sizeof(double4));
   L.ridx = o;    o = align256(o + (size_t)max_atoms * sizeof(int));
-  L.rows = o;    o = align256(o + (2 * (size_t)max_cells + nblk) * sizeof(double));
+  L.rows = o;    o = align256(o + (2 * (size_t)max_cells * kRsBlocks + nblk) * sizeof(double));
   L.total = o;
   return L;
 }
@@ -367,6 +419,7 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
     a.nc[big] -= 1;
   }
   a.ncell = (int)ncell;
+  a.nrow = (int)ncell * kRsBlocks;
   a.N = N;
   a.n_count_blocks = (N + kRsCountThreads - 1) / kRsCountThreads;
   for (int d = 0; d < 3; ++d) {
@@ -401,7 +454,7 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
   }
   k_rs_scan<<<dim3(1), dim3(kRsScanThreads), 0, s>>>(a);
   if (N > 0) k_rs_fill<<<dim3(nb), dim3(256), 0, s>>>(a);
-  k_rs_pairs<<<dim3(a.ncell), dim3(kRsThreads), 0, s>>>(a);
+  k_rs_pairs<<<dim3(a.ncell, kRsBlocks), dim3(kRsThreads), 0, s>>>(a);
   k_rs_reduce<<<dim3(1), dim3(64), 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? PME_OK : PME_EDEVICE;
 }
