@@ -53,6 +53,16 @@ def step_bytes(N, K, fp64=False):
                ("bin", "spread_x", "convolve_yz", "interpolate"))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def source_digest():
     h = hashlib.sha256()
     for f in ("spme_kernels.hip", "spme_device.h"):
@@ -250,7 +260,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--parity-frames", type=int, default=3)
+    ap.add_argument("--parity-frames", type=int, default=1000,
+                    help="at most this many frames checked against the oracle (0: none)")
+    ap.add_argument("--parity-every", type=int, default=10,
+                    help="check every n-th frame of the timed run")
     ap.add_argument("--no-half", action="store_true", help="skip the binary16-spectrum variant")
     ap.add_argument("--no-real", action="store_true", help="skip the real-space term")
     ap.add_argument("--profile", action="store_true",
@@ -519,16 +532,30 @@ def main():
         import oracle
         oracle._load()
     if args.parity_frames > 0:
-        errs = []
-        pick = sorted(set(np.linspace(0, F - 1, args.parity_frames).astype(int).tolist()))
+        # every args.parity_every-th frame of the timed run, one host-launched
+        # step each, against the oracle (oracle calls run in threads: the C
+        # library releases the GIL)
+        from concurrent.futures import ThreadPoolExecutor
+        pick = list(range(0, F, max(1, args.parity_every)))[:max(args.parity_frames, 1)]
+        got = []
         for t in pick:
             f, e = plan.step(d_frames[t], d_q, box)
-            ref = oracle.spme(frames[t], q, box, K, w.order, w.beta)
-            fr = float(np.linalg.norm(f.cpu().numpy() - ref["forces"]) / np.linalg.norm(ref["forces"]))
-            er = float(abs(e[0].item() - ref["E"]) / abs(ref["E"]))
-            errs.append((fr, er))
-        parity = {"frames": pick, "force_rel_rms_max": max(x[0] for x in errs),
-                  "energy_rel_max": max(x[1] for x in errs), "reference": "FP64 CPU oracle"}
+            got.append((f.cpu().numpy(), float(e[0].item())))
+
+        def check(i):
+            ref = oracle.spme(frames[pick[i]], q, box, K, w.order, w.beta)
+            fr = float(np.linalg.norm(got[i][0] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+            return fr, float(abs(got[i][1] - ref["E"]) / abs(ref["E"]))
+
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            errs = list(ex.map(check, range(len(pick))))
+        parity = {"frames": len(pick), "every": args.parity_every,
+                  "force_rel_rms_max": max(x[0] for x in errs),
+                  "energy_rel_max": max(x[1] for x in errs),
+                  "within_bar": bool(all(x[0] <= 1e-5 and x[1] <= 1e-6 for x in errs)),
+                  "reference": "FP64 CPU oracle"}
+        print(f"# parity on {len(pick)} frames: force rel RMS max {parity['force_rel_rms_max']:.2e}, "
+              f"energy rel max {parity['energy_rel_max']:.2e}", file=sys.stderr, flush=True)
         if plan16 is not None:
             f, e = plan16.step(d_frames[pick[0]], d_q, box)
             ref = oracle.spme(frames[pick[0]], q, box, K, w.order, w.beta)
@@ -544,7 +571,25 @@ def main():
             n += 1
         dt = time.perf_counter() - t0
         cpu = {"value": dt / n * 1e6, "unit": "us/step", "cores": 1, "kind": "oracle",
-               "sample": f"{n} full oracle steps (single-threaded FP64 C) on frames 0..{n - 1} of the same workload"}
+               "sample": f"{n} full oracle steps (single-threaded FP64 C) on frames 0..{n - 1} of the same workload",
+               "host": cpu_model(), "nproc": os.cpu_count()}
+        # median of 5 steps with the oracle's own phase split, and the small
+        # and large workloads for context
+        def phases(pos_, q_, box_, K_, p_, b_, reps):
+            runs = [oracle.spme(pos_, q_, box_, K_, p_, b_, want_times=True)["times"] for _ in range(reps)]
+            tot = [sum(r.values()) for r in runs]
+            mid = runs[int(np.argsort(tot)[len(tot) // 2])]
+            return {"s_per_step": float(np.median(tot)), **{k: float(v) for k, v in mid.items()}}
+        cpu["median_of_5"] = phases(frames[0], q, box, K, w.order, w.beta, 5)
+        small = I.SMALL_32
+        ps, qs, bs = small.make()
+        cpu["water_4095_k32_median_of_5"] = phases(ps, qs, bs, small.K, small.order, small.beta, 5)
+        if not args.no_large:
+            for wl in (I.LARGE_128_P4, I.LARGE_128_P6):
+                pl, ql, bl = wl.make()
+                cpu[wl.name] = phases(pl, ql, bl, wl.K, wl.order, wl.beta, 1)
+        print(f"# oracle: {cpu['value'] / 1e3:.1f} ms/step on one core ({cpu['host']})",
+              file=sys.stderr, flush=True)
 
     us = ms_step * 1e3
     out = {

@@ -38,7 +38,7 @@
  * the ABI.
  *
  * Supported on the GPU: cubic grids K1 = K2 = K3 = K with
- * K in {16, 24, 32, 48, 64, 96, 128} and the non-cubic grids (K1, K2, K3) =
+ * K in {16, 24, 32, 36, 48, 64, 72, 96, 128} and the non-cubic grids (K1, K2, K3) =
  * (32, 32, 64), (64, 64, 128) and (48, 32, 64); spline order p in {4, 6};
  * any non-degenerate cell (diagonal boxes take a separable fast path for the
  * influence function).  Anything else returns PME_EUNSUPPORTED.

@@ -178,24 +178,29 @@ struct Dft<8, S, T> {
 // butterfly count N/R is a multiple of it.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int fft_nstages(int N) {
-  return N == 8 ? 2 : N == 12 ? 3 : N == 16 ? 2 : N == 24 ? 3 : N == 32 ? 2 : N == 48 ? 3
-       : N == 64 ? 2 : N == 96 ? 4 : N == 128 ? 3 : 0;
+  return N == 8 ? 2 : N == 12 ? 3 : N == 16 ? 2 : N == 18 ? 3 : N == 24 ? 3 : N == 32 ? 2
+       : N == 36 ? 4 : N == 48 ? 3 : N == 64 ? 2 : N == 72 ? 5 : N == 96 ? 4 : N == 128 ? 3 : 0;
 }
 __host__ __device__ constexpr int fft_radix(int N, int s) {
   return N == 8 ? (s == 0 ? 4 : 2)
        : N == 12 ? (s < 2 ? 2 : 3)
        : N == 16 ? 4
+       : N == 18 ? (s == 0 ? 2 : 3)
        : N == 24 ? (s == 0 ? 4 : s == 1 ? 2 : 3)
        : N == 32 ? (s == 0 ? 8 : 4)
+       : N == 36 ? (s < 2 ? 2 : 3)
        : N == 48 ? (s < 2 ? 4 : 3)
        : N == 64 ? 8
+       : N == 72 ? (s < 3 ? 2 : 3)
        : N == 96 ? (s < 2 ? 4 : s == 2 ? 2 : 3)
        : N == 128 ? (s == 0 ? 8 : 4)
        : 0;
 }
+// (a power of two that divides every stage's butterfly count: 18 has stages
+// of 9 and 6 butterflies, so one lane per pencil)
 __host__ __device__ constexpr int fft_lanes(int N) {
-  return N == 8 ? 2 : N == 12 ? 2 : N == 16 ? 4 : N == 24 ? 2 : N == 32 ? 4 : N == 48 ? 4
-       : N == 64 ? 8 : N == 96 ? 8 : N == 128 ? 16 : 0;
+  return N == 8 ? 2 : N == 12 ? 2 : N == 16 ? 4 : N == 18 ? 1 : N == 24 ? 2 : N == 32 ? 4
+       : N == 36 ? 2 : N == 48 ? 4 : N == 64 ? 8 : N == 72 ? 4 : N == 96 ? 8 : N == 128 ? 16 : 0;
 }
 __host__ __device__ constexpr int fft_span(int N, int s) {  // product of the radices before s
   return s == 0 ? 1 : fft_span(N, s - 1) * fft_radix(N, s - 1);

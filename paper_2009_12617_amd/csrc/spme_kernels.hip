@@ -829,7 +829,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = pl + K2 * PC;
   const int tid = threadIdx.x;
-  const int z = xcd_local(blockIdx.x, K3);
+  // (the XCD remap needs a multiple of 8 planes)
+  const int z = K3 % kXcds == 0 ? xcd_local(blockIdx.x, K3) : (int)blockIdx.x;
   const typename P::spec* spec = reinterpret_cast<const typename P::spec*>(a.ws + a.lay.spec);
   for (int i = tid; i < KH * K2; i += kPlaneThreads) {
     const int x = i / K2, y = i - x * K2;
@@ -1070,8 +1071,8 @@ hipError_t with_prec(int prec, F&& f) {
   if (prec == PME_FP32_FIXED_HALF) return f(PHalf{});
   return hipErrorInvalidValue;
 }
-// Supported grids: cubic K = 16, 24, 32, 48, 64, 96, 128, and the non-cubic
-// shapes 32 x 32 x 64, 64 x 64 x 128 and 48 x 32 x 64 (x, y, z).
+// Supported grids: cubic K = 16, 24, 32, 36, 48, 64, 72, 96, 128, and the
+// non-cubic shapes 32 x 32 x 64, 64 x 64 x 128 and 48 x 32 x 64 (x, y, z).
 template <class F>
 hipError_t with_grid(int K1, int K2, int K3, F&& f) {
   if (K1 == K2 && K2 == K3) {
@@ -1079,8 +1080,10 @@ hipError_t with_grid(int K1, int K2, int K3, F&& f) {
       case 16: return f(Grid<16, 16, 16>{});
       case 24: return f(Grid<24, 24, 24>{});
       case 32: return f(Grid<32, 32, 32>{});
+      case 36: return f(Grid<36, 36, 36>{});
       case 48: return f(Grid<48, 48, 48>{});
       case 64: return f(Grid<64, 64, 64>{});
+      case 72: return f(Grid<72, 72, 72>{});
       case 96: return f(Grid<96, 96, 96>{});
       case 128: return f(Grid<128, 128, 128>{});
       default: return hipErrorInvalidValue;

@@ -44,8 +44,10 @@ SMALL = [
     ("k16_p4", 150, 14.0, 16, 4, 0.40),
     ("k24_p6", 400, 18.0, 24, 6, 0.38),
     ("k32_p4", 1365, 32.0, 32, 4, 0.35),
+    ("k36_p6", 1100, 33.0, 36, 6, 0.36),
     ("k48_p4", 2000, 40.0, 48, 4, 0.34),
     ("k64_p6", 1700, 38.0, 64, 6, 0.34),
+    ("k72_p4", 2500, 62.0, 72, 4, 0.34),
     ("k96_p4", 3000, 60.0, 96, 4, 0.34),
     ("k128_p6", 1000, 50.0, 128, 6, 0.34),
 ]
