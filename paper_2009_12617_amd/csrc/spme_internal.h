@@ -64,6 +64,8 @@ struct Layout {
   size_t rec;      // records [2 K3 nq][cap] (RecF or RecD): one bucket per bin
   size_t orec;     // records [max_atoms]: atoms that found their bucket full
   size_t spec;     // complex[K1/2+1][K3][K2] half spectrum, columns [x'][z][y]
+  size_t mid;      // complex[K1/2+1][K3][K2] at full precision between the split convolution
+                   // passes of a binary16-spectrum plan; otherwise the same region as spec
   size_t phi;      // real[K3][K2][phi_pitch]: potential rows with a (p-1) wrap halo in front
   size_t partial;  // double[partial_rows][8]: energy/virial partial sums
   size_t dbg;      // int64 or double [K3][K2][K1]: charge-grid copy (debug)

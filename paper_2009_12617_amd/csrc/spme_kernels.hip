@@ -450,12 +450,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
 // the K3 x K2 column does not fit in LDS (FP64, 128^3) it is staged through
 // the workspace in halves.
 // ---------------------------------------------------------------------------
-// Threads per column: 1024, or 512 where the FP64 radix stages of 128-point
-// pencils need more than the 128 registers a 1024-thread workgroup leaves
-// per lane.
+// Threads per column: 1024, or 512 where the FP64 radix stages of long
+// pencils (72 points and up) need more than the 128 registers a 1024-thread
+// workgroup leaves per lane.
 template <class P, class G>
 __host__ __device__ constexpr int conv_threads() {
-  return (sizeof(typename P::real) == 8 && (G::K2 >= 128 || G::K3 >= 128)) ? 512 : 1024;
+  return (sizeof(typename P::real) == 8 && (G::K2 >= 72 || G::K3 >= 72)) ? 512 : 1024;
 }
 template <class P, class G>
 __host__ __device__ constexpr size_t conv_tables_bytes() {
@@ -498,6 +498,187 @@ __host__ __device__ constexpr size_t conv_lds_bytes() {
   return conv_buf_bytes<P, G>() + conv_tables_bytes<P, G>();
 }
 
+// Per-axis factors T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) of an
+// orthorhombic cell (a general cell keeps the bare moduli: its Gaussian does
+// not factor), x then y then z, into bs[K1 + K2 + K3].
+template <class G, int NT>
+__device__ __forceinline__ void axis_factors(const Args& a, double* bs) {
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr double PI = 3.14159265358979323846;
+  const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
+  const double fac = PI * PI / (a.beta * a.beta);
+  // (values selected, not a.invL[ax]: a dynamic index, or a select of
+  // addresses, would move a batched run's Args copy to scratch)
+  const double il0 = a.invL[0], il1 = a.invL[1], il2 = a.invL[2];
+  for (int i = threadIdx.x; i < K1 + K2 + K3; i += NT) {
+    const int ax = i < K1 ? 0 : i < K1 + K2 ? 1 : 2;
+    const int Ka = ax == 0 ? K1 : ax == 1 ? K2 : K3;
+    const int m = i - (ax == 0 ? 0 : ax == 1 ? K1 : K1 + K2);
+    const int mt = (2 * m <= Ka) ? m : m - Ka;
+    const double il = ax == 0 ? il0 : ax == 1 ? il1 : il2;
+    const double u = mt * il;
+    bs[i] = a.triclinic ? bsg[i] : bsg[i] * exp(-fac * u * u);
+  }
+}
+
+// The convolution's extra workgroup: keeps the bucket counts of this step
+// for the interpolation pass and clears them (and the overflow count) for
+// the next step's binning; checks the fixed-point headroom.
+template <class P, class G, int NT>
+__device__ __forceinline__ void keep_counts(const Args& a, double* wred) {
+  const int tid = threadIdx.x;
+  unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
+  unsigned* bcnt2 = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt2);
+  unsigned* ovf = reinterpret_cast<unsigned*>(a.ws + a.lay.ovf);
+  constexpr int NBINS = 2 * G::K3 * nq_of(G::K2, P::fixed);
+  for (int b = tid; b < NBINS; b += NT) {
+    bcnt2[b] = bcnt[b];
+    bcnt[b] = 0u;
+  }
+  if (tid == 0) {
+    ovf[1] = ovf[0];
+    ovf[0] = 0u;
+  }
+  if constexpr (P::fixed) {
+    // sum |q| 2^F must stay below 2^51 so that every contribution and grid
+    // value is exact in FP64 and the rounding of to_fixed holds
+    const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
+    double v[1] = {0.0};
+    for (int c = tid; c < a.n_chunks; c += NT) v[0] += absq[c];
+    block_sums<1>(v, wred);
+    if (tid == 15 && v[0] * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
+      atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
+  }
+}
+
+// Influence function on z-transformed modes of column x' = xp held in LDS as
+// buf[z * PZ + yy] (z < K3, y = y0 + yy, yy < CY): each mode is multiplied
+// by G(m) and its energy/virial terms are added to acc.
+// G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) with
+// B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3) in an orthorhombic
+// cell.  The half spectrum counts every m1 = 1 .. K1/2-1 twice (its
+// Hermitian partner), m1 = 0 and m1 = K1/2 once.  Per mode, with
+// e = w G |F|^2 and u = 1/|m|^2 + pi^2/beta^2:
+//   E += e,  P_ab += e (delta_ab - 2 u m_a m_b),
+// accumulated as S0 = sum e and S_ab = sum e u m_a m_b (acc: S0, Sxx, Syy,
+// Szz, Sxy, Sxz, Syz), so that P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A
+// Nyquist index aliases +K_a/2 and -K_a/2 equally, so its sign-odd
+// (off-diagonal) products vanish.
+template <class P, class G, int CY, int PZ, int NT>
+__device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>* buf, int xp,
+                                          int y0, const double* bs, double* acc) {
+  using T = typename P::real;
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr double PI = 3.14159265358979323846;
+  const int tid = threadIdx.x;
+  const double pref = a.coulomb / (PI * a.volume);
+  const double fac = PI * PI / (a.beta * a.beta);
+  const double mvx = xp * a.invL[0];
+  const double nx = (2 * xp == K1) ? 0.0 : mvx;
+  const double wx = (xp == 0 || 2 * xp == K1) ? 0.5 : 1.0;
+  const double mvx2 = mvx * mvx;
+  const double A = pref * bs[xp];
+  if (a.triclinic) {
+    // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
+    // each Nyquist index is averaged over its two signs explicitly
+    for (int i = tid; i < K3 * CY; i += NT) {
+      const int z = i / CY, yy = i - z * CY, y = y0 + yy;
+      const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
+      const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
+      const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
+      const cplx<T> f = buf[z * PZ + yy];
+      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+      double gm = 0.0;  // G(m), averaged over the Nyquist signs
+      if (xp != 0 || y != 0 || z != 0) {
+        const double Bw = A * bs[K1 + y] * bs[K1 + K2 + z] / nvar;
+        for (int v = 0; v < nvar; ++v) {
+          double ms[3];
+          int bit = 0;
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            ms[ax] = ms0[ax];
+            if (ny3[ax]) {
+              if ((v >> bit) & 1) ms[ax] = -ms[ax];
+              ++bit;
+            }
+          }
+          double mv[3];
+#pragma unroll
+          for (int c2 = 0; c2 < 3; ++c2)
+            mv[c2] = ms[0] * a.rec[c2] + ms[1] * a.rec[3 + c2] + ms[2] * a.rec[6 + c2];
+          const double msq = mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2];
+          double r = __builtin_amdgcn_rcp(msq);
+          r = fma(r, fma(-msq, r, 1.0), r);
+          r = fma(r, fma(-msq, r, 1.0), r);
+          const double Gv = Bw * exp(-fac * msq) * r;
+          const double e = wx * Gv * f2;
+          const double eu = e * (r + fac);
+          acc[0] += e;
+          acc[1] = fma(eu * mv[0], mv[0], acc[1]);
+          acc[2] = fma(eu * mv[1], mv[1], acc[2]);
+          acc[3] = fma(eu * mv[2], mv[2], acc[3]);
+          acc[4] = fma(eu * mv[0], mv[1], acc[4]);
+          acc[5] = fma(eu * mv[0], mv[2], acc[5]);
+          acc[6] = fma(eu * mv[1], mv[2], acc[6]);
+          gm += Gv;
+        }
+      }
+      const T g = (T)gm;
+      buf[z * PZ + yy] = {f.x * g, f.y * g};
+    }
+  } else {
+    constexpr int NIT = (K3 * CY + NT - 1) / NT;
+    constexpr int UNR = NIT <= 4 ? NIT : 2;
+#pragma unroll UNR
+    for (int it = 0; it < NIT; ++it) {
+      const int i = tid + it * NT;
+      if ((K3 * CY) % NT != 0 && i >= K3 * CY) break;
+      const int z = i / CY, yy = i - z * CY, y = y0 + yy;
+      const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
+      const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
+      const double ny = (2 * y == K2) ? 0.0 : mvy, nz = (2 * z == K3) ? 0.0 : mvz;
+      const cplx<T> f = buf[z * PZ + yy];
+      // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
+      // its G by 0, without a branch
+      const bool m0 = (xp == 0) && (y == 0) && (z == 0);
+      const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
+      // 1/msq: hardware reciprocal and two Newton steps
+      double r = __builtin_amdgcn_rcp(msq);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      const double gm = m0 ? 0.0 : A * bs[K1 + y] * bs[K1 + K2 + z] * r;  // G(m)
+      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+      const double e = wx * gm * f2;
+      const double eu = e * (r + fac);
+      const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
+      acc[0] += e;
+      acc[1] = fma(eux, mvx, acc[1]);
+      acc[2] = fma(euy, mvy, acc[2]);
+      acc[3] = fma(eu * mvz, mvz, acc[3]);
+      acc[4] = fma(eun, ny, acc[4]);
+      acc[5] = fma(eun, nz, acc[5]);
+      acc[6] = fma(eu * ny, nz, acc[6]);
+      const T g = (T)gm;
+      buf[z * PZ + yy] = {f.x * g, f.y * g};
+    }
+  }
+}
+
+// Energy/virial: a fixed-order DPP sum over each wavefront, one partial row
+// (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz) per wavefront at row `first + wave`,
+// added in row order later.
+__device__ __forceinline__ void ev_row(const Args& a, double* acc, int first) {
+  wave_sums<7>(acc);
+  if ((threadIdx.x & 63) == 63) {
+    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + (first + (threadIdx.x >> 6)) * 8;
+    row[0] = acc[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
+#pragma unroll
+    for (int c = 4; c < 7; ++c) row[c] = -2.0 * acc[c];
+  }
+}
+
 template <class P, class G, bool BATCH>
 __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
@@ -511,7 +692,6 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   constexpr int PZ = conv_zpitch<P, G>();      // z pass: one row of pitch PZ per z
   constexpr int TY = fft_lanes(K2), TZ = fft_lanes(K3);
   constexpr int NT = conv_threads<P, G>();
-  constexpr double PI = 3.14159265358979323846;
   static_assert(conv_lds_bytes<P, G>() <= kMaxLds, "convolution column does not fit in LDS");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
@@ -522,38 +702,13 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   TRACE(2, 0);
   const int tid = threadIdx.x;
   if (blockIdx.x == KH) {
-    // the extra workgroup: keeps the bucket counts of this step for the
-    // interpolation pass and clears them (and the overflow count) for the
-    // next step's binning
-    unsigned* bcnt = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt);
-    unsigned* bcnt2 = reinterpret_cast<unsigned*>(a.ws + a.lay.bcnt2);
-    unsigned* ovf = reinterpret_cast<unsigned*>(a.ws + a.lay.ovf);
-    constexpr int NBINS = 2 * K3 * nq_of(K2, P::fixed);
-    for (int b = tid; b < NBINS; b += NT) {
-      bcnt2[b] = bcnt[b];
-      bcnt[b] = 0u;
-    }
-    if (tid == 0) {
-      ovf[1] = ovf[0];
-      ovf[0] = 0u;
-    }
-    if constexpr (P::fixed) {
-      // sum |q| 2^F must stay below 2^51 so that every contribution and grid
-      // value is exact in FP64 and the rounding of to_fixed holds
-      const double* absq = reinterpret_cast<const double*>(a.ws + a.lay.absq);
-      double v[1] = {0.0};
-      for (int c = tid; c < a.n_chunks; c += NT) v[0] += absq[c];
-      block_sums<1>(v, wred);
-      if (tid == 15 && v[0] * ldexp(1.0, a.frac_bits) >= 2251799813685248.0)
-        atomicOr(reinterpret_cast<unsigned*>(a.ws + a.lay.ctrl), PME_FLAG_OVERFLOW);
-    }
+    keep_counts<P, G, NT>(a, wred);
     return;
   }
   const int xp = blockIdx.x;  // m1
   using S = typename P::spec;
   S* col = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)xp * K3 * K2;  // [z][y]
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  const double* bsg = reinterpret_cast<const double*>(a.ws + a.lay.bsq);
   // the first chunk's loads are issued before the tables are computed
   // (when they fit in a few registers)
   constexpr int EPT = (CZ * K2 + NT - 1) / NT;
@@ -568,22 +723,7 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   }
   // the y and z twiddle tables follow the x table
   for (int i = tid; i < K2 + K3; i += NT) twy[i] = twg[K1 + i];
-  {
-    // T_a(m) = |b_a(m)|^2 exp(-pi^2 mt^2 / (beta L_a)^2) per axis
-    const double fac = PI * PI / (a.beta * a.beta);
-    for (int i = tid; i < K1 + K2 + K3; i += NT) {
-      const int ax = i < K1 ? 0 : i < K1 + K2 ? 1 : 2;
-      const int Ka = ax == 0 ? K1 : ax == 1 ? K2 : K3;
-      const int m = i - (ax == 0 ? 0 : ax == 1 ? K1 : K1 + K2);
-      const int mt = (2 * m <= Ka) ? m : m - Ka;
-      // (a select, not a[ax]: a dynamic index would move a batched run's
-      // Args copy to scratch)
-      const double il = ax == 0 ? a.invL[0] : ax == 1 ? a.invL[1] : a.invL[2];
-      const double u = mt * il;
-      // a general cell keeps the bare moduli: its Gaussian does not factor
-      bs[i] = a.triclinic ? bsg[i] : bsg[i] * exp(-fac * u * u);
-    }
-  }
+  axis_factors<G, NT>(a, bs);
 
   // --- forward y: one pencil per z
   for (int c = 0; c < NC; ++c) {
@@ -616,23 +756,8 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   }
   TRACE(2, 1);
 
-  // --- z: forward transform, influence function, inverse transform.
-  // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) with
-  // B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3) in an orthorhombic
-  // cell.  The half spectrum counts every m1 = 1 .. K1/2-1 twice (its
-  // Hermitian partner), m1 = 0 and m1 = K1/2 once.  Per mode, with
-  // e = w G |F|^2 and u = 1/|m|^2 + pi^2/beta^2:
-  //   E += e,  P_ab += e (delta_ab - 2 u m_a m_b),
-  // accumulated as S0 = sum e and S_ab = sum e u m_a m_b, so that
-  // P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A Nyquist index aliases +K_a/2
-  // and -K_a/2 equally, so its sign-odd (off-diagonal) products vanish.
-  const double pref = a.coulomb / (PI * a.volume);
-  const double fac = PI * PI / (a.beta * a.beta);
-  const double mvx = xp * a.invL[0];
-  const double nx = (2 * xp == K1) ? 0.0 : mvx;
-  const double wx = (xp == 0 || 2 * xp == K1) ? 0.5 : 1.0;
-  const double mvx2 = mvx * mvx;
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // S0, Sxx, Syy, Szz, Sxy, Sxz, Syz
+  // --- z: forward transform, influence function, inverse transform
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int c = 0; c < NC; ++c) {
     const int y0 = c * CY;
     if constexpr (NC > 1) {
@@ -648,91 +773,7 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
     }
     __syncthreads();
     TRACE(2, 2);
-    const double A = pref * bs[xp];
-    if (a.triclinic) {
-      // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
-      // each Nyquist index is averaged over its two signs explicitly
-      for (int i = tid; i < K3 * CY; i += NT) {
-        const int z = i / CY, yy = i - z * CY, y = y0 + yy;
-        const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
-        const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
-        const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
-        const cplx<T> f = buf[z * PZ + yy];
-        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-        double gm = 0.0;  // G(m), averaged over the Nyquist signs
-        if (xp != 0 || y != 0 || z != 0) {
-          const double Bw = A * bs[K1 + y] * bs[K1 + K2 + z] / nvar;
-          for (int v = 0; v < nvar; ++v) {
-            double ms[3];
-            int bit = 0;
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-              ms[ax] = ms0[ax];
-              if (ny3[ax]) {
-                if ((v >> bit) & 1) ms[ax] = -ms[ax];
-                ++bit;
-              }
-            }
-            double mv[3];
-#pragma unroll
-            for (int c2 = 0; c2 < 3; ++c2)
-              mv[c2] = ms[0] * a.rec[c2] + ms[1] * a.rec[3 + c2] + ms[2] * a.rec[6 + c2];
-            const double msq = mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2];
-            double r = __builtin_amdgcn_rcp(msq);
-            r = fma(r, fma(-msq, r, 1.0), r);
-            r = fma(r, fma(-msq, r, 1.0), r);
-            const double Gv = Bw * exp(-fac * msq) * r;
-            const double e = wx * Gv * f2;
-            const double eu = e * (r + fac);
-            acc[0] += e;
-            acc[1] = fma(eu * mv[0], mv[0], acc[1]);
-            acc[2] = fma(eu * mv[1], mv[1], acc[2]);
-            acc[3] = fma(eu * mv[2], mv[2], acc[3]);
-            acc[4] = fma(eu * mv[0], mv[1], acc[4]);
-            acc[5] = fma(eu * mv[0], mv[2], acc[5]);
-            acc[6] = fma(eu * mv[1], mv[2], acc[6]);
-            gm += Gv;
-          }
-        }
-        const T g = (T)gm;
-        buf[z * PZ + yy] = {f.x * g, f.y * g};
-      }
-    } else {
-      constexpr int NIT = (K3 * CY + NT - 1) / NT;
-      constexpr int UNR = NIT <= 4 ? NIT : 2;
-#pragma unroll UNR
-      for (int it = 0; it < NIT; ++it) {
-        const int i = tid + it * NT;
-        if ((K3 * CY) % NT != 0 && i >= K3 * CY) break;
-        const int z = i / CY, yy = i - z * CY, y = y0 + yy;
-        const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
-        const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
-        const double ny = (2 * y == K2) ? 0.0 : mvy, nz = (2 * z == K3) ? 0.0 : mvz;
-        const cplx<T> f = buf[z * PZ + yy];
-        // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
-        // its G by 0, without a branch
-        const bool m0 = (xp == 0) && (y == 0) && (z == 0);
-        const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
-        // 1/msq: hardware reciprocal and two Newton steps
-        double r = __builtin_amdgcn_rcp(msq);
-        r = fma(r, fma(-msq, r, 1.0), r);
-        r = fma(r, fma(-msq, r, 1.0), r);
-        const double gm = m0 ? 0.0 : A * bs[K1 + y] * bs[K1 + K2 + z] * r;  // G(m)
-        const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-        const double e = wx * gm * f2;
-        const double eu = e * (r + fac);
-        const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
-        acc[0] += e;
-        acc[1] = fma(eux, mvx, acc[1]);
-        acc[2] = fma(euy, mvy, acc[2]);
-        acc[3] = fma(eu * mvz, mvz, acc[3]);
-        acc[4] = fma(eun, ny, acc[4]);
-        acc[5] = fma(eun, nz, acc[5]);
-        acc[6] = fma(eu * ny, nz, acc[6]);
-        const T g = (T)gm;
-        buf[z * PZ + yy] = {f.x * g, f.y * g};
-      }
-    }
+    influence<P, G, CY, PZ, NT>(a, buf, xp, y0, bs, acc);
     __syncthreads();
     TRACE(2, 3);
     for (int task = tid; task < CY * TZ; task += NT) {
@@ -771,19 +812,133 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
     }
     if constexpr (NC > 1) __syncthreads();
   }
-  // Energy/virial: a fixed-order DPP sum over each wavefront, one partial
-  // row (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz) per wavefront, added in row order
-  // later; placed after the last stores so that it overlaps their completion.
-  wave_sums<7>(acc);
-  if ((tid & 63) == 63) {
-    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + (xp * (NT / 64) + (tid >> 6)) * 8;
-    row[0] = acc[0];
-#pragma unroll
-    for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
-#pragma unroll
-    for (int c = 4; c < 7; ++c) row[c] = -2.0 * acc[c];
-  }
+  // placed after the last stores so that it overlaps their completion
+  ev_row(a, acc, xp * (NT / 64));
   TRACE(2, 15);
+}
+
+// ---------------------------------------------------------------------------
+// Large columns (K2 K3 >= 8192, e.g. 128^3, where one workgroup per x'
+// column leaves most of the chip idle and makes the FP64 influence function
+// a one-CU job): the convolution runs as three launches of small workgroups,
+// with the half spectrum in the workspace between them --
+//   k_conv_y<-1>  forward y transforms of a chunk of z-rows of one column
+//   k_conv_z      z transforms, influence function and inverse z transforms
+//                 of a chunk of y-columns of one column (plus the counts
+//                 workgroup)
+//   k_conv_y<+1>  inverse y transforms
+// ---------------------------------------------------------------------------
+template <class G>
+__host__ __device__ constexpr bool conv_split() {
+  return G::K2 * G::K3 >= 8192;
+}
+constexpr int kPassThreads = 256;
+template <class G>
+__host__ __device__ constexpr int pass_cz() {  // z-rows per y-pass workgroup
+  return kPassThreads / fft_lanes(G::K2);
+}
+template <class G>
+__host__ __device__ constexpr int pass_cy() {  // y-columns per z-pass workgroup
+  return kPassThreads / fft_lanes(G::K3);
+}
+template <class P, class G>
+__host__ __device__ constexpr size_t conv_y_lds_bytes() {
+  return ((size_t)pass_cz<G>() * conv_pitch<P>(G::K2) + G::K2) * sizeof(cplx<typename P::real>);
+}
+template <class P, class G>
+__host__ __device__ constexpr size_t conv_z_lds_bytes() {
+  return ((size_t)G::K3 * (pass_cy<G>() + 1) + G::K3) * sizeof(cplx<typename P::real>) +
+         (size_t)(G::K1 + G::K2 + G::K3) * sizeof(double) + 16 * 8 * sizeof(double);
+}
+
+// (the forward pass reads the spectrum and writes the full-precision
+// intermediate; the inverse pass the other way round; the two are one
+// region unless the spectrum is kept in binary16)
+template <class P, class G, int DIR, bool BATCH>
+__global__ __launch_bounds__(kPassThreads) void k_conv_y(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  using T = typename P::real;
+  using S = typename P::spec;
+  using M = cplx<T>;
+  using In = std::conditional_t<(DIR < 0), S, M>;
+  using Out = std::conditional_t<(DIR < 0), M, S>;
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  constexpr int CZ = pass_cz<G>(), NZC = K3 / CZ;
+  constexpr int PY = conv_pitch<P>(K2), TY = fft_lanes(K2);
+  static_assert(K3 % CZ == 0 && CZ * TY == kPassThreads, "y pass chunks do not tile the column");
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + CZ * PY;
+  const int tid = threadIdx.x;
+  const int xp = blockIdx.x / NZC, z0 = (blockIdx.x - xp * NZC) * CZ;
+  const size_t off = ((size_t)xp * K3 + z0) * K2;  // rows [zz][y]
+  const In* src = reinterpret_cast<const In*>(a.ws + (DIR < 0 ? a.lay.spec : a.lay.mid)) + off;
+  Out* dst = reinterpret_cast<Out*>(a.ws + (DIR < 0 ? a.lay.mid : a.lay.spec)) + off;
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+  for (int i = tid; i < CZ * K2; i += kPassThreads) {
+    const int zz = i / K2, y = i - zz * K2;
+    buf[zz * PY + y] = spec_ld(&src[i]);
+  }
+  for (int i = tid; i < K2; i += kPassThreads) tw[i] = twg[K1 + i];
+  __syncthreads();
+  {
+    const int zz = tid / TY, l = tid - zz * TY;
+    fft_pencil<T, K2, DIR>(buf + zz * PY, 1, l, tw, 1);
+  }
+  __syncthreads();
+  for (int i = tid; i < CZ * K2; i += kPassThreads) {
+    const int zz = i / K2, y = i - zz * K2;
+    spec_st(&dst[i], buf[zz * PY + y]);
+  }
+}
+
+template <class P, class G, bool BATCH>
+__global__ __launch_bounds__(kPassThreads) void k_conv_z(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  using T = typename P::real;
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3, KH = K1 / 2 + 1;
+  constexpr int CY = pass_cy<G>(), NYC = K2 / CY, PZ = CY + 1, TZ = fft_lanes(K3);
+  constexpr int NT = kPassThreads;
+  static_assert(K2 % CY == 0 && CY * TZ == NT, "z pass chunks do not tile the column");
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + K3 * PZ;
+  double* bs = reinterpret_cast<double*>(tw + K3);  // x, y, z factors
+  double* wred = bs + K1 + K2 + K3;
+  const int tid = threadIdx.x;
+  TRACE(4, 0);
+  if (blockIdx.x == KH * NYC) {
+    keep_counts<P, G, NT>(a, wred);
+    return;
+  }
+  const int xp = blockIdx.x / NYC, y0 = (blockIdx.x - xp * NYC) * CY;
+  cplx<T>* col = reinterpret_cast<cplx<T>*>(a.ws + a.lay.mid) + (size_t)xp * K3 * K2;  // [z][y]
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+  for (int i = tid; i < K3 * CY; i += NT) {
+    const int z = i / CY, yy = i - z * CY;
+    buf[z * PZ + yy] = spec_ld(&col[(size_t)z * K2 + y0 + yy]);
+  }
+  for (int i = tid; i < K3; i += NT) tw[i] = twg[K1 + K2 + i];
+  axis_factors<G, NT>(a, bs);
+  __syncthreads();
+  TRACE(4, 1);
+  const int yy = tid / TZ, l = tid - yy * TZ;
+  fft_pencil<T, K3, -1>(buf + yy, PZ, l, tw, 1);
+  __syncthreads();
+  TRACE(4, 2);
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  influence<P, G, CY, PZ, NT>(a, buf, xp, y0, bs, acc);
+  __syncthreads();
+  TRACE(4, 3);
+  fft_pencil<T, K3, 1>(buf + yy, PZ, l, tw, 1);
+  __syncthreads();
+  TRACE(4, 4);
+  for (int i = tid; i < K3 * CY; i += NT) {
+    const int z = i / CY, yy2 = i - z * CY;
+    spec_st(&col[(size_t)z * K2 + y0 + yy2], buf[z * PZ + yy2]);
+  }
+  ev_row(a, acc, blockIdx.x * (NT / 64));
+  TRACE(4, 15);
 }
 
 // Sum of the energy/virial partial rows in a fixed order by the first
@@ -1050,7 +1205,7 @@ hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
   static const BatchArgs kNoBatch{};
   const BatchArgs& b = bt != nullptr ? *bt : kNoBatch;
   if (bt != nullptr) grid.y = bt->n;
-  if (t.start != nullptr)
+  if (t.start != nullptr || t.stop != nullptr)
     hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t.start, t.stop, 0u, a, b);
   else
     kernel<<<grid, block, lds, s>>>(a, b);
@@ -1109,17 +1264,31 @@ bool grid_supported(int K1, int K2, int K3) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Wavefronts per convolution workgroup (one energy/virial row each).
-static int conv_waves(int K1, int K2, int K3, int precision) {
+// Energy/virial rows per x' column: one per wavefront of the workgroups
+// that convolve it.
+static int conv_rows(int K1, int K2, int K3, int precision) {
   int w = 0;
   (void)with_prec(precision, [&](auto pt) {
     using P = decltype(pt);
     return with_grid(K1, K2, K3, [&](auto gc) {
-      w = conv_threads<P, decltype(gc)>() / 64;
+      using G = decltype(gc);
+      if constexpr (conv_split<G>())
+        w = (G::K2 / pass_cy<G>()) * (kPassThreads / 64);
+      else
+        w = conv_threads<P, G>() / 64;
       return hipSuccess;
     });
   });
   return w;
+}
+
+static bool conv_is_split(int K1, int K2, int K3) {
+  bool sp = false;
+  (void)with_grid(K1, K2, K3, [&](auto gc) {
+    sp = conv_split<decltype(gc)>();
+    return hipSuccess;
+  });
+  return sp;
 }
 
 bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision, Layout* lay) {
@@ -1149,9 +1318,13 @@ bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision,
   L.orec = o;      o = align256(o + (size_t)max_atoms * rsz);
   L.orec_max = max_atoms;
   L.spec = o;      o = align256(o + plane * kh * spec_cpx);
+  L.mid = L.spec;
+  if (precision == PME_FP32_FIXED_HALF && conv_is_split(K1, K2, K3)) {
+    L.mid = o;     o = align256(o + plane * kh * cpx);
+  }
   L.phi_pitch = phi_pitch_of(K1, order);
   L.phi = o;       o = align256(o + plane * L.phi_pitch * real);
-  L.partial_rows = (int)kh * conv_waves(K1, K2, K3, precision);
+  L.partial_rows = (int)kh * conv_rows(K1, K2, K3, precision);
   L.partial = o;   o = align256(o + (size_t)L.partial_rows * 8 * sizeof(double));
   L.dbg = o;       o = align256(o + plane * K1 * 8);
   L.args = o;      o = align256(o + sizeof(Args));
@@ -1166,8 +1339,19 @@ hipError_t raise_lds_limits() {
   const hipFuncAttribute attr = hipFuncAttributeMaxDynamicSharedMemorySize;
   hipError_t e = hipFuncSetAttribute((const void*)k_spread_x<P, G, O, B>, attr,
                                      (int)spread_lds_bytes<P, G>());
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_conv<P, G, B>, attr, (int)conv_lds_bytes<P, G>());
+  if constexpr (conv_split<G>()) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_conv_y<P, G, -1, B>, attr,
+                              (int)conv_y_lds_bytes<P, G>());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_conv_y<P, G, 1, B>, attr,
+                              (int)conv_y_lds_bytes<P, G>());
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_conv_z<P, G, B>, attr, (int)conv_z_lds_bytes<P, G>());
+  } else {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_conv<P, G, B>, attr, (int)conv_lds_bytes<P, G>());
+  }
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_inv_x<P, G, O, B>, attr, (int)inv_x_lds_bytes<P, G>());
   if (e == hipSuccess)
@@ -1231,9 +1415,25 @@ hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t, const Batc
       using G = decltype(gc);
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
-        const int blocks = G::K1 / 2 + 2;  // columns and the counts/headroom workgroup
-        return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_threads<P, G>()),
-                      conv_lds_bytes<P, G>(), s, t, a, bt);
+        constexpr int KH = G::K1 / 2 + 1;
+        if constexpr (conv_split<G>()) {
+          // three launches; the timing window spans all of them
+          const Timing first{t.start, nullptr}, last{nullptr, t.stop};
+          const dim3 ygrid(KH * (G::K3 / pass_cz<G>()));
+          hipError_t e = launch(k_conv_y<P, G, -1, B>, ygrid, dim3(kPassThreads),
+                                conv_y_lds_bytes<P, G>(), s, first, a, bt);
+          if (e == hipSuccess)  // column chunks and the counts/headroom workgroup
+            e = launch(k_conv_z<P, G, B>, dim3(KH * (G::K2 / pass_cy<G>()) + 1),
+                       dim3(kPassThreads), conv_z_lds_bytes<P, G>(), s, Timing(), a, bt);
+          if (e == hipSuccess)
+            e = launch(k_conv_y<P, G, 1, B>, ygrid, dim3(kPassThreads), conv_y_lds_bytes<P, G>(),
+                       s, last, a, bt);
+          return e;
+        } else {
+          const int blocks = KH + 1;  // columns and the counts/headroom workgroup
+          return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_threads<P, G>()),
+                        conv_lds_bytes<P, G>(), s, t, a, bt);
+        }
       });
     });
   });

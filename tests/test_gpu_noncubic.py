@@ -138,7 +138,9 @@ def test_sheared_cell_non_cubic_grid(P, precision):
 def test_batch_mixes_grid_shapes(P):
     # one batch with cubic and non-cubic plans: grouped by shape, each
     # system's result equals its own single-plan step
-    shapes = [(CASES[0], 32), (CASES[2], None), (CASES[0], None), (CASES[2], 48)]
+    # (64 x 64 x 128 takes the three-launch convolution)
+    shapes = [(CASES[0], 32), (CASES[2], None), (CASES[4], None), (CASES[0], None),
+              (CASES[2], 48), (CASES[4], None)]
     plans, inputs_, outs = [], [], []
     for i, (case, cubic) in enumerate(shapes):
         name, K, p, edges, nw, beta = case
