@@ -202,7 +202,9 @@ int pme_check(pme_plan *plan, unsigned *flags);
  * synchronises, adds the elapsed times of all completed launches into
  * ms[0..n-1] (kernel order: 0 bin, 1 spread + x FFT, 2 y/z FFTs with the
  * influence function and the inverse z/y FFTs, 3 inverse x FFT + force
- * interpolation) and returns the number of steps accumulated in *steps. */
+ * interpolation) and returns the number of steps accumulated in *steps.
+ * Where the y/z work takes three launches (K2 K3 >= 8192), slot 2 runs from
+ * the start of the first to the end of the last, gaps included. */
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
 
