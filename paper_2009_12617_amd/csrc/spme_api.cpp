@@ -460,6 +460,23 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     }
     reps[g] = rep;
   }
+  // binning does not depend on the grid: one launch per precision (the
+  // order above is sorted by precision first)
+  std::vector<spme::BatchArgs> bin_bts;
+  std::vector<Args> bin_reps;
+  for (int i : order) {
+    const Args& a = plans[i]->bound;
+    if (bin_bts.empty() || bin_reps.back().precision != a.precision ||
+        bin_bts.back().n == spme::kMaxBatch) {
+      bin_bts.push_back(spme::BatchArgs{});
+      bin_bts.back().n = 0;
+      bin_reps.push_back(a);
+    }
+    spme::BatchArgs& bt = bin_bts.back();
+    bt.sys[bt.n++] = reinterpret_cast<const Args*>(plans[i]->ws + plans[i]->lay.args);
+    bin_reps.back().N = std::max(bin_reps.back().N, a.N);
+    bin_reps.back().n_chunks = std::max(bin_reps.back().n_chunks, a.n_chunks);
+  }
   const spme::Timing none;
   // plans whose last binning was not followed by a convolution
   for (int i = 0; i < n; ++i) {
@@ -470,13 +487,14 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     p->state = kDirty;
   }
   // stage by stage over the groups, all on one stream
-  for (int stage = 0; stage < spme::kNumKernels; ++stage) {
+  for (size_t g = 0; g < bin_bts.size(); ++g)
+    if (spme::launch_bin(bin_reps[g], s, none, &bin_bts[g]) != hipSuccess) return PME_EDEVICE;
+  for (int stage = 1; stage < spme::kNumKernels; ++stage) {
     for (size_t g = 0; g < groups.size(); ++g) {
       const Args& a = reps[g];
       const spme::BatchArgs* bt = &bts[g];
       hipError_t e = hipSuccess;
       switch (stage) {
-        case 0: e = spme::launch_bin(a, s, none, bt); break;
         case 1: e = spme::launch_spread_x(a, s, none, bt); break;
         case 2: e = spme::launch_conv(a, s, none, bt); break;
         default: e = spme::launch_interp(a, s, none, bt); break;

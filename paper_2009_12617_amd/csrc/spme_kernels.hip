@@ -457,6 +457,16 @@ template <class P, class G>
 __host__ __device__ constexpr int conv_threads() {
   return (sizeof(typename P::real) == 8 && (G::K2 >= 72 || G::K3 >= 72)) ? 512 : 1024;
 }
+// Batched columns (FP32 precisions): 512 threads where that still covers
+// every FFT task of a pass (64-point pencils and shorter), so that two
+// columns share a CU.
+template <class P, class G, bool BATCH>
+__host__ __device__ constexpr int conv_block() {
+  return (BATCH && P::fixed && conv_threads<P, G>() == 1024 && fft_lanes(G::K2) * G::K3 <= 512 &&
+          fft_lanes(G::K3) * G::K2 <= 512)
+             ? 512
+             : conv_threads<P, G>();
+}
 template <class P, class G>
 __host__ __device__ constexpr size_t conv_tables_bytes() {
   // y and z twiddles, per-axis factors, one energy/virial row per wavefront
@@ -552,8 +562,10 @@ __device__ __forceinline__ void keep_counts(const Args& a, double* wred) {
 }
 
 // Influence function on z-transformed modes of column x' = xp held in LDS as
-// buf[z * PZ + yy] (z < K3, y = y0 + yy, yy < CY): each mode is multiplied
-// by G(m) and its energy/virial terms are added to acc.
+// buf[z * PZ + yy] (z < K3, y = y0 + yy, yy < CY): the modes of virtual
+// thread vt of VT (mode i = vt + k VT) are multiplied by G(m) and their
+// energy/virial terms are added to acc.  The partition over virtual threads,
+// not the launch's thread count, fixes the order of every sum.
 // G(m) = c B(m) exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) with
 // B exp(-pi^2|m|^2/beta^2) = T_x(m1) T_y(m2) T_z(m3) in an orthorhombic
 // cell.  The half spectrum counts every m1 = 1 .. K1/2-1 twice (its
@@ -564,13 +576,12 @@ __device__ __forceinline__ void keep_counts(const Args& a, double* wred) {
 // Szz, Sxy, Sxz, Syz), so that P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A
 // Nyquist index aliases +K_a/2 and -K_a/2 equally, so its sign-odd
 // (off-diagonal) products vanish.
-template <class P, class G, int CY, int PZ, int NT>
+template <class P, class G, int CY, int PZ, int VT>
 __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>* buf, int xp,
-                                          int y0, const double* bs, double* acc) {
+                                          int y0, const double* bs, double* acc, int vt) {
   using T = typename P::real;
   constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
   constexpr double PI = 3.14159265358979323846;
-  const int tid = threadIdx.x;
   const double pref = a.coulomb / (PI * a.volume);
   const double fac = PI * PI / (a.beta * a.beta);
   const double mvx = xp * a.invL[0];
@@ -581,7 +592,7 @@ __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>*
   if (a.triclinic) {
     // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
     // each Nyquist index is averaged over its two signs explicitly
-    for (int i = tid; i < K3 * CY; i += NT) {
+    for (int i = vt; i < K3 * CY; i += VT) {
       const int z = i / CY, yy = i - z * CY, y = y0 + yy;
       const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
       const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
@@ -627,12 +638,12 @@ __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>*
       buf[z * PZ + yy] = {f.x * g, f.y * g};
     }
   } else {
-    constexpr int NIT = (K3 * CY + NT - 1) / NT;
+    constexpr int NIT = (K3 * CY + VT - 1) / VT;
     constexpr int UNR = NIT <= 4 ? NIT : 2;
 #pragma unroll UNR
     for (int it = 0; it < NIT; ++it) {
-      const int i = tid + it * NT;
-      if ((K3 * CY) % NT != 0 && i >= K3 * CY) break;
+      const int i = vt + it * VT;
+      if ((K3 * CY) % VT != 0 && i >= K3 * CY) break;
       const int z = i / CY, yy = i - z * CY, y = y0 + yy;
       const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
       const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
@@ -664,13 +675,13 @@ __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>*
   }
 }
 
-// Energy/virial: a fixed-order DPP sum over each wavefront, one partial row
-// (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz) per wavefront at row `first + wave`,
-// added in row order later.
-__device__ __forceinline__ void ev_row(const Args& a, double* acc, int first) {
+// Energy/virial: a fixed-order DPP sum over the wavefront, one partial row
+// (E, Pxx, Pyy, Pzz, Pxy, Pxz, Pyz) written at row `r`, the rows added in
+// row order later.
+__device__ __forceinline__ void ev_row(const Args& a, double* acc, int r) {
   wave_sums<7>(acc);
   if ((threadIdx.x & 63) == 63) {
-    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + (first + (threadIdx.x >> 6)) * 8;
+    double* row = reinterpret_cast<double*>(a.ws + a.lay.partial) + r * 8;
     row[0] = acc[0];
 #pragma unroll
     for (int c = 1; c < 4; ++c) row[c] = acc[0] - 2.0 * acc[c];
@@ -680,7 +691,9 @@ __device__ __forceinline__ void ev_row(const Args& a, double* acc, int first) {
 }
 
 template <class P, class G, bool BATCH>
-__global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, BatchArgs bt) {
+__global__ __launch_bounds__((conv_block<P, G, BATCH>()),
+                             (conv_block<P, G, BATCH>() == 512 ? 4 : 1)) void k_conv(Args a_in,
+                                                                                      BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
@@ -691,7 +704,11 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   constexpr int PY = conv_pitch<P>(K2);        // y pass: one row of pitch PY per z
   constexpr int PZ = conv_zpitch<P, G>();      // z pass: one row of pitch PZ per z
   constexpr int TY = fft_lanes(K2), TZ = fft_lanes(K3);
-  constexpr int NT = conv_threads<P, G>();
+  constexpr int NT = conv_block<P, G, BATCH>();
+  // the modes are dealt to VT virtual threads, NV per thread, as a VT-thread
+  // launch deals them, so that batched and single steps add alike
+  constexpr int VT = conv_threads<P, G>(), NV = VT / NT;
+  constexpr bool EARLY_EV = NV > 1 && NC == 1;
   static_assert(conv_lds_bytes<P, G>() <= kMaxLds, "convolution column does not fit in LDS");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
@@ -712,7 +729,7 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   // the first chunk's loads are issued before the tables are computed
   // (when they fit in a few registers)
   constexpr int EPT = (CZ * K2 + NT - 1) / NT;
-  constexpr bool PREFETCH = P::fixed && EPT * sizeof(cplx<T>) <= 64;
+  constexpr bool PREFETCH = P::fixed && EPT * sizeof(cplx<T>) <= 32;
   cplx<T> first[PREFETCH ? EPT : 1];
   if constexpr (PREFETCH) {
 #pragma unroll
@@ -757,7 +774,11 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
   TRACE(2, 1);
 
   // --- z: forward transform, influence function, inverse transform
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  double acc[NV][7];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[v][c] = 0.0;
   for (int c = 0; c < NC; ++c) {
     const int y0 = c * CY;
     if constexpr (NC > 1) {
@@ -773,7 +794,12 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
     }
     __syncthreads();
     TRACE(2, 2);
-    influence<P, G, CY, PZ, NT>(a, buf, xp, y0, bs, acc);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) influence<P, G, CY, PZ, VT>(a, buf, xp, y0, bs, acc[v], tid + v * NT);
+    if constexpr (EARLY_EV) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) ev_row(a, acc[v], xp * (VT / 64) + ((tid + v * NT) >> 6));
+    }
     __syncthreads();
     TRACE(2, 3);
     for (int task = tid; task < CY * TZ; task += NT) {
@@ -813,7 +839,11 @@ __global__ __launch_bounds__((conv_threads<P, G>())) void k_conv(Args a_in, Batc
     if constexpr (NC > 1) __syncthreads();
   }
   // placed after the last stores so that it overlaps their completion
-  ev_row(a, acc, xp * (NT / 64));
+  // (unless the registers it holds are needed for occupancy)
+  if constexpr (!EARLY_EV) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ev_row(a, acc[v], xp * (VT / 64) + ((tid + v * NT) >> 6));
+  }
   TRACE(2, 15);
 }
 
@@ -927,7 +957,7 @@ __global__ __launch_bounds__(kPassThreads) void k_conv_z(Args a_in, BatchArgs bt
   __syncthreads();
   TRACE(4, 2);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  influence<P, G, CY, PZ, NT>(a, buf, xp, y0, bs, acc);
+  influence<P, G, CY, PZ, NT>(a, buf, xp, y0, bs, acc, tid);
   __syncthreads();
   TRACE(4, 3);
   fft_pencil<T, K3, 1>(buf + yy, PZ, l, tw, 1);
@@ -937,7 +967,7 @@ __global__ __launch_bounds__(kPassThreads) void k_conv_z(Args a_in, BatchArgs bt
     const int z = i / CY, yy2 = i - z * CY;
     spec_st(&col[(size_t)z * K2 + y0 + yy2], buf[z * PZ + yy2]);
   }
-  ev_row(a, acc, blockIdx.x * (NT / 64));
+  ev_row(a, acc, blockIdx.x * (NT / 64) + (tid >> 6));
   TRACE(4, 15);
 }
 
@@ -1431,7 +1461,7 @@ hipError_t launch_conv(const Args& a, hipStream_t s, const Timing& t, const Batc
           return e;
         } else {
           const int blocks = KH + 1;  // columns and the counts/headroom workgroup
-          return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_threads<P, G>()),
+          return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_block<P, G, B>()),
                         conv_lds_bytes<P, G>(), s, t, a, bt);
         }
       });
