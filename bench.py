@@ -219,6 +219,44 @@ def stacked_water(I):
     return pos, q, np.diag([L, L, 2 * L])
 
 
+def profile_leg(torch, dev, Plan, I, leg, steps):
+    """Host-launched evaluations of one leg and nothing else, so that a
+    profiler's statistics cover that leg only."""
+    if leg == "real":
+        from paper_2009_12617_amd import RealSpace
+        w = I.HEADLINE_64
+        pos, q, box = w.make()
+        rs = RealSpace(len(q), device=dev)
+        off, idx = I.water_exclusions(len(q))
+        excl = (torch.from_numpy(off).to(dev), torch.from_numpy(idx).to(dev))
+        dp, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+        fr = torch.empty((len(q), 3), dtype=torch.float64, device=dev)
+        run = lambda: rs(dp, dq, box, w.beta, 9.0, exclusions=excl, forces=fr)  # noqa: E731
+    else:
+        named = {wl.name: wl for wl in (I.SMALL_32, I.HEADLINE_64, I.LARGE_128_P4, I.LARGE_128_P6)}
+        if leg == "water_131070_k64x64x128":
+            pos, q, box = stacked_water(I)
+            K, order, beta = (64, 64, 128), 4, 0.34
+        elif leg in named:
+            wl = named[leg]
+            pos, q, box = wl.make()
+            K, order, beta = wl.K, wl.order, wl.beta
+        else:
+            raise SystemExit(f"bench.py: unknown leg {leg!r}")
+        plan = Plan(K, order, beta, max_atoms=len(q), device=dev)
+        dp, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+        run = lambda: plan.step(dp, dq, box)  # noqa: E731
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    print(json.dumps({"leg": leg, "evaluations": steps,
+                      "us_per_evaluation": (time.perf_counter() - t0) / steps * 1e6, "mode": "profile"}))
+
+
 def bench_serving(torch, dev, I, n_requests, rate, budget_gib):
     """Open-loop Poisson arrivals over the batch mix plus four 128^3 boxes."""
     from paper_2009_12617_amd.serve import PoolSystem, Server
@@ -271,6 +309,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
     ap.add_argument("--no-noncubic", action="store_true", help="skip the 64 x 64 x 128 grid run")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 (209,715-atom) runs")
+    ap.add_argument("--profile-leg", default="",
+                    help="for profilers: only `steps` host-launched evaluations of one leg "
+                         "(real, or a workload name such as water_209715_k128_p4)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -293,6 +334,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.profile_leg:
+        profile_leg(torch, dev, Plan, I, args.profile_leg, args.steps)
+        return
     w = I.HEADLINE_64
     pos0, q, box = w.make()
     N, K = len(q), w.K
