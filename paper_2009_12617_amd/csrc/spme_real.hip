@@ -89,17 +89,45 @@ __global__ __launch_bounds__(256) void k_rs_zero(RsArgs a) {
     a.count[c] = 0u;
 }
 
+// Adds n to counter[c] once per distinct c among the lanes of the
+// wavefront (lanes with c < 0 take no part) and returns each lane's slot:
+// the counter's old value plus the number of lanes of the same c below it.
+// Neighbouring atoms (the atoms of a molecule) usually share a cell, so this
+// issues a fraction of the per-atom atomics on the contended counters.
+__device__ __forceinline__ unsigned wave_add(unsigned* counter, int c) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(c >= 0);
+  unsigned slot = 0u;
+  while (todo != 0ull) {  // uniform over the wavefront
+    const int leader = __ffsll((long long)todo) - 1;
+    const int cl = __shfl(c, leader, 64);
+    const unsigned long long same = __ballot(c == cl) & todo;
+    unsigned base = 0u;
+    if (lane == leader) base = atomicAdd(&counter[cl], (unsigned)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (c == cl) {
+      const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+      slot = base + (unsigned)below;
+    }
+    todo &= ~same;
+  }
+  return slot;
+}
+
 __global__ __launch_bounds__(kRsCountThreads) void k_rs_count(RsArgs a) {
   __shared__ double wred[16 * 8];
   const int i = blockIdx.x * kRsCountThreads + threadIdx.x;
   double v[1] = {0.0};
+  int c = -1;
   if (i < a.N) {
     const double x = wrap(a.pos[3 * (size_t)i], a.L[0], a.invL[0]);
     const double y = wrap(a.pos[3 * (size_t)i + 1], a.L[1], a.invL[1]);
     const double z = wrap(a.pos[3 * (size_t)i + 2], a.L[2], a.invL[2]);
-    atomicAdd(&a.count[cell_of(a, x, y, z)], 1u);
+    c = cell_of(a, x, y, z);
     v[0] = a.q[i] * a.q[i];
   }
+  (void)wave_add(a.count, c);
   block_sums<1>(v, wred);
   if (threadIdx.x == 15) a.rows[2 * (size_t)a.nrow + blockIdx.x] = v[0];
 }
@@ -137,11 +165,16 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(RsArgs a) {
 
 __global__ __launch_bounds__(256) void k_rs_fill(RsArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
-  const double x = wrap(a.pos[3 * (size_t)i], a.L[0], a.invL[0]);
-  const double y = wrap(a.pos[3 * (size_t)i + 1], a.L[1], a.invL[1]);
-  const double z = wrap(a.pos[3 * (size_t)i + 2], a.L[2], a.invL[2]);
-  const unsigned slot = atomicAdd(&a.cursor[cell_of(a, x, y, z)], 1u);
+  double x = 0.0, y = 0.0, z = 0.0;
+  int c = -1;
+  if (i < a.N) {
+    x = wrap(a.pos[3 * (size_t)i], a.L[0], a.invL[0]);
+    y = wrap(a.pos[3 * (size_t)i + 1], a.L[1], a.invL[1]);
+    z = wrap(a.pos[3 * (size_t)i + 2], a.L[2], a.invL[2]);
+    c = cell_of(a, x, y, z);
+  }
+  const unsigned slot = wave_add(a.cursor, c);
+  if (c < 0) return;
   a.rec[slot] = make_double4(x, y, z, a.q[i]);
   a.ridx[slot] = i;
 }
@@ -331,11 +364,15 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
 
 // Energies in a fixed order by one wavefront: E_real, E_self, E_excl.
 __global__ __launch_bounds__(64) void k_rs_reduce(RsArgs a) {
+  // (unrolled so that the loads of several rows are in flight together;
+  // the additions keep their row order)
   double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int r = threadIdx.x; r < a.nrow; r += 64) {
     v[0] += a.rows[2 * (size_t)r];
     v[2] += a.rows[2 * (size_t)r + 1];
   }
+#pragma unroll 8
   for (int r = threadIdx.x; r < a.n_count_blocks; r += 64) v[1] += a.rows[2 * (size_t)a.nrow + r];
   wave_sums<3>(v);
   if (threadIdx.x == 63) {
