@@ -1,6 +1,6 @@
 // HIP kernels of the SPME reciprocal-space step for gfx950 (CDNA4).
 //
-// One step is four launches on one stream:
+// One step is four launches on one stream (more on large grids, below):
 //   k_bin       fractional coordinates, base grid index and offsets of each
 //               atom; the atoms are put into buckets by (base z, y slice,
 //               head/body) -- the GPU counterpart of the paper's atom
@@ -22,8 +22,11 @@
 //               extra workgroup adds the energy/virial partial rows
 // The paper's two all-to-all corner turns (§III.A.2, §IV.C) become the
 // column layout of the half spectrum: each column holds every y and z of one
-// x', so both turns happen inside k_conv.  k_inv_x (debug copies only)
-// writes the potential rows to the workspace.
+// x', so both turns happen inside k_conv.  Large grids (K2 K3 >= 8192) split
+// the column work over three launches (k_conv_y, k_conv_z, k_conv_y), and at
+// p >= 6 on K2 K3 >= 16384 the inverse x transform runs once per plane
+// (k_inv_x, which also serves the debug copy of the potential) before a
+// gather kernel (k_interp_phi).
 #include <hip/hip_ext.h>
 
 #include <type_traits>

@@ -155,3 +155,34 @@ def test_batch_with_general_cells(P):
         fr = np.linalg.norm(fb.cpu().numpy() - ref["forces"]) / np.linalg.norm(ref["forces"])
         er = abs(eb[0].item() - ref["E"]) / abs(ref["E"])
         assert fr <= 1e-5 and er <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp32_fixed", "fp64"])
+def test_batch_large_grids_p6(P, precision):
+    # 128^3 at p = 6 takes the split convolution and the once-per-plane
+    # inverse x transform with the gather kernel; batched with a 64^3 plan,
+    # each result equals its own single step
+    specs = [(128, 900, 60.0, 51), (64, 700, 40.0, 52), (128, 600, 50.0, 53)]
+    sys = []
+    for K, nw, L, seed in specs:
+        pos, q, box = I.water_box(nw, L, seed)
+        plan = P.Plan(K, 6, 0.34, max_atoms=len(q), precision=precision)
+        dp, dq = dev(pos), dev(q)
+        f, e = plan.bind(dp, dq, box)
+        sys.append(dict(plan=plan, dp=dp, dq=dq, pos=pos, q=q, box=box, K=K, f=f, e=e))
+    P.Batch([s["plan"] for s in sys]).run()
+    torch.cuda.synchronize()
+    got = [(s["f"].clone(), s["e"].clone()) for s in sys]
+    for s, (fb, eb) in zip(sys, got):
+        fa, ea = s["plan"].step(s["dp"], s["dq"], s["box"])
+        if precision == "fp32_fixed":
+            assert torch.equal(fa, fb) and torch.equal(ea, eb)
+        else:
+            assert torch.allclose(fa, fb, rtol=1e-11, atol=1e-15)
+            assert torch.allclose(ea, eb, rtol=1e-11, atol=1e-15)
+    s = sys[0]
+    ref = oracle.spme(s["pos"], s["q"], s["box"], s["K"], 6, 0.34)
+    fr = np.linalg.norm(got[0][0].cpu().numpy() - ref["forces"]) / np.linalg.norm(ref["forces"])
+    er = abs(got[0][1][0].item() - ref["E"]) / abs(ref["E"])
+    assert fr <= (1e-5 if precision == "fp32_fixed" else 1e-10)
+    assert er <= (1e-6 if precision == "fp32_fixed" else 1e-11)
