@@ -798,10 +798,10 @@ __global__ __launch_bounds__((conv_block<P, G, BATCH>()),
     __syncthreads();
     TRACE(2, 2);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) influence<P, G, CY, PZ, VT>(a, buf, xp, y0, bs, acc[v], tid + v * NT);
-    if constexpr (EARLY_EV) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) ev_row(a, acc[v], xp * (VT / 64) + ((tid + v * NT) >> 6));
+    for (int v = 0; v < NV; ++v) {
+      influence<P, G, CY, PZ, VT>(a, buf, xp, y0, bs, acc[v], tid + v * NT);
+      // (one virtual thread's sums written before the next one's start)
+      if constexpr (EARLY_EV) ev_row(a, acc[v], xp * (VT / 64) + ((tid + v * NT) >> 6));
     }
     __syncthreads();
     TRACE(2, 3);
