@@ -65,7 +65,7 @@ def cpu_model():
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("spme_kernels.hip", "spme_device.h"):
+    for f in ("spme_kernels.hip", "spme_device.h", "spme_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2009_12617_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
