@@ -219,9 +219,12 @@ int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
  *            + (r <= rcut ? erfc(beta r)/r : 0)]   (removes excluded pairs
  *            from both the pair sum and the reciprocal sum)
  * Forces are -grad of E_real + E_excl.  FP64 throughout; diagonal boxes
- * only (PME_EUNSUPPORTED otherwise, or when rcut > L/3 on some axis).  Two
- * distinct atoms at exactly the same position are not paired (their pair
- * term is infinite).
+ * only (PME_EUNSUPPORTED otherwise, when rcut > L/3 on some axis, or when
+ * beta rcut > 6, where erfc(beta rcut) < 3e-17 and a shorter cutoff gives the
+ * same sums).  erfc of a pair inside the cutoff comes from a 32-term
+ * Chebyshev series of exp(x^2) erfc(x) on [0, beta rcut], relative error
+ * <= 2e-14.  Two distinct atoms at exactly the same position are not paired
+ * (their pair term is infinite).
  * ------------------------------------------------------------------------ */
 
 /* Bytes of device workspace for pme_real with at most max_atoms atoms and

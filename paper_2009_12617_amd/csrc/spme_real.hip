@@ -42,6 +42,8 @@ static_assert(kRsStage % (2 * kRsUnroll) == 0, "the padded stage must fit");
 constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
                                     // followed by one discard slot per lane
 constexpr int kRsCountThreads = 256;
+constexpr int kRsCheb = 32;         // Chebyshev terms of exp(x^2) erfc(x)
+constexpr double kRsMaxBetaRcut = 6.0;  // series error <= 2e-14 relative up to here
 constexpr int kRsScanThreads = 1024;
 
 struct RsArgs {
@@ -49,6 +51,8 @@ struct RsArgs {
   int nrow;             // pair workgroups: ncell * kRsBlocks
   double L[3], invL[3], cell_inv[3];
   double beta, rc2, rcut, coulomb;
+  double cheb[kRsCheb];  // exp(x^2) erfc(x) on [0, beta rcut] as a Chebyshev series
+  double cheb_scale;     // 2 / (beta rcut)
   const double* pos;
   const double* q;
   const int* excl_off;  // may be null
@@ -182,7 +186,11 @@ __global__ __launch_bounds__(256) void k_rs_fill(RsArgs a) {
 // One candidate pair taken from a wavefront's queue: entry = (staged index
 // << 7) | home slot.  Adds the pair's energy to e and its force on the home
 // atom to hf (LDS atomics: a home atom's pairs are spread over lanes and
-// wavefronts).
+// wavefronts).  erfc(x) = exp(-x^2) erfcx(x), with erfcx = exp(x^2) erfc(x)
+// from its Chebyshev series on [0, beta rcut] (Clenshaw's recurrence, the
+// coefficients uniform over the launch), so the exp the force needs is the
+// only transcendental besides 1/r (hardware reciprocal square root and two
+// Newton steps).
 __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, const double4* home,
                                         double (*hf)[3], int entry, double& e) {
   const double two_over_sqrtpi = 1.12837916709551257390;
@@ -190,11 +198,23 @@ __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, c
   const double4 rj = stage[t], ri = home[s];
   const double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
   const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  const double r = sqrt(r2), br = a.beta * r;
-  const double ec = erfc(br) / r;
+  double rinv = __builtin_amdgcn_rsq(r2);
+  rinv = rinv * fma(-0.5 * r2 * rinv, rinv, 1.5);
+  rinv = rinv * fma(-0.5 * r2 * rinv, rinv, 1.5);
+  const double br = a.beta * (r2 * rinv);
+  const double ex = exp(-br * br);
+  const double tc = fma(br, a.cheb_scale, -1.0), t2 = tc + tc;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kRsCheb - 1; k >= 1; --k) {
+    const double b0 = fma(t2, b1, a.cheb[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  const double ec = ex * fma(tc, b1, a.cheb[0] - b2) * rinv;  // erfc(beta r) / r
   const double qq = a.coulomb * ri.w * rj.w;
   e += 0.5 * qq * ec;
-  const double g = qq * (ec + two_over_sqrtpi * a.beta * exp(-br * br)) / r2;
+  const double g = qq * (ec + two_over_sqrtpi * a.beta * ex) * (rinv * rinv);
 #pragma unroll
   for (int c = 0; c < 3; ++c) atomicAdd(&hf[s][c], g * d[c]);
 }
@@ -428,6 +448,7 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
   if ((excl_off == nullptr) != (excl_idx == nullptr)) return PME_EINVAL;
   if (!(beta > 0.0) || !(rcut > 0.0) || !std::isfinite(beta) || !std::isfinite(rcut))
     return PME_EINVAL;
+  if (beta * rcut > kRsMaxBetaRcut) return PME_EUNSUPPORTED;  // erfc(6) < 3e-17
   if (coulomb == 0.0) coulomb = 1.0;
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(box[i])) return PME_EINVAL;
@@ -467,6 +488,25 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
   a.beta = beta;
   a.rcut = rcut;
   a.rc2 = rcut * rcut;
+  // exp(x^2) erfc(x) on [0, X], X = beta rcut: Chebyshev coefficients from
+  // its values at 64 Chebyshev nodes (a discrete cosine transform), the
+  // first kRsCheb kept
+  {
+    const double X = beta * rcut;
+    const double pi = 3.14159265358979323846;
+    constexpr int kNodes = 64;
+    double f[kNodes];
+    for (int j = 0; j < kNodes; ++j) {
+      const double x = 0.5 * X * (std::cos(pi * (j + 0.5) / kNodes) + 1.0);
+      f[j] = std::erfc(x) * std::exp(x * x);
+    }
+    for (int k = 0; k < kRsCheb; ++k) {
+      double c = 0.0;
+      for (int j = 0; j < kNodes; ++j) c += f[j] * std::cos(pi * k * (j + 0.5) / kNodes);
+      a.cheb[k] = (k == 0 ? 1.0 : 2.0) * c / kNodes;
+    }
+    a.cheb_scale = 2.0 / X;
+  }
   a.coulomb = coulomb;
   a.pos = pos;
   a.q = q;

@@ -65,6 +65,28 @@ def test_real_space_matches_brute_force(P, with_excl, max_cells):
     assert e[2] == pytest.approx(want_excl, rel=1e-12, abs=1e-12)
 
 
+@pytest.mark.parametrize("beta", [0.05, 0.755])
+def test_real_space_screening_range(P, beta):
+    # the erfc inside the cutoff comes from a Chebyshev series on
+    # [0, beta rcut]: the two ends of the supported range of beta rcut
+    # (0.4 and 5.96) against the oracle's brute-force sum; just past the
+    # range (6.04) the call is refused
+    from paper_2009_12617_amd._lib import SpmeError
+    pos, q, box = I.water_box(400, 24.0, 34)
+    rcut = 7.9
+    rs = P.RealSpace(len(q))
+    f, e = rs(dev(pos), dev(q), box, beta, rcut)
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    ref = oracle.ewald_real(np.mod(pos, 24.0), q, box, beta, nimg=1, rcut=rcut)
+    print(f"beta*rcut={beta * rcut:.3f} force_rel_rms={rel_rms(f, ref['forces']):.2e} "
+          f"E_real={e[0]:.12e} ref={ref['E_real']:.12e}", flush=True)
+    assert rel_rms(f, ref["forces"]) <= 1e-11
+    assert e[0] == pytest.approx(ref["E_real"], rel=1e-12)
+    with pytest.raises(SpmeError) as ei:
+        rs(dev(pos), dev(q), box, 6.04 / rcut, rcut)
+    assert ei.value.code == 2
+
+
 def test_real_space_accumulates_and_rejects_bad_geometry(P):
     from paper_2009_12617_amd._lib import SpmeError
     pos, q, box = I.water_box(100, 16.0, 32)
