@@ -302,7 +302,7 @@ def main():
                     help="at most this many frames checked against the oracle (0: none)")
     ap.add_argument("--parity-every", type=int, default=10,
                     help="check every n-th frame of the timed run")
-    ap.add_argument("--no-half", action="store_true", help="skip the binary16-spectrum variant")
+    ap.add_argument("--no-half", action="store_true", help="skip the binary16- and bfloat16-spectrum variants")
     ap.add_argument("--no-real", action="store_true", help="skip the real-space term")
     ap.add_argument("--profile", action="store_true",
                     help="short run for a profiler: fixed steps, no oracle legs")
@@ -493,20 +493,21 @@ def main():
                 "step_roofline_frac": step_bytes(N, K, True) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
         print(f"# fp64: {ms64 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
-    half = None
-    plan16 = None
+    reduced = {}  # precision -> (plan, result dict)
     if not args.no_half:
-        # the reduced-precision variant: the half spectrum in binary16 between
-        # launches (bytes of both corner turns halved); accuracy below
-        plan16 = Plan(K, w.order, w.beta, max_atoms=N, precision="fp32_fixed_half", device=dev)
-        ms16, _, ok16 = run_graph(plan16, args.steps, args.warmup)
-        if not ok16:
-            print("bench.py: half-spectrum graph replay differs from host-launched steps", file=sys.stderr)
-            sys.exit(1)
-        kh = K // 2 + 1
-        half = {"us_per_step": ms16 * 1e3, "speedup_vs_fp32_fixed": ms_step / ms16,
-                "step_algorithmic_bytes": step_bytes(N, K) - 16 * K * K * kh}
-        print(f"# fp32_fixed_half: {ms16 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+        # the reduced-precision variants: the half spectrum in binary16 or
+        # bfloat16 between launches (bytes of both corner turns halved);
+        # accuracy below
+        for prec in ("fp32_fixed_half", "fp32_fixed_bf16"):
+            plan16 = Plan(K, w.order, w.beta, max_atoms=N, precision=prec, device=dev)
+            ms16, _, ok16 = run_graph(plan16, args.steps, args.warmup)
+            if not ok16:
+                print(f"bench.py: {prec} graph replay differs from host-launched steps", file=sys.stderr)
+                sys.exit(1)
+            kh = K // 2 + 1
+            reduced[prec] = (plan16, {"us_per_step": ms16 * 1e3, "speedup_vs_fp32_fixed": ms_step / ms16,
+                                      "step_algorithmic_bytes": step_bytes(N, K) - 16 * K * K * kh})
+            print(f"# {prec}: {ms16 * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
     real = None
     if not args.no_real:
@@ -600,13 +601,14 @@ def main():
                   "reference": "FP64 CPU oracle"}
         print(f"# parity on {len(pick)} frames: force rel RMS max {parity['force_rel_rms_max']:.2e}, "
               f"energy rel max {parity['energy_rel_max']:.2e}", file=sys.stderr, flush=True)
-        if plan16 is not None:
-            f, e = plan16.step(d_frames[pick[0]], d_q, box)
+        if reduced:
             ref = oracle.spme(frames[pick[0]], q, box, K, w.order, w.beta)
-            half["force_rel_rms"] = float(np.linalg.norm(f.cpu().numpy() - ref["forces"]) /
-                                          np.linalg.norm(ref["forces"]))
-            half["energy_rel"] = float(abs(e[0].item() - ref["E"]) / abs(ref["E"]))
-            half["parity_frame"] = pick[0]
+            for plan16, half in reduced.values():
+                f, e = plan16.step(d_frames[pick[0]], d_q, box)
+                half["force_rel_rms"] = float(np.linalg.norm(f.cpu().numpy() - ref["forces"]) /
+                                              np.linalg.norm(ref["forces"]))
+                half["energy_rel"] = float(abs(e[0].item() - ref["E"]) / abs(ref["E"]))
+                half["parity_frame"] = pick[0]
     if not args.no_cpu_baseline:
         n = 0
         t0 = time.perf_counter()
@@ -667,7 +669,8 @@ def main():
         "step_roofline_frac": step_bytes(N, K) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "step_algorithmic_bytes": step_bytes(N, K),
         "fp64_path": fp64,
-        "half_spectrum_path": half,
+        "half_spectrum_path": reduced.get("fp32_fixed_half", (None, None))[1],
+        "bf16_spectrum_path": reduced.get("fp32_fixed_bf16", (None, None))[1],
         "real_space": real,
         "more_workloads": more,
         "batched": batched,

@@ -65,8 +65,17 @@ typedef struct pme_plan pme_plan;
  *   between launches in IEEE binary16 (round to nearest even), halving the
  *   bytes of both corner turns; arithmetic stays FP32/FP64.  Accuracy is
  *   bounded by binary16's 11-bit significand (force errors of order 1e-4
- *   relative) and its range (|values| < 65504). */
-typedef enum { PME_FP64 = 0, PME_FP32_FIXED = 1, PME_FP32_FIXED_HALF = 2 } pme_precision;
+ *   relative) and its range (|values| < 65504).
+ * PME_FP32_FIXED_BF16: as PME_FP32_FIXED_HALF, but in bfloat16 (the upper
+ *   half of an FP32, round to nearest even): FP32's range, an 8-bit
+ *   significand (rounding error <= 2^-8 relative), so force errors about
+ *   eight times those of binary16 (of order 1e-3 relative). */
+typedef enum {
+  PME_FP64 = 0,
+  PME_FP32_FIXED = 1,
+  PME_FP32_FIXED_HALF = 2,
+  PME_FP32_FIXED_BF16 = 3
+} pme_precision;
 
 typedef enum {
   PME_OK = 0,
@@ -179,11 +188,12 @@ int pme_set_debug(pme_plan *plan, int keep_charge_grid);
  *            frac_bits fraction bits) or double (FP64); needs pme_set_debug(1)
  *            before the spread
  *   which 1: the half spectrum, stored as columns [K1/2+1][K3][K2] complex
- *            (float2 / double2 / two binary16 for PME_FP32_FIXED_HALF; index
- *            m1 slowest, y fastest): after
+ *            (float2 / double2 / two binary16 for PME_FP32_FIXED_HALF / two
+ *            bfloat16 for PME_FP32_FIXED_BF16; index m1 slowest, y fastest):
+ *            after
  *            pme_spread the forward transform of the charge grid along x;
  *            after pme_solve G F transformed back along z and y
- *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED, _HALF) or double */
+ *   which 2: the potential phi [K3][K2][K1], float (FP32_FIXED, _HALF, _BF16) or double */
 int pme_debug_grid(pme_plan *plan, int which, void *dst);
 
 /* Size in bytes of pme_debug_grid(which)'s output (0 for a bad which). */

@@ -14,6 +14,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "spme.h")
 PME_FP64 = 0
 PME_FP32_FIXED = 1
 PME_FP32_FIXED_HALF = 2
+PME_FP32_FIXED_BF16 = 3
 PME_FLAG_NONFINITE = 1
 PME_FLAG_OVERFLOW = 2
 PME_FLAG_BUCKETS = 4

@@ -143,7 +143,8 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   *out = nullptr;
   if (K1 < 2 || K2 < 2 || K3 < 2 || order < 3 || !(beta > 0.0) || !is_fin(beta) ||
       max_atoms < 0 ||
-      (precision != PME_FP64 && precision != PME_FP32_FIXED && precision != PME_FP32_FIXED_HALF) ||
+      (precision != PME_FP64 && precision != PME_FP32_FIXED && precision != PME_FP32_FIXED_HALF &&
+       precision != PME_FP32_FIXED_BF16) ||
       !is_fin(coulomb))
     return PME_EINVAL;
   if (frac_bits == 0) frac_bits = 32;
@@ -516,7 +517,8 @@ size_t pme_debug_grid_bytes(pme_plan* p, int which) {
   if (p == nullptr) return 0;
   const size_t n = (size_t)p->K1 * p->K2 * p->K3, kh = (size_t)p->K1 / 2 + 1;
   const size_t real = p->precision != PME_FP64 ? 4 : 8;
-  const size_t spec_cpx = p->precision == PME_FP32_FIXED_HALF ? 4 : 2 * real;
+  const size_t spec_cpx =
+      p->precision == PME_FP32_FIXED_HALF || p->precision == PME_FP32_FIXED_BF16 ? 4 : 2 * real;
   switch (which) {
     case 0: return n * 8;
     case 1: return (size_t)p->K2 * p->K3 * kh * spec_cpx;

@@ -55,11 +55,25 @@ __device__ unsigned long long* g_trace;
 #endif
 
 // Half-spectrum storage between launches: complex float, complex double, or
-// (reduced-precision variant) a pair of IEEE binary16 values rounded to
-// nearest even.
+// (reduced-precision variants) a pair of IEEE binary16 values, or a pair of
+// bfloat16 values (the upper 16 bits of an FP32), rounded to nearest even.
 struct cplx_h {
   _Float16 x, y;
 };
+struct cplx_b {
+  unsigned short x, y;
+};
+// FP32 -> bfloat16, round to nearest, ties to even: add 0x7fff plus the
+// kept part's lowest bit, then truncate.  Finite inputs only (the spectrum
+// of a finite grid); values within half a bfloat16 step of FLT_MAX round to
+// infinity as the rule says.
+__device__ __forceinline__ unsigned short bf16_rne(float v) {
+  const unsigned u = __float_as_uint(v);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_up(unsigned short h) {
+  return __uint_as_float((unsigned)h << 16);
+}
 __device__ __forceinline__ cplx<float> spec_ld(const cplx<float>* p) { return *p; }
 __device__ __forceinline__ cplx<double> spec_ld(const cplx<double>* p) { return *p; }
 __device__ __forceinline__ cplx<float> spec_ld(const cplx_h* p) {
@@ -70,6 +84,13 @@ __device__ __forceinline__ void spec_st(cplx<float>* p, cplx<float> v) { *p = v;
 __device__ __forceinline__ void spec_st(cplx<double>* p, cplx<double> v) { *p = v; }
 __device__ __forceinline__ void spec_st(cplx_h* p, cplx<float> v) {
   *p = cplx_h{(_Float16)v.x, (_Float16)v.y};
+}
+__device__ __forceinline__ cplx<float> spec_ld(const cplx_b* p) {
+  const cplx_b h = *p;
+  return {bf16_up(h.x), bf16_up(h.y)};
+}
+__device__ __forceinline__ void spec_st(cplx_b* p, cplx<float> v) {
+  *p = cplx_b{bf16_rne(v.x), bf16_rne(v.y)};
 }
 
 struct PFixed {
@@ -85,6 +106,14 @@ struct PHalf {
   using acc = unsigned long long;
   using rec = RecF;
   using spec = cplx_h;
+  static constexpr bool fixed = true;
+};
+// FP32/fixed with the half spectrum kept in bfloat16 between launches
+struct PBf16 {
+  using real = float;
+  using acc = unsigned long long;
+  using rec = RecF;
+  using spec = cplx_b;
   static constexpr bool fixed = true;
 };
 struct PDouble {
@@ -1336,6 +1365,7 @@ hipError_t with_prec(int prec, F&& f) {
   if (prec == PME_FP32_FIXED) return f(PFixed{});
   if (prec == PME_FP64) return f(PDouble{});
   if (prec == PME_FP32_FIXED_HALF) return f(PHalf{});
+  if (prec == PME_FP32_FIXED_BF16) return f(PBf16{});
   return hipErrorInvalidValue;
 }
 // Supported grids: cubic K = 16, 24, 32, 36, 48, 64, 72, 96, 128, and the
@@ -1405,11 +1435,13 @@ static bool conv_is_split(int K1, int K2, int K3) {
 
 bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision, Layout* lay) {
   if (!grid_supported(K1, K2, K3) || (order != 4 && order != 6) || max_atoms < 0) return false;
-  if (precision != PME_FP32_FIXED && precision != PME_FP64 && precision != PME_FP32_FIXED_HALF)
+  if (precision != PME_FP32_FIXED && precision != PME_FP64 && precision != PME_FP32_FIXED_HALF &&
+      precision != PME_FP32_FIXED_BF16)
     return false;
   const bool fx = precision != PME_FP64;
+  const bool reduced = precision == PME_FP32_FIXED_HALF || precision == PME_FP32_FIXED_BF16;
   const size_t real = fx ? 4 : 8, cpx = 2 * real;
-  const size_t spec_cpx = precision == PME_FP32_FIXED_HALF ? 4 : cpx;
+  const size_t spec_cpx = reduced ? 4 : cpx;
   const size_t kh = (size_t)K1 / 2 + 1, ksum = (size_t)K1 + K2 + K3;
   const size_t plane = (size_t)K2 * K3;  // (y, z) points
   const int nch = (max_atoms + kChunk - 1) / kChunk;
@@ -1431,7 +1463,7 @@ bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision,
   L.orec_max = max_atoms;
   L.spec = o;      o = align256(o + plane * kh * spec_cpx);
   L.mid = L.spec;
-  if (precision == PME_FP32_FIXED_HALF && conv_is_split(K1, K2, K3)) {
+  if (reduced && conv_is_split(K1, K2, K3)) {
     L.mid = o;     o = align256(o + plane * kh * cpx);
   }
   L.phi_pitch = phi_pitch_of(K1, order);

@@ -10,11 +10,11 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PME_FP32_FIXED, PME_FP32_FIXED_HALF, PME_FP64, check
+from ._lib import PME_FP32_FIXED, PME_FP32_FIXED_BF16, PME_FP32_FIXED_HALF, PME_FP64, check
 
 KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "interpolate")
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64,
-              "fp32_fixed_half": PME_FP32_FIXED_HALF}
+              "fp32_fixed_half": PME_FP32_FIXED_HALF, "fp32_fixed_bf16": PME_FP32_FIXED_BF16}
 
 
 def _box9(box):
@@ -53,7 +53,8 @@ class Plan:
 
     precision: "fp32_fixed" (FP32 splines/FFT/convolution, 64-bit fixed-point
     charge grid, FP64 moduli/energy/virial), "fp32_fixed_half" (the same with
-    the half spectrum stored in binary16 between launches) or "fp64".
+    the half spectrum stored in binary16 between launches), "fp32_fixed_bf16"
+    (the same in bfloat16) or "fp64".
     """
 
     def __init__(self, K, order=4, beta=0.34, max_atoms=0, precision="fp32_fixed",
@@ -176,7 +177,8 @@ class Plan:
 
     def debug_grid(self, which):
         """0: charge grid (int64 fixed point or float64) [z, y, x], 1: half
-        spectrum (complex) as columns [x', z, y] of shape [K1/2+1, K3, K2],
+        spectrum (complex) as columns [x', z, y] of shape [K1/2+1, K3, K2]
+        (bfloat16 plans: real and imaginary parts as a trailing axis of 2),
         2: potential phi [z, y, x]."""
         K1, K2, K3 = self.grid
         kh = K1 // 2 + 1
@@ -185,9 +187,12 @@ class Plan:
             out = torch.empty((K3, K2, K1), dtype=torch.int64 if fx else torch.float64,
                               device=self.device)
         elif which == 1:
-            dt = {"fp32_fixed": torch.complex64, "fp32_fixed_half": torch.complex32,
-                  "fp64": torch.complex128}[self.precision]
-            out = torch.empty((kh, K3, K2), dtype=dt, device=self.device)
+            if self.precision == "fp32_fixed_bf16":  # torch has no bfloat16 complex type
+                out = torch.empty((kh, K3, K2, 2), dtype=torch.bfloat16, device=self.device)
+            else:
+                dt = {"fp32_fixed": torch.complex64, "fp32_fixed_half": torch.complex32,
+                      "fp64": torch.complex128}[self.precision]
+                out = torch.empty((kh, K3, K2), dtype=dt, device=self.device)
         elif which == 2:
             out = torch.empty((K3, K2, K1), dtype=torch.float32 if fx else torch.float64,
                               device=self.device)

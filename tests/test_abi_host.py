@@ -47,6 +47,13 @@ def test_workspace_bytes(lib):
     assert lib.pme_workspace_bytes(64, 64, 64, 5, 100, 1) == 0      # odd order
     assert lib.pme_workspace_bytes(64, 64, 64, 4, -1, 1) == 0
     assert lib.pme_workspace_bytes(64, 64, 64, 4, 100, 7) == 0
+    # the two reduced-precision spectra store 4 bytes per complex value, so
+    # their workspaces agree: on a one-launch convolution (64^3) and on a
+    # split one (64 x 64 x 128, with its full-precision intermediate)
+    for g in ((64, 64, 64), (64, 64, 128)):
+        wh = lib.pme_workspace_bytes(*g, 4, 65535, 2)
+        assert wh > 0 and lib.pme_workspace_bytes(*g, 4, 65535, 3) == wh
+        assert wh < lib.pme_workspace_bytes(*g, 4, 65535, 1) or g[2] == 128
 
 
 def create(lib, K=32, order=4, beta=0.35, max_atoms=100, prec=1, frac=0, coul=0.0,
@@ -64,7 +71,7 @@ def test_create_rejects_bad_arguments_without_a_device(lib):
     assert create(lib, beta=0.0, ws=fake)[0] == 1
     assert create(lib, beta=float("nan"), ws=fake)[0] == 1
     assert create(lib, max_atoms=-5, ws=fake)[0] == 1
-    assert create(lib, prec=3, ws=fake)[0] == 1
+    assert create(lib, prec=4, ws=fake)[0] == 1  # 0..3 are the precisions
     assert create(lib, frac=50, ws=fake)[0] == 1
     assert create(lib, coul=float("inf"), ws=fake)[0] == 1
     assert create(lib, K=50, ws=fake)[0] == 2

@@ -109,12 +109,16 @@ def test_x_pass_spectrum_layout(P):
     assert np.abs(spec - want).max() / np.abs(want).max() < 2e-6
 
 
-def test_half_spectrum(P):
+@pytest.mark.parametrize("precision,bars", [("fp32_fixed_half", (1e-3, 2e-4, 2e-4)),
+                                            ("fp32_fixed_bf16", (8e-3, 4e-3, 4e-3))])
+def test_half_spectrum(P, precision, bars):
+    # 64 x 64 x 128 splits the convolution over three launches (full-precision
+    # intermediate between them); bfloat16 rounds at 2^-8, eight times binary16
     name, K, p, edges, nw, beta = CASES[4]
     pos, q, box = system(name, edges, nw)
-    plan = P.Plan(K, p, beta, max_atoms=len(q), precision="fp32_fixed_half")
+    plan = P.Plan(K, p, beta, max_atoms=len(q), precision=precision)
     res = plan.step(dev(pos), dev(q), box)
-    compare(res, oracle.spme(pos, q, box, K, p, beta), 1e-3, 2e-4, 2e-4)
+    compare(res, oracle.spme(pos, q, box, K, p, beta), *bars)
 
 
 @pytest.mark.parametrize("precision", ["fp32_fixed", "fp64"])

@@ -284,22 +284,49 @@ def test_call_order_and_arguments(P):
 
 # binary16 half spectrum between launches: each stored value is rounded once
 # with relative error <= 2^-11 (two stores per step), so forces move by a few
-# 1e-4 relative; energy and virial come from the once-rounded spectrum
-F16_FORCE, F16_ENERGY, F16_VIRIAL = 1e-3, 2e-4, 2e-4
+# 1e-4 relative; energy and virial come from the once-rounded spectrum.
+# bfloat16 (8-bit significand) rounds with relative error u <= 2^-8: forces
+# within 2u (two roundings), energy and virial within u (each term of their
+# sums comes from the once-rounded spectrum; with a few hundred atoms a few
+# terms dominate, so the statistical margin of the binary16 bars is not taken).
+REDUCED_BARS = {"fp32_fixed_half": (1e-3, 2e-4, 2e-4), "fp32_fixed_bf16": (8e-3, 4e-3, 4e-3)}
 
 
+@pytest.mark.parametrize("precision", sorted(REDUCED_BARS))
 @pytest.mark.parametrize("case", [c for c in SMALL if c[3] in (32, 64, 128)],
                          ids=[c[0] for c in SMALL if c[3] in (32, 64, 128)])
-def test_step_half_spectrum(P, case):
+def test_step_half_spectrum(P, case, precision):
     name, nw, L, K, p, beta = case
     pos, q, box = system(name, nw, L)
-    plan = P.Plan(K, p, beta, max_atoms=len(q), precision="fp32_fixed_half")
+    plan = P.Plan(K, p, beta, max_atoms=len(q), precision=precision)
     plan.set_debug(True)
     res = plan.step(dev(pos), dev(q), box)
     # spreading is unchanged: the fixed-point grid is still the mirror's
     assert np.array_equal(plan.debug_grid(0).cpu().numpy(), oracle.mirror_grid(pos, q, box, K, p)[0])
     ref = oracle.spme(pos, q, box, K, p, beta)
-    compare(res, ref, F16_FORCE, F16_ENERGY, F16_VIRIAL)
+    compare(res, ref, *REDUCED_BARS[precision])
+
+
+@pytest.mark.parametrize("precision", sorted(REDUCED_BARS))
+def test_reduced_spectrum_is_the_rounded_fp32_spectrum(P, precision):
+    # after the spread the stored spectrum is the FP32 plan's x-pass
+    # spectrum rounded to nearest even, value by value (the rounding is
+    # torch's own conversion on the host)
+    name, nw, L, K, p, beta = SMALL[0]
+    pos, q, box = system(name, nw, L)
+    full = P.Plan(K, p, beta, max_atoms=len(q))
+    full.spread(dev(pos), dev(q), box)
+    want = torch.view_as_real(full.debug_grid(1)).cpu()
+    red = P.Plan(K, p, beta, max_atoms=len(q), precision=precision)
+    red.spread(dev(pos), dev(q), box)
+    got = red.debug_grid(1).cpu()
+    if precision == "fp32_fixed_half":
+        got, want = torch.view_as_real(got), want.to(torch.float16)
+    else:
+        want = want.to(torch.bfloat16)
+    assert got.shape == want.shape and got.dtype == want.dtype
+    bad = int((got.view(torch.int16) != want.view(torch.int16)).sum())
+    assert bad == 0, f"{bad} of {got.numel()} stored values differ"
 
 
 # a sheared cell: rows a1, a2, a3
