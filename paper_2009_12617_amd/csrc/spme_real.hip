@@ -12,7 +12,7 @@
 //                per workgroup (self term)
 //   k_rs_scan    one workgroup: exclusive prefix sum of the counts
 //   k_rs_fill    atoms into cell order (position, charge, original index)
-//   k_rs_pairs   one cell per workgroup: its atoms, two lanes each, against
+//   k_rs_pairs   kRsBlocks workgroups per cell: its atoms, 2 to 8 lanes each, against
 //                the atoms of the 27 neighbour cells staged in LDS with their
 //                periodic shifts applied; pairs inside the cutoff are queued
 //                per wavefront and evaluated in batches of 64; then each
@@ -34,11 +34,12 @@ namespace spme {
 namespace {
 
 constexpr int kRsThreads = 128;     // threads of a pair workgroup (two wavefronts)
-constexpr int kRsHome = kRsThreads / 2;  // home atoms per pass (two lanes each)
-constexpr int kRsBlocks = 2;        // pair workgroups per cell (home atoms dealt out in passes)
+constexpr int kRsHome = kRsThreads / 2;  // most home atoms per pass (two lanes each)
+constexpr int kRsMaxSplit = 8;      // most lanes sharing one home atom's candidates
+constexpr int kRsBlocks = 4;        // pair workgroups per cell (home atoms dealt out in passes)
 constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (< 2^24)
 constexpr int kRsUnroll = 2;        // candidates each lane tests per step
-static_assert(kRsStage % (2 * kRsUnroll) == 0, "the padded stage must fit");
+static_assert(kRsStage % (kRsMaxSplit * kRsUnroll) == 0, "the padded stage must fit");
 constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
                                     // followed by one discard slot per lane
 constexpr int kRsCountThreads = 256;
@@ -265,15 +266,19 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   const double two_over_sqrtpi = 1.12837916709551257390;
   double e_pair = 0.0, e_excl = 0.0;
   int* wq = queue[wave];
-  // Home atoms of the cell in passes of up to kRsHome, pass i going to
-  // workgroup i mod kRsBlocks; two lanes per home atom (lane L: home L mod
-  // nh, candidates of parity L / nh).  Each lane tests its candidates in
-  // step with the wavefront (every lane reads the same staged atom); pairs
-  // inside the cutoff go to the wavefront's queue, and the erfc work runs
-  // only on full batches of 64 queued pairs, one per lane.
-  for (int hb = h0 + blk * kRsHome; hb < h1; hb += kRsBlocks * kRsHome) {
-    const int nh = min(kRsHome, h1 - hb);
-    const bool active = tid < 2 * nh;
+  // Home atoms of the cell dealt evenly over its kRsBlocks workgroups, in
+  // passes of at most kRsHome.  S lanes share a home atom (S = 2, 4 or 8,
+  // the most that fit the workgroup: lane L takes home L mod nh and every
+  // S-th candidate from L / nh), so a sparsely filled pass still spreads its
+  // candidate tests over the whole workgroup.  Each lane tests its
+  // candidates in step with the wavefront (every lane reads the same staged
+  // atom); pairs inside the cutoff go to the wavefront's queue, and the erfc
+  // work runs only on full batches of 64 queued pairs, one per lane.
+  const int chunk = max(1, min(kRsHome, (h1 - h0 + kRsBlocks - 1) / kRsBlocks));
+  for (int hb = h0 + blk * chunk; hb < h1; hb += kRsBlocks * chunk) {
+    const int nh = min(chunk, h1 - hb);
+    const int S = nh > kRsThreads / 4 ? 2 : nh > kRsThreads / 8 ? 4 : kRsMaxSplit;
+    const bool active = tid < S * nh;
     const int slot = active ? tid % nh : 0, split = active ? tid / nh : 0;
     __syncthreads();  // the previous pass is done with home and hf
     if (tid < nh) {
@@ -289,8 +294,9 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
     }
     for (int s0 = 0; s0 < total; s0 += kRsStage) {
       const int sn = min(kRsStage, total - s0);
-      // padded to whole steps with atoms far away (never inside the cutoff)
-      const int snp = (sn + 2 * kRsUnroll - 1) / (2 * kRsUnroll) * (2 * kRsUnroll);
+      // padded to whole steps with atoms far away (never inside the cutoff);
+      // kRsStage is a multiple of every step S * kRsUnroll
+      const int snp = (sn + S * kRsUnroll - 1) / (S * kRsUnroll) * (S * kRsUnroll);
       __syncthreads();
       for (int t = tid; t < snp; t += kRsThreads) {
         if (t >= sn) {
@@ -305,15 +311,15 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
         stage[t] = make_double4(r.x + nb_shift[k][0], r.y + nb_shift[k][1], r.z + nb_shift[k][2], r.w);
       }
       __syncthreads();
-      if (wave * 64 >= 2 * nh) continue;  // no active lane in this wavefront
+      if (wave * 64 >= S * nh) continue;  // no active lane in this wavefront
       // ring of queued pairs: head qh, length qn (uniform over the wavefront)
       int qh = 0, qn = 0;
       const int entry0 = (split << 7) | slot;
-      for (int t0 = 0; t0 < sn; t0 += 2 * kRsUnroll) {
+      for (int t0 = 0; t0 < sn; t0 += S * kRsUnroll) {
         // kRsUnroll candidates per lane, loads issued together
         double4 rj[kRsUnroll];
 #pragma unroll
-        for (int u = 0; u < kRsUnroll; ++u) rj[u] = stage[t0 + 2 * u + split];
+        for (int u = 0; u < kRsUnroll; ++u) rj[u] = stage[t0 + S * u + split];
 #pragma unroll
         for (int u = 0; u < kRsUnroll; ++u) {
           // branch-free: every lane writes, a miss into its discard slot.
@@ -325,7 +331,7 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
           const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
           wq[hit ? ((qh + qn + below) & (kRsQueue - 1)) : kRsQueue + lane] =
-              entry0 + ((t0 + 2 * u) << 7);
+              entry0 + ((t0 + S * u) << 7);
           qn += __popcll(m);
         }
         while (qn >= 64) {
