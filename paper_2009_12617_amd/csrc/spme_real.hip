@@ -198,7 +198,10 @@ __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, c
   const int t = entry >> 7, s = entry & 127;
   const double4 rj = stage[t], ri = home[s];
   const double d[3] = {ri.x - rj.x, ri.y - rj.y, ri.z - rj.z};
-  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  // the home atom's own staged copy (and an atom on the same position) is
+  // queued too, at distance exactly 0: it adds nothing
+  const bool paired = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] > 0.0;
+  const double r2 = paired ? d[0] * d[0] + d[1] * d[1] + d[2] * d[2] : 1.0;
   double rinv = __builtin_amdgcn_rsq(r2);
   rinv = rinv * fma(-0.5 * r2 * rinv, rinv, 1.5);
   rinv = rinv * fma(-0.5 * r2 * rinv, rinv, 1.5);
@@ -213,7 +216,7 @@ __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, c
     b1 = b0;
   }
   const double ec = ex * fma(tc, b1, a.cheb[0] - b2) * rinv;  // erfc(beta r) / r
-  const double qq = a.coulomb * ri.w * rj.w;
+  const double qq = paired ? a.coulomb * ri.w * rj.w : 0.0;
   e += 0.5 * qq * ec;
   const double g = qq * (ec + two_over_sqrtpi * a.beta * ex) * (rinv * rinv);
 #pragma unroll
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   __shared__ double nb_shift[27][3];
   __shared__ double4 home[kRsHome];
   __shared__ double hf[kRsHome][3];
-  __shared__ int queue[kRsThreads / 64][kRsQueue + 64];
+  __shared__ int queue[kRsThreads / 64][kRsQueue];
   __shared__ double wred[16 * 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cell = blockIdx.x, blk = blockIdx.y;
@@ -322,16 +325,17 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
         for (int u = 0; u < kRsUnroll; ++u) rj[u] = stage[t0 + S * u + split];
 #pragma unroll
         for (int u = 0; u < kRsUnroll; ++u) {
-          // branch-free: every lane writes, a miss into its discard slot.
-          // The home atom's own staged copy is at distance exactly 0.
+          // one compare per candidate: the home atom's own staged copy (at
+          // distance exactly 0) is queued as well and adds nothing there
           const double d0 = ri.x - rj[u].x, d1 = ri.y - rj[u].y, d2 = ri.z - rj[u].z;
           const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-          const bool hit = (r2 <= a.rc2) & (r2 > 0.0);
+          const bool hit = r2 <= a.rc2;
           const unsigned long long m = __ballot(hit);
-          const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-          wq[hit ? ((qh + qn + below) & (kRsQueue - 1)) : kRsQueue + lane] =
-              entry0 + ((t0 + S * u) << 7);
+          if (hit) {
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            wq[(qh + qn + below) & (kRsQueue - 1)] = entry0 + ((t0 + S * u) << 7);
+          }
           qn += __popcll(m);
         }
         while (qn >= 64) {

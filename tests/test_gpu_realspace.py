@@ -87,6 +87,42 @@ def test_real_space_screening_range(P, beta):
     assert ei.value.code == 2
 
 
+def test_coincident_atoms_are_not_paired(P):
+    # atom B placed exactly on atom A (another water's oxygen): the pair
+    # (A, B) is skipped, every other pair counts.  The oracle cannot take
+    # the system whole (its A-B term is infinite), so the expected values
+    # are combined from three systems it can take: without B, without A,
+    # and without both (each pair term appears in exactly one of them with
+    # the right sign)
+    pos, q, box = I.water_box(300, 22.0, 35)
+    A, B = 0, 3 * 150
+    pos = pos.copy()
+    pos[B] = pos[A]
+    beta, rcut = 0.4, 7.0
+    rs = P.RealSpace(len(q))
+    f, e = rs(dev(pos), dev(q), box, beta, rcut)
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    keep = np.ones(len(q), bool)
+    w = np.mod(pos, 22.0)
+
+    def part(drop):
+        m = keep.copy()
+        m[list(drop)] = False
+        r = oracle.ewald_real(w[m], q[m], box, beta, nimg=1, rcut=rcut)
+        full = np.zeros_like(pos)
+        full[m] = r["forces"]
+        return full, r["E_real"]
+    f_nb, e_nb = part([B])
+    f_na, e_na = part([A])
+    f_no, e_no = part([A, B])
+    want_f = f_nb + f_na - f_no
+    want_e = e_nb + e_na - e_no
+    print(f"force_rel_rms={rel_rms(f, want_f):.2e} E_real={e[0]:.10f} ref={want_e:.10f}", flush=True)
+    assert np.all(np.isfinite(f)) and np.isfinite(e[0])
+    assert rel_rms(f, want_f) <= 1e-11
+    assert e[0] == pytest.approx(want_e, rel=1e-11)
+
+
 def test_real_space_accumulates_and_rejects_bad_geometry(P):
     from paper_2009_12617_amd._lib import SpmeError
     pos, q, box = I.water_box(100, 16.0, 32)
