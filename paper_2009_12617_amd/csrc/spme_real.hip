@@ -41,7 +41,8 @@ constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (<
 constexpr int kRsUnroll = 2;        // candidates each lane tests per step
 static_assert(kRsStage % (kRsMaxSplit * kRsUnroll) == 0, "the padded stage must fit");
 constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
-                                    // followed by one discard slot per lane
+static_assert((kRsQueue & (kRsQueue - 1)) == 0 && kRsQueue >= 64 + 64 * kRsUnroll,
+              "a wavefront's ring holds under 64 leftovers plus one step's hits");
 constexpr int kRsCountThreads = 256;
 constexpr int kRsCheb = 32;         // Chebyshev terms of exp(x^2) erfc(x)
 constexpr double kRsMaxBetaRcut = 6.0;  // series error <= 2e-14 relative up to here
