@@ -9,6 +9,8 @@ Bars:
 Sizes span several plane/pencil tiles and ragged atom chunks; the full
 benchmark-size systems are compared over every atom.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -116,6 +118,15 @@ def test_step_fp64(P, case):
     assert np.abs(grid - ref["Q"]).max() < 1e-13
 
 
+# binary16 half spectrum between launches: each stored value is rounded once
+# with relative error <= 2^-11 (two stores per step), so forces move by a few
+# 1e-4 relative; energy and virial come from the once-rounded spectrum.
+# bfloat16 (8-bit significand) rounds with relative error u <= 2^-8: forces
+# within 2u (two roundings), energy and virial within u (each term of their
+# sums comes from the once-rounded spectrum; with a few hundred atoms a few
+# terms dominate, so the statistical margin of the binary16 bars is not taken).
+REDUCED_BARS = {"fp32_fixed_half": (1e-3, 2e-4, 2e-4), "fp32_fixed_bf16": (8e-3, 4e-3, 4e-3)}
+
 WORKLOADS = [I.SMALL_32, I.HEADLINE_64, I.LARGE_128_P4, I.LARGE_128_P6]
 
 
@@ -139,6 +150,24 @@ def test_full_size_fp64(P, w):
     res = plan.step(dev(pos), dev(q), box)
     ref = oracle.spme(pos, q, box, w.K, w.order, w.beta)
     compare(res, ref, F64_FORCE, F64_ENERGY, 1e-11)
+
+
+@pytest.mark.parametrize("precision", sorted(REDUCED_BARS))
+@pytest.mark.parametrize("w", [I.HEADLINE_64, I.LARGE_128_P6], ids=["water_65535_k64", "water_209715_k128_p6"])
+def test_full_size_reduced_spectrum(P, w, precision):
+    # the 16-bit spectra at the full sizes (128^3 takes the split
+    # convolution with its full-precision intermediate)
+    pos, q, box = w.make()
+    plan = P.Plan(w.K, w.order, w.beta, max_atoms=len(q), precision=precision)
+    res = plan.step(dev(pos), dev(q), box)
+    compare(res, full_size_ref(w.name), *REDUCED_BARS[precision])
+
+
+@functools.lru_cache(maxsize=None)
+def full_size_ref(name):
+    w = {x.name: x for x in WORKLOADS}[name]
+    pos, q, box = w.make()
+    return oracle.spme(pos, q, box, w.K, w.order, w.beta)
 
 
 def test_jittered_frames_reuse_plan(P):
@@ -282,14 +311,6 @@ def test_call_order_and_arguments(P):
     assert ei.value.code == 1
 
 
-# binary16 half spectrum between launches: each stored value is rounded once
-# with relative error <= 2^-11 (two stores per step), so forces move by a few
-# 1e-4 relative; energy and virial come from the once-rounded spectrum.
-# bfloat16 (8-bit significand) rounds with relative error u <= 2^-8: forces
-# within 2u (two roundings), energy and virial within u (each term of their
-# sums comes from the once-rounded spectrum; with a few hundred atoms a few
-# terms dominate, so the statistical margin of the binary16 bars is not taken).
-REDUCED_BARS = {"fp32_fixed_half": (1e-3, 2e-4, 2e-4), "fp32_fixed_bf16": (8e-3, 4e-3, 4e-3)}
 
 
 @pytest.mark.parametrize("precision", sorted(REDUCED_BARS))
