@@ -231,9 +231,9 @@ int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
  * Forces are -grad of E_real + E_excl.  FP64 throughout; diagonal boxes
  * only (PME_EUNSUPPORTED otherwise, when rcut > L/3 on some axis, or when
  * beta rcut > 6, where erfc(beta rcut) < 3e-17 and a shorter cutoff gives the
- * same sums).  erfc of a pair inside the cutoff comes from a 32-term
- * Chebyshev series of exp(x^2) erfc(x) on [0, beta rcut], relative error
- * <= 2e-14.  Two distinct atoms at exactly the same position are not paired
+ * same sums).  erfc of a pair inside the cutoff comes from a Chebyshev
+ * series of exp(x^2) erfc(x) on [0, beta rcut] (24 terms up to beta rcut =
+ * 3.2, 32 beyond), relative error <= 2e-14.  Two distinct atoms at exactly the same position are not paired
  * (their pair term is infinite).
  * ------------------------------------------------------------------------ */
 

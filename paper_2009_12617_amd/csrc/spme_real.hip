@@ -45,6 +45,8 @@ static_assert((kRsQueue & (kRsQueue - 1)) == 0 && kRsQueue >= 64 + 64 * kRsUnrol
               "a wavefront's ring holds under 64 leftovers plus one step's hits");
 constexpr int kRsCountThreads = 256;
 constexpr int kRsCheb = 32;         // Chebyshev terms of exp(x^2) erfc(x)
+constexpr int kRsChebShort = 24;    // terms enough for beta rcut <= kRsShortRange
+constexpr double kRsShortRange = 3.2;  // 24 terms: <= 1.3e-14 relative up to here
 constexpr double kRsMaxBetaRcut = 6.0;  // series error <= 2e-14 relative up to here
 constexpr int kRsScanThreads = 1024;
 
@@ -54,6 +56,7 @@ struct RsArgs {
   double L[3], invL[3], cell_inv[3];
   double beta, rc2, rcut, coulomb;
   double cheb[kRsCheb];  // exp(x^2) erfc(x) on [0, beta rcut] as a Chebyshev series
+  int ncheb;             // terms the pair kernel uses: kRsChebShort or kRsCheb
   double cheb_scale;     // 2 / (beta rcut)
   const double* pos;
   const double* q;
@@ -189,10 +192,12 @@ __global__ __launch_bounds__(256) void k_rs_fill(RsArgs a) {
 // << 7) | home slot.  Adds the pair's energy to e and its force on the home
 // atom to hf (LDS atomics: a home atom's pairs are spread over lanes and
 // wavefronts).  erfc(x) = exp(-x^2) erfcx(x), with erfcx = exp(x^2) erfc(x)
-// from its Chebyshev series on [0, beta rcut] (Clenshaw's recurrence, the
-// coefficients uniform over the launch), so the exp the force needs is the
+// from its Chebyshev series on [0, beta rcut] (Clenshaw's recurrence over NC
+// terms, 24 up to beta rcut = 3.2 and 32 beyond; the coefficients uniform
+// over the launch), so the exp the force needs is the
 // only transcendental besides 1/r (hardware reciprocal square root and two
 // Newton steps).
+template <int NC>
 __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, const double4* home,
                                         double (*hf)[3], int entry, double& e) {
   const double two_over_sqrtpi = 1.12837916709551257390;
@@ -211,7 +216,7 @@ __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, c
   const double tc = fma(br, a.cheb_scale, -1.0), t2 = tc + tc;
   double b1 = 0.0, b2 = 0.0;
 #pragma unroll
-  for (int k = kRsCheb - 1; k >= 1; --k) {
+  for (int k = NC - 1; k >= 1; --k) {
     const double b0 = fma(t2, b1, a.cheb[k] - b2);
     b2 = b1;
     b1 = b0;
@@ -224,6 +229,7 @@ __device__ __forceinline__ void rs_pair(const RsArgs& a, const double4* stage, c
   for (int c = 0; c < 3; ++c) atomicAdd(&hf[s][c], g * d[c]);
 }
 
+template <int NC>
 __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   __shared__ double4 stage[kRsStage];
   __shared__ int nb_start[27], nb_pre[28];
@@ -341,13 +347,13 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
         }
         while (qn >= 64) {
           lds_order();
-          rs_pair(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
+          rs_pair<NC>(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
           qh += 64;
           qn -= 64;
         }
       }
       lds_order();
-      if (lane < qn) rs_pair(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
+      if (lane < qn) rs_pair<NC>(a, stage, home, hf, wq[(qh + lane) & (kRsQueue - 1)], e_pair);
     }
     if (active && split == 0 && a.excl_off != nullptr) {
       // excluded partners: remove the erfc/r the pair sum took (inside the
@@ -517,6 +523,9 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
       a.cheb[k] = (k == 0 ? 1.0 : 2.0) * c / kNodes;
     }
     a.cheb_scale = 2.0 / X;
+    // a shorter range needs fewer terms (the coefficients of this entire
+    // function fall off faster on a shorter interval)
+    a.ncheb = X <= kRsShortRange ? kRsChebShort : kRsCheb;
   }
   a.coulomb = coulomb;
   a.pos = pos;
@@ -542,7 +551,10 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
   }
   k_rs_scan<<<dim3(1), dim3(kRsScanThreads), 0, s>>>(a);
   if (N > 0) k_rs_fill<<<dim3(nb), dim3(256), 0, s>>>(a);
-  k_rs_pairs<<<dim3(a.ncell, kRsBlocks), dim3(kRsThreads), 0, s>>>(a);
+  if (a.ncheb == kRsChebShort)
+    k_rs_pairs<kRsChebShort><<<dim3(a.ncell, kRsBlocks), dim3(kRsThreads), 0, s>>>(a);
+  else
+    k_rs_pairs<kRsCheb><<<dim3(a.ncell, kRsBlocks), dim3(kRsThreads), 0, s>>>(a);
   k_rs_reduce<<<dim3(1), dim3(64), 0, s>>>(a);
   return hipGetLastError() == hipSuccess ? PME_OK : PME_EDEVICE;
 }
