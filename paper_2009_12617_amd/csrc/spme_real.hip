@@ -102,26 +102,30 @@ __global__ __launch_bounds__(256) void k_rs_zero(RsArgs a) {
 // wavefront (lanes with c < 0 take no part) and returns each lane's slot:
 // the counter's old value plus the number of lanes of the same c below it.
 // Neighbouring atoms (the atoms of a molecule) usually share a cell, so this
-// issues a fraction of the per-atom atomics on the contended counters.
+// issues a fraction of the per-atom atomics on the contended counters.  The
+// groups of equal c are found first (ballots only); then every group's
+// first lane issues its atomic at once, so the wavefront waits for one
+// atomic round trip, not one per group.
 __device__ __forceinline__ unsigned wave_add(unsigned* counter, int c) {
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(c >= 0);
-  unsigned slot = 0u;
+  int leader = lane;  // first lane of this lane's group
+  unsigned n = 0u, below = 0u;
   while (todo != 0ull) {  // uniform over the wavefront
-    const int leader = __ffsll((long long)todo) - 1;
-    const int cl = __shfl(c, leader, 64);
+    const int first = __ffsll((long long)todo) - 1;
+    const int cl = __shfl(c, first, 64);
     const unsigned long long same = __ballot(c == cl) & todo;
-    unsigned base = 0u;
-    if (lane == leader) base = atomicAdd(&counter[cl], (unsigned)__popcll(same));
-    base = __shfl(base, leader, 64);
     if (c == cl) {
-      const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
-      slot = base + (unsigned)below;
+      leader = first;
+      below = __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
     }
+    if (lane == first) n = (unsigned)__popcll(same);
     todo &= ~same;
   }
-  return slot;
+  unsigned base = 0u;
+  if (c >= 0 && lane == leader) base = atomicAdd(&counter[c], n);
+  return __shfl(base, leader, 64) + below;
 }
 
 __global__ __launch_bounds__(kRsCountThreads) void k_rs_count(RsArgs a) {
