@@ -113,7 +113,7 @@ __device__ __forceinline__ unsigned wave_add(unsigned* counter, int c) {
   unsigned n = 0u, below = 0u;
   while (todo != 0ull) {  // uniform over the wavefront
     const int first = __ffsll((long long)todo) - 1;
-    const int cl = __shfl(c, first, 64);
+    const int cl = __builtin_amdgcn_readlane(c, first);  // first is uniform
     const unsigned long long same = __ballot(c == cl) & todo;
     if (c == cl) {
       leader = first;
