@@ -85,7 +85,8 @@ typedef enum {
   PME_EOVERFLOW = 4,     /* fixed-point headroom exceeded (sum |q| 2^F >= 2^51) */
   PME_EDEVICE = 5,       /* a HIP runtime call failed */
   PME_ENONFINITE = 6,    /* a position or charge was NaN or infinite */
-  PME_ESTATE = 7         /* call out of order (e.g. pme_solve before pme_spread) */
+  PME_ESTATE = 7,        /* call out of order (e.g. pme_solve before pme_spread) */
+  PME_EBUSY = 8          /* batch admission: no free slot or arena range for the system */
 } pme_status;
 
 /* Sticky device flags reported by pme_check. */
@@ -112,8 +113,11 @@ size_t pme_workspace_bytes(int K1, int K2, int K3, int order, int max_atoms, int
  *               owned by the caller, must outlive the plan, must not be used
  *               by anyone else while the plan exists
  *   stream      hipStream_t (NULL = the default stream)
- * Uploads the plan tables (moduli, twiddles) and synchronises the stream
- * once.  On failure *out is NULL. */
+ * Enqueues one initialisation launch on the stream (per-axis B-spline
+ * moduli and twiddles computed on the device in FP64, counters cleared);
+ * no host synchronisation.  Later calls on the plan are ordered after it on
+ * the stream.  On failure *out is NULL.  The kernel variants start at the
+ * built-in choice for the shape (pme_default_tuning). */
 int pme_create(pme_plan **out, int K1, int K2, int K3, int order, double beta, int max_atoms,
                int precision, int frac_bits, double coulomb, void *workspace,
                size_t workspace_bytes, void *stream);
@@ -156,14 +160,20 @@ int pme_solve(pme_plan *plan, double *ev);
  *   accumulate  0 overwrites, 1 adds to the existing values */
 int pme_gather(pme_plan *plan, double *forces, int accumulate);
 
-/* The whole step: pme_spread + pme_solve + pme_gather. */
+/* The whole step (§III.A, Fig. 2: each timestep the long-range pipeline
+ * takes positions and charges and returns the long-range force on every
+ * atom): pme_spread + pme_solve + pme_gather, with the energy/virial sum
+ * folded into the last launch. */
 int pme_step(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
              double *forces, int accumulate, double *ev);
 
 /* Bind the inputs and outputs of this plan's next batched steps (same
- * meaning and checks as pme_step's arguments).  Copies them synchronously to
- * the plan's workspace; rebind whenever a pointer, N or the box changes.
- * Buffers must stay valid while batched runs use them. */
+ * meaning and checks as pme_step's arguments).  The arguments are written to
+ * the plan's workspace by a one-workgroup launch on the plan's stream, so a
+ * bind is stream-ordered: batched runs enqueued before it on that stream
+ * still see the previous binding, runs enqueued after it (or ordered after
+ * it by an event) see the new one.  Rebind whenever a pointer, N or the box
+ * changes.  Buffers must stay valid while batched runs use them. */
 int pme_bind(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
              double *forces, int accumulate, double *ev);
 
@@ -178,6 +188,139 @@ int pme_bind(pme_plan *plan, const double *pos, const double *q, int N, const do
  * pme_gather, or pme_batch_run): the atom buckets a spread fills are moved
  * on by the convolution that follows it. */
 int pme_batch_run(pme_plan *const *plans, int n, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel variants and autotuning.  The paper fixes its FFT size and stage
+ * count per bitstream (§IV.A); here the shape of the work is chosen per plan
+ * among variants that compute the same step (same E, forces and virial up
+ * to FP32 summation order), by default from a built-in rule or by measuring
+ * them on the device (pme_autotune).
+ * ------------------------------------------------------------------------ */
+#define PME_CONV_FUSED 0   /* y/z transforms, influence function and inverse y/z transforms:
+                              one workgroup per x' column, the column held in LDS (one launch) */
+#define PME_CONV_SPLIT 1   /* the same in three launches of row-chunk workgroups (forward y;
+                              z, influence function, inverse z; inverse y), the half
+                              spectrum in the workspace between them */
+#define PME_INTERP_FUSED 0 /* each (z-plane, y-slice) tile transforms the potential rows its
+                              atoms read back along x in LDS, then interpolates (one launch) */
+#define PME_INTERP_SPLIT 1 /* inverse x transform once per plane into the workspace, then
+                              a gather launch */
+/* bits of pme_tuning_variants() */
+#define PME_VAR_CONV_FUSED 1u
+#define PME_VAR_CONV_SPLIT 2u
+#define PME_VAR_INTERP_FUSED 4u
+#define PME_VAR_INTERP_SPLIT 8u
+
+typedef struct {
+  int conv;       /* PME_CONV_FUSED or PME_CONV_SPLIT */
+  int interp;     /* PME_INTERP_FUSED or PME_INTERP_SPLIT */
+  int bin_chunk;  /* atoms per binning workgroup: 256, 512 or 1024 */
+} pme_tuning;
+
+/* Variants a plan with these parameters can run (PME_VAR_* bits; 0 when the
+ * parameters are unsupported).  Host only. */
+unsigned pme_tuning_variants(int K1, int K2, int K3, int order, int precision);
+
+/* The built-in choice for these parameters (PME_EUNSUPPORTED when none). */
+int pme_default_tuning(int K1, int K2, int K3, int order, int precision, pme_tuning *out);
+
+/* Read or change a plan's variants.  pme_set_tuning returns
+ * PME_EUNSUPPORTED for a variant the plan's shape cannot run and PME_EINVAL
+ * for a bin_chunk outside {256, 512, 1024}; it takes effect at the next
+ * spread (or bind).  Changing the variants between pme_spread and pme_gather
+ * returns PME_ESTATE. */
+int pme_get_tuning(pme_plan *plan, pme_tuning *out);
+int pme_set_tuning(pme_plan *plan, const pme_tuning *t);
+
+/* Autotuning: runs whole steps (pme_step with these arguments) of every
+ * variant the plan supports -- each conv x interp x bin_chunk combination,
+ * in that nesting order, bin_chunk fastest -- `reps` timed steps each
+ * (after 3 untimed), measured with HIP events on the plan's stream; repeats
+ * the sweep three times and keeps each candidate's best mean.  Leaves the
+ * plan set to the fastest and returns it in *best with its time in
+ * *best_us (microseconds per step).  times_us (may be NULL) receives up to
+ * max_times candidate times in the same order, unsupported candidates as
+ * -1.  Synchronises the plan's stream; forces and ev hold the last step.
+ * Returns PME_EINVAL for reps < 1. */
+int pme_autotune(pme_plan *plan, const double *pos, const double *q, int N, const double box[9],
+                 double *forces, double *ev, int reps, pme_tuning *best, double *best_us,
+                 double *times_us, int max_times);
+
+/* ------------------------------------------------------------------------
+ * Batch admission (continuous batching of independent systems).  A batch
+ * owns up to max_systems resident systems inside one caller-owned device
+ * arena: admitting a system carves its workspace out of the arena (first
+ * fit over a free list, 256-byte aligned) and creates and binds its plan;
+ * retiring it returns the range (merged with free neighbours).  A launch
+ * runs one step of every admitted system, grid groups overlapping on
+ * forked streams.  Everything is enqueued on the batch's stream; nothing
+ * synchronises the host.
+ * ------------------------------------------------------------------------ */
+typedef struct pme_batch pme_batch;
+
+typedef struct {
+  int K1, K2, K3;       /* grid */
+  int order;            /* B-spline order p */
+  double beta;          /* Ewald splitting parameter (1/A) */
+  int precision;        /* pme_precision */
+  int max_atoms;        /* largest N this system will be updated to */
+  const double *pos;    /* device [N][3], or NULL: carved from the arena with q, forces, ev */
+  const double *q;      /* device [N] (NULL iff pos is NULL) */
+  int N;
+  double box[9];        /* rows a1, a2, a3 (A) */
+  double *forces;       /* device [N][3] (NULL iff pos is NULL) */
+  double *ev;           /* device [7], or NULL (not written; carved when pos is NULL) */
+} pme_system_desc;
+
+/* Arena bytes admitting this system takes (0 when unsupported): its plan
+ * workspace, plus max_atoms x 56 + 56 bytes of inputs and outputs when the
+ * desc leaves pos NULL. */
+size_t pme_batch_footprint(const pme_system_desc *s);
+
+/* Create a batch over `arena` (device, 256-byte aligned, arena_bytes long,
+ * owned by the caller and unused by anyone else while the batch exists);
+ * max_systems in [1, 4096]; stream a hipStream_t.  Host only: the batch's
+ * three fork streams are created at its first admission. */
+int pme_batch_create(pme_batch **out, int max_systems, void *arena, size_t arena_bytes,
+                     void *stream);
+
+/* Destroy the batch and every plan still admitted (does not wait for
+ * enqueued work; does not free the arena). */
+int pme_batch_destroy(pme_batch *b);
+
+/* Admit a system: PME_EBUSY when every slot is taken or no free range of
+ * the arena is large enough (nothing changes then); otherwise *slot is its
+ * handle.  Argument errors as for pme_create and pme_bind. */
+int pme_batch_admit(pme_batch *b, const pme_system_desc *s, int *slot);
+
+/* New inputs/outputs of an admitted system (as pme_bind, on the batch's
+ * stream; N <= its max_atoms). */
+int pme_batch_update(pme_batch *b, int slot, const double *pos, const double *q, int N,
+                     const double box[9], double *forces, double *ev);
+
+/* Retire an admitted system: its plan is destroyed and its arena range
+ * returned.  Work already enqueued for it completes first (stream order);
+ * a later admission may reuse the range only after that work. */
+int pme_batch_retire(pme_batch *b, int slot);
+
+/* Device buffers of an admitted system (those carved from the arena, or
+ * the caller's): positions [max_atoms][3], charges [max_atoms], forces
+ * [max_atoms][3], energy/virial [7] (may be NULL for a caller's ev). */
+int pme_batch_io(pme_batch *b, int slot, double **pos, double **q, double **forces, double **ev);
+
+/* One step of the n listed admitted slots (slots NULL: every admitted
+ * system; a slot listed twice is PME_EINVAL): systems sharing precision,
+ * grid, order and variants share every launch; the groups run on up to
+ * three forked streams joined back into the batch's stream (so a launch can
+ * be captured in a hipGraph as one fork/join).  PME_OK with nothing to
+ * run. */
+int pme_batch_launch(pme_batch *b, const int *slots, int n);
+
+/* Occupancy: admitted systems, arena bytes in use, largest free range. */
+int pme_batch_stats(pme_batch *b, int *admitted, size_t *bytes_used, size_t *largest_free);
+
+/* The plan of an admitted slot (NULL otherwise), e.g. for pme_check. */
+pme_plan *pme_batch_plan(pme_batch *b, int slot);
 
 /* Keep a copy of the charge grid at each spread (costs K1 K2 K3 x 8 bytes
  * of extra writes; off by default). */

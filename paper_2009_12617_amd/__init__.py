@@ -9,11 +9,11 @@ PyTorch only provides device memory and streams.  Submodules are imported
 lazily so that `paper_2009_12617_amd.inputs` works without torch or a GPU.
 """
 
-__all__ = ["Plan", "Batch", "KERNEL_NAMES", "RealSpace"]
+__all__ = ["Plan", "Batch", "BatchPool", "KERNEL_NAMES", "RealSpace"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "Batch", "KERNEL_NAMES"):
+    if name in ("Plan", "Batch", "BatchPool", "KERNEL_NAMES", "TUNE_CANDIDATES"):
         from . import plan as _plan
         return getattr(_plan, name)
     if name == "RealSpace":

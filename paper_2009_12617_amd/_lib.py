@@ -19,8 +19,31 @@ PME_FLAG_NONFINITE = 1
 PME_FLAG_OVERFLOW = 2
 PME_FLAG_BUCKETS = 4
 
+PME_EBUSY = 8
+PME_CONV_FUSED, PME_CONV_SPLIT = 0, 1
+PME_INTERP_FUSED, PME_INTERP_SPLIT = 0, 1
+PME_VAR_CONV_FUSED, PME_VAR_CONV_SPLIT, PME_VAR_INTERP_FUSED, PME_VAR_INTERP_SPLIT = 1, 2, 4, 8
+
 STATUS = {0: "PME_OK", 1: "PME_EINVAL", 2: "PME_EUNSUPPORTED", 3: "PME_EWORKSPACE",
-          4: "PME_EOVERFLOW", 5: "PME_EDEVICE", 6: "PME_ENONFINITE", 7: "PME_ESTATE"}
+          4: "PME_EOVERFLOW", 5: "PME_EDEVICE", 6: "PME_ENONFINITE", 7: "PME_ESTATE",
+          8: "PME_EBUSY"}
+
+
+class Tuning(ctypes.Structure):
+    """pme_tuning: the kernel variants of a plan."""
+    _fields_ = [("conv", ctypes.c_int), ("interp", ctypes.c_int), ("bin_chunk", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"conv": int(self.conv), "interp": int(self.interp), "bin_chunk": int(self.bin_chunk)}
+
+
+class SystemDesc(ctypes.Structure):
+    """pme_system_desc: one system of a batch."""
+    _fields_ = [("K1", ctypes.c_int), ("K2", ctypes.c_int), ("K3", ctypes.c_int),
+                ("order", ctypes.c_int), ("beta", ctypes.c_double), ("precision", ctypes.c_int),
+                ("max_atoms", ctypes.c_int), ("pos", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("N", ctypes.c_int), ("box", ctypes.c_double * 9), ("forces", ctypes.c_void_p),
+                ("ev", ctypes.c_void_p)]
 
 _lib = None
 
@@ -90,6 +113,38 @@ def load():
     lib.pme_real_workspace_bytes.argtypes = [i, i]
     lib.pme_real.restype = i
     lib.pme_real.argtypes = [vp, vp, i, dp, d, d, d, vp, vp, vp, i, vp, vp, sz, i, i, vp]
+    tp = ctypes.POINTER(Tuning)
+    sdp = ctypes.POINTER(SystemDesc)
+    lib.pme_tuning_variants.restype = ctypes.c_uint
+    lib.pme_tuning_variants.argtypes = [i, i, i, i, i]
+    lib.pme_default_tuning.restype = i
+    lib.pme_default_tuning.argtypes = [i, i, i, i, i, tp]
+    lib.pme_get_tuning.restype = i
+    lib.pme_get_tuning.argtypes = [vp, tp]
+    lib.pme_set_tuning.restype = i
+    lib.pme_set_tuning.argtypes = [vp, tp]
+    lib.pme_autotune.restype = i
+    lib.pme_autotune.argtypes = [vp, vp, vp, i, dp, vp, vp, i, tp, dp, dp, i]
+    lib.pme_batch_footprint.restype = sz
+    lib.pme_batch_footprint.argtypes = [sdp]
+    lib.pme_batch_create.restype = i
+    lib.pme_batch_create.argtypes = [ctypes.POINTER(vp), i, vp, sz, vp]
+    lib.pme_batch_destroy.restype = i
+    lib.pme_batch_destroy.argtypes = [vp]
+    lib.pme_batch_admit.restype = i
+    lib.pme_batch_admit.argtypes = [vp, sdp, ctypes.POINTER(i)]
+    lib.pme_batch_update.restype = i
+    lib.pme_batch_update.argtypes = [vp, i, vp, vp, i, dp, vp, vp]
+    lib.pme_batch_retire.restype = i
+    lib.pme_batch_retire.argtypes = [vp, i]
+    lib.pme_batch_launch.restype = i
+    lib.pme_batch_launch.argtypes = [vp, ctypes.POINTER(i), i]
+    lib.pme_batch_io.restype = i
+    lib.pme_batch_io.argtypes = [vp, i] + [ctypes.POINTER(ctypes.c_void_p)] * 4
+    lib.pme_batch_stats.restype = i
+    lib.pme_batch_stats.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.pme_batch_plan.restype = vp
+    lib.pme_batch_plan.argtypes = [vp, i]
     _lib = lib
     return lib
 

@@ -25,7 +25,8 @@ COMMON = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["spme_kernels.hip", "spme_real.hip", "spme_api.cpp"]
+SOURCES = ["spme_kern_fixed.hip", "spme_kern_fp64.hip", "spme_kern_half.hip", "spme_kern_bf16.hip",
+           "spme_kernels.hip", "spme_real.hip", "spme_api.cpp"]
 
 
 def _compile(src, verbose):

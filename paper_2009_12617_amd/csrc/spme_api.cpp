@@ -8,6 +8,10 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <set>
 #include <vector>
 
 #include "../../include/spme.h"
@@ -43,10 +47,8 @@ struct pme_plan {
   int state = kCreated;
   int keep_grid = 0;
   int grid_kept = 0;
-  // host copies of the uploaded tables
-  std::vector<double> bsq;
-  std::vector<double> tw64;
-  std::vector<float> tw32;
+  // kernel variants (pme_tuning)
+  int conv_mode = 0, interp_mode = 0, bin_chunk = 1024;
   // per-kernel timing
   int timing = 0;
   std::vector<hipEvent_t> event_pool;
@@ -65,21 +67,6 @@ namespace {
 double bspline_at(int n, double x) {
   if (n == 2) return (x >= 0.0 && x <= 2.0) ? 1.0 - std::fabs(x - 1.0) : 0.0;
   return (x * bspline_at(n - 1, x) + (n - x) * bspline_at(n - 1, x - 1.0)) / (n - 1);
-}
-
-// |b(m)|^2 = 1 / |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2 (even p: no zeros).
-void moduli(int p, int K, double* out) {
-  const double pi = 3.14159265358979323846;
-  for (int m = 0; m < K; ++m) {
-    double re = 0.0, im = 0.0;
-    for (int k = 0; k <= p - 2; ++k) {
-      const double c = bspline_at(p, k + 1.0);
-      const double ang = 2.0 * pi * (double)((long)m * k % K) / (double)K;
-      re += c * std::cos(ang);
-      im += c * std::sin(ang);
-    }
-    out[m] = 1.0 / (re * re + im * im);
-  }
 }
 
 bool is_fin(double x) { return std::isfinite(x); }
@@ -109,11 +96,36 @@ int timed(pme_plan* p, int kernel, F&& launch) {
   return PME_OK;
 }
 
+// Copies the plan's kernel variants into its launch arguments.
+void apply_tuning(pme_plan* p, Args& a) {
+  a.conv_mode = p->conv_mode;
+  a.interp_mode = p->interp_mode;
+  a.bin_chunk = p->bin_chunk;
+  a.ev_rows = spme::ev_rows_for(p->K1, p->K2, p->K3, p->precision, p->conv_mode);
+}
+
+// Raises the dynamic-LDS limits of a (precision, grid, order)'s kernels once
+// per process and device (hipFuncSetAttribute is a host call of its own per
+// kernel; plans are created in serving loops).
+hipError_t prepare_kernels_once(int K1, int K2, int K3, int order, int precision) {
+  static std::mutex mu;
+  static std::set<std::array<int, 6>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const std::array<int, 6> key{dev, K1, K2, K3, order, precision};
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(key)) return hipSuccess;
+  e = spme::prepare_kernels(K1, K2, K3, order, precision);
+  if (e == hipSuccess) done.insert(key);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
 
-int pme_version(void) { return 200; }
+int pme_version(void) { return 300; }
 
 const char* pme_strerror(int code) {
   switch (code) {
@@ -125,6 +137,7 @@ const char* pme_strerror(int code) {
     case PME_EDEVICE: return "HIP runtime error";
     case PME_ENONFINITE: return "non-finite position or charge";
     case PME_ESTATE: return "call out of order";
+    case PME_EBUSY: return "no free batch slot or arena range";
     default: return "unknown status";
   }
 }
@@ -174,46 +187,7 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   p->stream = static_cast<hipStream_t>(stream);
   p->lay = L;
 
-  // Tables per axis, x then y then z: moduli |b_a(m)|^2 and twiddles
-  // exp(-2 pi i k / K_a), rounded once from FP64.
-  const int Ks[3] = {K1, K2, K3};
-  const int ksum = K1 + K2 + K3;
-  const double pi = 3.14159265358979323846;
-  p->bsq.resize((size_t)ksum);
-  p->tw64.resize(2 * (size_t)ksum);
-  for (int ax = 0, off = 0; ax < 3; off += Ks[ax], ++ax) {
-    moduli(order, Ks[ax], p->bsq.data() + off);
-    for (int k = 0; k < Ks[ax]; ++k) {
-      const double ang = 2.0 * pi * (double)k / (double)Ks[ax];
-      p->tw64[2 * (off + k)] = std::cos(ang);
-      p->tw64[2 * (off + k) + 1] = -std::sin(ang);
-    }
-  }
-  p->tw32.resize(2 * (size_t)ksum);
-  for (int i = 0; i < 2 * ksum; ++i) p->tw32[i] = (float)p->tw64[i];
-
-  hipError_t e = spme::prepare_kernels(K1, K2, K3, order, precision);
-  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ctrl, 0, 64 * sizeof(unsigned), p->stream);
-  // bucket and overflow counts start at zero; each step's convolution
-  // clears them again for the next
-  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.bcnt, 0, L.bcnt2 - L.bcnt, p->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(p->ws + L.ovf, 0, 4 * sizeof(unsigned), p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->ws + L.bsq, p->bsq.data(), sizeof(double) * ksum,
-                       hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) {
-    if (precision != PME_FP64)
-      e = hipMemcpyAsync(p->ws + L.tw, p->tw32.data(), sizeof(float) * 2 * ksum,
-                         hipMemcpyHostToDevice, p->stream);
-    else
-      e = hipMemcpyAsync(p->ws + L.tw, p->tw64.data(), sizeof(double) * 2 * ksum,
-                         hipMemcpyHostToDevice, p->stream);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-  if (e != hipSuccess) {
-    delete p;
-    return PME_EDEVICE;
-  }
+  spme::default_variants(K1, K2, K3, order, precision, &p->conv_mode, &p->interp_mode);
   Args& a = p->cur;
   a.K1 = K1;
   a.K2 = K2;
@@ -225,10 +199,19 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
   a.coulomb = coulomb;
   a.ws = p->ws;
   a.lay = L;
+  apply_tuning(p, a);
+  // the plan tables are computed on the device from M_p at the integers
+  spme::PlanInit init{};
+  for (int k = 0; k <= order - 2; ++k) init.mp[k] = bspline_at(order, k + 1.0);
+  hipError_t e = prepare_kernels_once(K1, K2, K3, order, precision);
+  if (e == hipSuccess) e = spme::launch_init_plan(a, init, p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return PME_EDEVICE;
+  }
   *out = p;
   return PME_OK;
 }
-
 int pme_destroy(pme_plan* p) {
   if (p == nullptr) return PME_EINVAL;
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
@@ -288,7 +271,7 @@ int set_inputs(pme_plan* p, Args& a, const double* pos, const double* q, int N,
   double rec[9], vol = 0.0;
   if (!diag && !box_recip(box, rec, &vol)) return PME_EINVAL;
   a.N = N;
-  a.n_chunks = (N + spme::kChunk - 1) / spme::kChunk;
+  a.n_chunks = (N + p->bin_chunk - 1) / p->bin_chunk;
   a.pos = pos;
   a.q = q;
   a.triclinic = diag ? 0 : 1;
@@ -308,6 +291,7 @@ int set_inputs(pme_plan* p, Args& a, const double* pos, const double* q, int N,
     a.volume = vol;
   }
   a.keep_grid = p->keep_grid;
+  apply_tuning(p, a);
   a.forces = nullptr;
   a.ev = nullptr;
   a.reduce_ev = 0;
@@ -406,42 +390,67 @@ int pme_bind(pme_plan* p, const double* pos, const double* q, int N, const doubl
   b.accumulate = accumulate ? 1 : 0;
   b.ev = ev;
   b.reduce_ev = ev != nullptr ? 1 : 0;
-  if (hipMemcpy(p->ws + p->lay.args, &b, sizeof(Args), hipMemcpyHostToDevice) != hipSuccess)
+  if (spme::launch_store_args(b, reinterpret_cast<Args*>(p->ws + p->lay.args), p->stream) !=
+      hipSuccess)
     return PME_EDEVICE;
   p->bound = b;
   p->is_bound = 1;
   return PME_OK;
 }
 
-int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Plans that run together in one launch of each kernel: same precision,
+// grid, order and variants.
+bool same_group(const Args& a, const Args& b) {
+  return a.precision == b.precision && a.K1 == b.K1 && a.K2 == b.K2 && a.K3 == b.K3 &&
+         a.order == b.order && a.conv_mode == b.conv_mode && a.interp_mode == b.interp_mode;
+}
+
+// Streams a batched run may fork its grid groups onto, with the events that
+// fork them from and join them back into the calling stream.
+struct Fork {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joined;  // one per fork stream
+  hipEvent_t start = nullptr;
+};
+
+// One step of each bound plan: one binning launch per (precision, chunk),
+// then spreading, convolution and interpolation once per grid group.
+// Without fork streams every launch goes to s in stage order; with them, the
+// groups run concurrently on fork streams after the binning and join s at
+// the end.
+int batch_run_impl(pme_plan* const* plans, int n, hipStream_t s, const Fork* fork) {
   if (n < 0 || (n > 0 && plans == nullptr)) return PME_EINVAL;
   for (int i = 0; i < n; ++i) {
     if (plans[i] == nullptr) return PME_EINVAL;
     if (!plans[i]->is_bound) return PME_ESTATE;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  // groups of at most kMaxBatch plans sharing (precision, grid, order)
-  std::vector<std::vector<int>> groups;
+  {
+    // a plan twice would bin its atoms twice into one set of buckets
+    std::vector<const pme_plan*> seen(plans, plans + n);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return PME_EINVAL;
+  }
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const Args &a = plans[x]->bound, &b = plans[y]->bound;
-    if (a.precision != b.precision) return a.precision < b.precision;
-    if (a.K1 != b.K1) return a.K1 < b.K1;
-    if (a.K2 != b.K2) return a.K2 < b.K2;
-    if (a.K3 != b.K3) return a.K3 < b.K3;
-    return a.order < b.order;
+    const std::array<int, 8> ka{a.precision, a.bin_chunk, a.K1, a.K2, a.K3, a.order, a.conv_mode,
+                                a.interp_mode};
+    const std::array<int, 8> kb{b.precision, b.bin_chunk, b.K1, b.K2, b.K3, b.order, b.conv_mode,
+                                b.interp_mode};
+    return ka < kb;
   });
+  // groups of at most kMaxBatch plans (kernel launches)
+  std::vector<std::vector<int>> groups;
   for (int i : order) {
-    const Args& a = plans[i]->bound;
-    if (!groups.empty()) {
-      const Args& g = plans[groups.back()[0]]->bound;
-      if (g.precision == a.precision && g.K1 == a.K1 && g.K2 == a.K2 && g.K3 == a.K3 &&
-          g.order == a.order &&
-          (int)groups.back().size() < spme::kMaxBatch) {
-        groups.back().push_back(i);
-        continue;
-      }
+    if (!groups.empty() && same_group(plans[groups.back()[0]]->bound, plans[i]->bound) &&
+        (int)groups.back().size() < spme::kMaxBatch) {
+      groups.back().push_back(i);
+      continue;
     }
     groups.push_back({i});
   }
@@ -461,14 +470,14 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     }
     reps[g] = rep;
   }
-  // binning does not depend on the grid: one launch per precision (the
-  // order above is sorted by precision first)
+  // binning does not depend on the grid: one launch per (precision, chunk)
+  // (the order above is sorted by those first)
   std::vector<spme::BatchArgs> bin_bts;
   std::vector<Args> bin_reps;
   for (int i : order) {
     const Args& a = plans[i]->bound;
     if (bin_bts.empty() || bin_reps.back().precision != a.precision ||
-        bin_bts.back().n == spme::kMaxBatch) {
+        bin_reps.back().bin_chunk != a.bin_chunk || bin_bts.back().n == spme::kMaxBatch) {
       bin_bts.push_back(spme::BatchArgs{});
       bin_bts.back().n = 0;
       bin_reps.push_back(a);
@@ -487,20 +496,53 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     }
     p->state = kDirty;
   }
-  // stage by stage over the groups, all on one stream
   for (size_t g = 0; g < bin_bts.size(); ++g)
     if (spme::launch_bin(bin_reps[g], s, none, &bin_bts[g]) != hipSuccess) return PME_EDEVICE;
-  for (int stage = 1; stage < spme::kNumKernels; ++stage) {
-    for (size_t g = 0; g < groups.size(); ++g) {
+  const int nfork = (fork != nullptr && groups.size() > 1)
+                        ? (int)std::min(fork->streams.size(), groups.size())
+                        : 0;
+  if (nfork == 0) {
+    // stage by stage over the groups, all on one stream
+    for (int stage = 1; stage < spme::kNumKernels; ++stage) {
+      for (size_t g = 0; g < groups.size(); ++g) {
+        const Args& a = reps[g];
+        const spme::BatchArgs* bt = &bts[g];
+        hipError_t e = hipSuccess;
+        switch (stage) {
+          case 1: e = spme::launch_spread_x(a, s, none, bt); break;
+          case 2: e = spme::launch_conv(a, s, none, bt); break;
+          default: e = spme::launch_interp(a, s, none, bt); break;
+        }
+        if (e != hipSuccess) return PME_EDEVICE;
+      }
+    }
+  } else {
+    // groups dealt to the fork streams, largest grids first (they take
+    // longest), each stream running its groups' stages in order
+    if (hipEventRecord(fork->start, s) != hipSuccess) return PME_EDEVICE;
+    for (int f = 0; f < nfork; ++f)
+      if (hipStreamWaitEvent(fork->streams[f], fork->start, 0) != hipSuccess) return PME_EDEVICE;
+    std::vector<size_t> by_size(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) by_size[g] = g;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](size_t x, size_t y) {
+      const long vx = (long)reps[x].K1 * reps[x].K2 * reps[x].K3 * bts[x].n;
+      const long vy = (long)reps[y].K1 * reps[y].K2 * reps[y].K3 * bts[y].n;
+      return vx > vy;
+    });
+    for (size_t k = 0; k < by_size.size(); ++k) {
+      const size_t g = by_size[k];
+      hipStream_t fs = fork->streams[k % nfork];
       const Args& a = reps[g];
       const spme::BatchArgs* bt = &bts[g];
-      hipError_t e = hipSuccess;
-      switch (stage) {
-        case 1: e = spme::launch_spread_x(a, s, none, bt); break;
-        case 2: e = spme::launch_conv(a, s, none, bt); break;
-        default: e = spme::launch_interp(a, s, none, bt); break;
-      }
-      if (e != hipSuccess) return PME_EDEVICE;
+      if (spme::launch_spread_x(a, fs, none, bt) != hipSuccess ||
+          spme::launch_conv(a, fs, none, bt) != hipSuccess ||
+          spme::launch_interp(a, fs, none, bt) != hipSuccess)
+        return PME_EDEVICE;
+    }
+    for (int f = 0; f < nfork; ++f) {
+      if (hipEventRecord(fork->joined[f], fork->streams[f]) != hipSuccess ||
+          hipStreamWaitEvent(s, fork->joined[f], 0) != hipSuccess)
+        return PME_EDEVICE;
     }
   }
   for (int i = 0; i < n; ++i) {
@@ -511,6 +553,14 @@ int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
     p->state = kSolved;
   }
   return PME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pme_batch_run(pme_plan* const* plans, int n, void* stream) {
+  return batch_run_impl(plans, n, static_cast<hipStream_t>(stream), nullptr);
 }
 
 size_t pme_debug_grid_bytes(pme_plan* p, int which) {
@@ -594,6 +644,383 @@ int pme_kernel_times(pme_plan* p, double* ms, int n, int* steps) {
   if (steps) *steps = p->timed_steps;
   p->timed_steps = 0;
   return PME_OK;
+}
+
+
+unsigned pme_tuning_variants(int K1, int K2, int K3, int order, int precision) {
+  return spme::variants_for(K1, K2, K3, order, precision);
+}
+
+int pme_default_tuning(int K1, int K2, int K3, int order, int precision, pme_tuning* out) {
+  if (out == nullptr) return PME_EINVAL;
+  if (spme::variants_for(K1, K2, K3, order, precision) == 0u) return PME_EUNSUPPORTED;
+  spme::default_variants(K1, K2, K3, order, precision, &out->conv, &out->interp);
+  out->bin_chunk = 1024;
+  return PME_OK;
+}
+
+int pme_get_tuning(pme_plan* p, pme_tuning* out) {
+  if (p == nullptr || out == nullptr) return PME_EINVAL;
+  out->conv = p->conv_mode;
+  out->interp = p->interp_mode;
+  out->bin_chunk = p->bin_chunk;
+  return PME_OK;
+}
+
+int pme_set_tuning(pme_plan* p, const pme_tuning* t) {
+  if (p == nullptr || t == nullptr) return PME_EINVAL;
+  if (t->bin_chunk != 256 && t->bin_chunk != 512 && t->bin_chunk != 1024) return PME_EINVAL;
+  if ((t->conv != PME_CONV_FUSED && t->conv != PME_CONV_SPLIT) ||
+      (t->interp != PME_INTERP_FUSED && t->interp != PME_INTERP_SPLIT))
+    return PME_EINVAL;
+  const unsigned v = spme::variants_for(p->K1, p->K2, p->K3, p->order, p->precision);
+  const unsigned need = (t->conv == PME_CONV_FUSED ? PME_VAR_CONV_FUSED : PME_VAR_CONV_SPLIT) |
+                        (t->interp == PME_INTERP_FUSED ? PME_VAR_INTERP_FUSED : PME_VAR_INTERP_SPLIT);
+  if ((v & need) != need) return PME_EUNSUPPORTED;
+  // the convolution of a spread step must match its spread (energy rows)
+  if (p->state == kSpread) return PME_ESTATE;
+  p->conv_mode = t->conv;
+  p->interp_mode = t->interp;
+  p->bin_chunk = t->bin_chunk;
+  apply_tuning(p, p->cur);
+  return PME_OK;
+}
+
+int pme_autotune(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
+                 double* forces, double* ev, int reps, pme_tuning* best, double* best_us,
+                 double* times_us, int max_times) {
+  if (p == nullptr || reps < 1 || (max_times > 0 && times_us == nullptr)) return PME_EINVAL;
+  if (N > 0 && forces == nullptr) return PME_EINVAL;
+  const unsigned v = spme::variants_for(p->K1, p->K2, p->K3, p->order, p->precision);
+  const int convs[2] = {PME_CONV_FUSED, PME_CONV_SPLIT};
+  const int interps[2] = {PME_INTERP_FUSED, PME_INTERP_SPLIT};
+  const int chunks[3] = {256, 512, 1024};
+  std::vector<pme_tuning> cand;
+  std::vector<double> mean_us;
+  for (int c : convs)
+    for (int it : interps)
+      for (int ch : chunks) cand.push_back(pme_tuning{c, it, ch});
+  mean_us.assign(cand.size(), -1.0);
+  pme_tuning keep;
+  pme_get_tuning(p, &keep);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return PME_EDEVICE;
+  }
+  int rc = PME_OK;
+  for (int round = 0; round < 3 && rc == PME_OK; ++round) {
+    for (size_t k = 0; k < cand.size() && rc == PME_OK; ++k) {
+      const pme_tuning& t = cand[k];
+      const unsigned need =
+          (t.conv == PME_CONV_FUSED ? PME_VAR_CONV_FUSED : PME_VAR_CONV_SPLIT) |
+          (t.interp == PME_INTERP_FUSED ? PME_VAR_INTERP_FUSED : PME_VAR_INTERP_SPLIT);
+      if ((v & need) != need) continue;
+      if (p->state == kSpread) p->state = kDirty;  // (a failed step left counts behind)
+      rc = pme_set_tuning(p, &t);
+      for (int w = 0; w < 3 && rc == PME_OK; ++w)
+        rc = pme_step(p, pos, q, N, box, forces, 0, ev);
+      if (rc == PME_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = PME_EDEVICE;
+      for (int r = 0; r < reps && rc == PME_OK; ++r) rc = pme_step(p, pos, q, N, box, forces, 0, ev);
+      if (rc == PME_OK && hipEventRecord(e1, p->stream) != hipSuccess) rc = PME_EDEVICE;
+      if (rc == PME_OK && hipEventSynchronize(e1) != hipSuccess) rc = PME_EDEVICE;
+      float ms = 0.0f;
+      if (rc == PME_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PME_EDEVICE;
+      if (rc == PME_OK) {
+        const double us = 1e3 * ms / reps;
+        mean_us[k] = mean_us[k] < 0.0 ? us : std::min(mean_us[k], us);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PME_OK) {
+    pme_set_tuning(p, &keep);
+    return rc;
+  }
+  size_t kb = cand.size();
+  for (size_t k = 0; k < cand.size(); ++k)
+    if (mean_us[k] >= 0.0 && (kb == cand.size() || mean_us[k] < mean_us[kb])) kb = k;
+  if (kb == cand.size()) return PME_EUNSUPPORTED;
+  for (int k = 0; k < max_times && k < (int)cand.size(); ++k) times_us[k] = mean_us[k];
+  rc = pme_set_tuning(p, &cand[kb]);
+  if (rc == PME_OK) rc = pme_step(p, pos, q, N, box, forces, 0, ev);
+  if (rc == PME_OK && hipStreamSynchronize(p->stream) != hipSuccess) rc = PME_EDEVICE;
+  if (best) *best = cand[kb];
+  if (best_us) *best_us = mean_us[kb];
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batch admission: resident systems inside one caller-owned arena.
+// ---------------------------------------------------------------------------
+struct pme_batch {
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+  std::map<size_t, size_t> free_ranges;  // offset -> bytes, disjoint, merged
+  struct Slot {
+    pme_plan* plan = nullptr;
+    size_t off = 0, bytes = 0;
+    double *pos = nullptr, *q = nullptr, *forces = nullptr, *ev = nullptr;
+    bool owned_io = false;  // buffers carved from the slot's arena range
+  };
+  std::vector<Slot> slots;  // plan == nullptr: free
+  Fork fork;
+  size_t used = 0;
+};
+
+namespace {
+
+constexpr int kForkStreams = 3;  // with the batch's own stream: the box's four hardware queues
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Inputs and outputs carved from the arena: pos [n][3], q [n], forces [n][3],
+// ev [7], each 256-byte aligned.
+size_t io_bytes(int n) {
+  const size_t m = (size_t)std::max(n, 0);
+  return align_up(m * 24) + align_up(m * 8) + align_up(m * 24) + align_up(7 * 8);
+}
+
+// First fit over the free ranges; SIZE_MAX when nothing fits.
+size_t arena_take(pme_batch* b, size_t bytes) {
+  for (auto it = b->free_ranges.begin(); it != b->free_ranges.end(); ++it) {
+    if (it->second >= bytes) {
+      const size_t off = it->first, rest = it->second - bytes;
+      b->free_ranges.erase(it);
+      if (rest > 0) b->free_ranges[off + bytes] = rest;
+      b->used += bytes;
+      return off;
+    }
+  }
+  return SIZE_MAX;
+}
+
+// Returns a range, merged with the free ranges on either side.
+void arena_give(pme_batch* b, size_t off, size_t bytes) {
+  b->used -= bytes;
+  auto next = b->free_ranges.lower_bound(off);
+  if (next != b->free_ranges.end() && off + bytes == next->first) {
+    bytes += next->second;
+    next = b->free_ranges.erase(next);
+  }
+  if (next != b->free_ranges.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += bytes;
+      return;
+    }
+  }
+  b->free_ranges[off] = bytes;
+}
+
+// The fork streams and events of a batch, created at its first admission
+// (creating a batch touches no device).
+bool fork_ready(pme_batch* b) {
+  if (b->fork.start != nullptr) return true;
+  hipEvent_t start = nullptr;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) return false;
+  for (int f = 0; f < kForkStreams; ++f) {
+    hipStream_t fs = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&fs, hipStreamNonBlocking) != hipSuccess) break;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(fs);
+      break;
+    }
+    b->fork.streams.push_back(fs);
+    b->fork.joined.push_back(ev);
+  }
+  if ((int)b->fork.streams.size() < kForkStreams) {
+    for (hipStream_t fs : b->fork.streams) (void)hipStreamDestroy(fs);
+    for (hipEvent_t ev : b->fork.joined) (void)hipEventDestroy(ev);
+    b->fork.streams.clear();
+    b->fork.joined.clear();
+    (void)hipEventDestroy(start);
+    return false;
+  }
+  b->fork.start = start;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pme_batch_footprint(const pme_system_desc* s) {
+  if (s == nullptr) return 0;
+  const size_t ws =
+      align_up(pme_workspace_bytes(s->K1, s->K2, s->K3, s->order, s->max_atoms, s->precision));
+  if (ws == 0) return 0;
+  return s->pos != nullptr ? ws : ws + io_bytes(s->max_atoms);
+}
+
+int pme_batch_create(pme_batch** out, int max_systems, void* arena, size_t arena_bytes,
+                     void* stream) {
+  if (out == nullptr) return PME_EINVAL;
+  *out = nullptr;
+  if (max_systems < 1 || max_systems > 4096) return PME_EINVAL;
+  if (arena == nullptr || (reinterpret_cast<uintptr_t>(arena) & 255u) != 0 || arena_bytes < 256)
+    return PME_EWORKSPACE;
+  pme_batch* b = new (std::nothrow) pme_batch();
+  if (b == nullptr) return PME_EDEVICE;
+  b->arena = static_cast<char*>(arena);
+  b->arena_bytes = arena_bytes & ~(size_t)255;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->free_ranges[0] = b->arena_bytes;
+  b->slots.resize((size_t)max_systems);
+  *out = b;
+  return PME_OK;
+}
+
+int pme_batch_destroy(pme_batch* b) {
+  if (b == nullptr) return PME_EINVAL;
+  for (auto& sl : b->slots)
+    if (sl.plan != nullptr) pme_destroy(sl.plan);
+  for (hipStream_t fs : b->fork.streams) (void)hipStreamDestroy(fs);
+  for (hipEvent_t ev : b->fork.joined) (void)hipEventDestroy(ev);
+  if (b->fork.start) (void)hipEventDestroy(b->fork.start);
+  delete b;
+  return PME_OK;
+}
+
+int pme_batch_admit(pme_batch* b, const pme_system_desc* s, int* slot) {
+  if (b == nullptr || s == nullptr || slot == nullptr) return PME_EINVAL;
+  *slot = -1;
+  const size_t need = pme_batch_footprint(s);
+  if (need == 0) {
+    // an argument error or an unsupported shape, as pme_create reports it
+    const bool bad = s->max_atoms < 0 || s->K1 < 2 || s->K2 < 2 || s->K3 < 2 || s->order < 3;
+    return bad ? PME_EINVAL : PME_EUNSUPPORTED;
+  }
+  int free_slot = -1;
+  for (size_t k = 0; k < b->slots.size(); ++k)
+    if (b->slots[k].plan == nullptr) {
+      free_slot = (int)k;
+      break;
+    }
+  if (free_slot < 0) return PME_EBUSY;
+  const size_t off = arena_take(b, need);
+  if (off == SIZE_MAX) return PME_EBUSY;
+  if (!fork_ready(b)) {
+    arena_give(b, off, need);
+    return PME_EDEVICE;
+  }
+  pme_batch::Slot sl;
+  sl.off = off;
+  sl.bytes = need;
+  sl.owned_io = s->pos == nullptr;
+  size_t ws_bytes = need;
+  if (sl.owned_io) {
+    if (s->q != nullptr || s->forces != nullptr || s->ev != nullptr) {
+      arena_give(b, off, need);
+      return PME_EINVAL;
+    }
+    const size_t m = (size_t)std::max(s->max_atoms, 0);
+    ws_bytes = need - io_bytes(s->max_atoms);
+    char* io = b->arena + off + ws_bytes;
+    sl.pos = reinterpret_cast<double*>(io);
+    sl.q = reinterpret_cast<double*>(io + align_up(m * 24));
+    sl.forces = reinterpret_cast<double*>(io + align_up(m * 24) + align_up(m * 8));
+    sl.ev = reinterpret_cast<double*>(io + align_up(m * 24) + align_up(m * 8) + align_up(m * 24));
+  } else {
+    sl.pos = const_cast<double*>(s->pos);
+    sl.q = const_cast<double*>(s->q);
+    sl.forces = s->forces;
+    sl.ev = s->ev;
+  }
+  int rc = pme_create(&sl.plan, s->K1, s->K2, s->K3, s->order, s->beta, s->max_atoms,
+                      s->precision, 0, 0.0, b->arena + off, ws_bytes, b->stream);
+  if (rc == PME_OK) {
+    rc = pme_bind(sl.plan, sl.pos, sl.q, s->N, s->box, sl.forces, 0, sl.ev);
+    if (rc != PME_OK) pme_destroy(sl.plan);
+  }
+  if (rc != PME_OK) {
+    arena_give(b, off, need);
+    return rc;
+  }
+  b->slots[(size_t)free_slot] = sl;
+  *slot = free_slot;
+  return PME_OK;
+}
+
+int pme_batch_update(pme_batch* b, int slot, const double* pos, const double* q, int N,
+                     const double box[9], double* forces, double* ev) {
+  pme_plan* p = pme_batch_plan(b, slot);
+  if (p == nullptr) return PME_EINVAL;
+  pme_batch::Slot& sl = b->slots[(size_t)slot];
+  if (sl.owned_io) {
+    // the carved buffers stay; only N and the box change
+    if (pos != nullptr || q != nullptr || forces != nullptr || ev != nullptr) return PME_EINVAL;
+    return pme_bind(p, sl.pos, sl.q, N, box, sl.forces, 0, sl.ev);
+  }
+  const int rc = pme_bind(p, pos, q, N, box, forces, 0, ev);
+  if (rc == PME_OK) {
+    sl.pos = const_cast<double*>(pos);
+    sl.q = const_cast<double*>(q);
+    sl.forces = forces;
+    sl.ev = ev;
+  }
+  return rc;
+}
+
+int pme_batch_io(pme_batch* b, int slot, double** pos, double** q, double** forces, double** ev) {
+  if (pme_batch_plan(b, slot) == nullptr) return PME_EINVAL;
+  const pme_batch::Slot& sl = b->slots[(size_t)slot];
+  if (pos) *pos = sl.pos;
+  if (q) *q = sl.q;
+  if (forces) *forces = sl.forces;
+  if (ev) *ev = sl.ev;
+  return PME_OK;
+}
+
+int pme_batch_retire(pme_batch* b, int slot) {
+  pme_plan* p = pme_batch_plan(b, slot);
+  if (p == nullptr) return PME_EINVAL;
+  pme_batch::Slot& sl = b->slots[(size_t)slot];
+  pme_destroy(p);
+  // the range is reused only by launches enqueued later on the same stream
+  arena_give(b, sl.off, sl.bytes);
+  sl = pme_batch::Slot{};
+  return PME_OK;
+}
+
+int pme_batch_launch(pme_batch* b, const int* slots, int n) {
+  if (b == nullptr || (slots != nullptr && n < 0)) return PME_EINVAL;
+  std::vector<pme_plan*> plans;
+  if (slots == nullptr) {
+    for (auto& sl : b->slots)
+      if (sl.plan != nullptr) plans.push_back(sl.plan);
+  } else {
+    for (int k = 0; k < n; ++k) {
+      pme_plan* p = pme_batch_plan(b, slots[k]);
+      if (p == nullptr) return PME_EINVAL;
+      plans.push_back(p);
+    }
+  }
+  if (plans.empty()) return PME_OK;
+  return batch_run_impl(plans.data(), (int)plans.size(), b->stream,
+                        b->fork.start != nullptr ? &b->fork : nullptr);
+}
+
+int pme_batch_stats(pme_batch* b, int* admitted, size_t* bytes_used, size_t* largest_free) {
+  if (b == nullptr) return PME_EINVAL;
+  int n = 0;
+  for (auto& sl : b->slots) n += sl.plan != nullptr ? 1 : 0;
+  size_t lf = 0;
+  for (auto& fr : b->free_ranges) lf = std::max(lf, fr.second);
+  if (admitted) *admitted = n;
+  if (bytes_used) *bytes_used = b->used;
+  if (largest_free) *largest_free = lf;
+  return PME_OK;
+}
+
+pme_plan* pme_batch_plan(pme_batch* b, int slot) {
+  if (b == nullptr || slot < 0 || (size_t)slot >= b->slots.size()) return nullptr;
+  return b->slots[(size_t)slot].plan;
 }
 
 }  // extern "C"

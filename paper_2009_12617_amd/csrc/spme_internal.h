@@ -7,8 +7,8 @@
 
 namespace spme {
 
-constexpr int kChunk = 1024;         // atoms per binning workgroup
-constexpr int kBinThreads = 1024;    // one atom per thread
+constexpr int kBinThreads = 1024;    // largest binning chunk (one atom per thread)
+constexpr int kMinChunk = 256;       // smallest binning chunk
 constexpr int kMaxBins = 2048;       // (z, y slice, head/body) bins: 2 K3 nq <= 2048
 constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
 constexpr int kPlaneThreads = 512;   // one z-plane per workgroup (debug potential copy)
@@ -60,7 +60,7 @@ struct Layout {
   size_t bcnt;     // unsigned[2 K3 nq]: atoms binned so far per bucket (zero between steps)
   size_t bcnt2;    // unsigned[2 K3 nq]: this step's counts, kept for the interpolation
   size_t ovf;      // unsigned[4]: [0] overflow records so far, [1] this step's, kept
-  size_t absq;     // double[n_chunks]: sum |q| per chunk (fixed-point headroom)
+  size_t absq;     // double[n_chunks_max]: sum |q| per binning chunk (fixed-point headroom)
   size_t rec;      // records [2 K3 nq][cap] (RecF or RecD): one bucket per bin
   size_t orec;     // records [max_atoms]: atoms that found their bucket full
   size_t spec;     // complex[K1/2+1][K3][K2] half spectrum, columns [x'][z][y]
@@ -74,7 +74,7 @@ struct Layout {
   int n_chunks_max;
   int cap;          // records per bucket
   int orec_max;     // overflow records (max_atoms)
-  int partial_rows;  // energy/virial rows: one per wavefront of the convolution
+  int partial_rows;  // energy/virial rows: one per wavefront of the convolution (largest variant)
   int phi_pitch;
 };
 
@@ -84,6 +84,10 @@ struct Args {
   int N, n_chunks;
   int accumulate, keep_grid;
   int reduce_ev;  // the last launch's extra workgroup adds the energy/virial rows
+  int conv_mode;    // kConvFused or kConvSplit
+  int interp_mode;  // kInterpFused or kInterpSplit
+  int bin_chunk;    // atoms per binning workgroup (kMinChunk .. kBinThreads, a multiple of 64)
+  int ev_rows;      // energy/virial rows the convolution variant writes (from row 0)
   int triclinic;     // 0: diagonal box (L, invL); 1: general cell (rec)
   double L[3], invL[3];
   double rec[9];     // rec[3a + c]: component c of reciprocal vector a*_a
@@ -104,13 +108,44 @@ struct BatchArgs {
   const Args* sys[kMaxBatch];
 };
 
+// Variants of the y/z convolution and of the interpolation (a plan's
+// tuning picks one of each among those its shape supports).
+constexpr int kConvFused = 0;    // one workgroup per x' column, all y/z work in LDS
+constexpr int kConvSplit = 1;    // three launches of row-chunk workgroups
+constexpr int kInterpFused = 0;  // inverse x transform of a bin's rows + interpolation, one launch
+constexpr int kInterpSplit = 1;  // inverse x transform per plane, then a gather launch
+constexpr unsigned kVarConvFused = 1u, kVarConvSplit = 2u, kVarInterpFused = 4u,
+                   kVarInterpSplit = 8u;
+
 // Optional events attached to one kernel dispatch (both null: untimed).
 struct Timing {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
+using LaunchFn = hipError_t (*)(const Args&, hipStream_t, const Timing&, const BatchArgs*);
+
+// Launch table of one precision: its kernels are compiled in a translation
+// unit of their own (spme_kern_<precision>.hip).
+struct PrecOps {
+  hipError_t (*prepare)(int K1, int K2, int K3, int order);  // dynamic-LDS limits
+  unsigned (*variants)(int K1, int K2, int K3, int order);   // kVar* bits
+  LaunchFn bin, spread_x, conv, inv_x, interp;
+#ifdef SPME_TRACE
+  hipError_t (*trace_set)(void* buf);
+#endif
+};
+extern const PrecOps kOpsFixed, kOpsHalf, kOpsBf16, kOpsDouble;
+const PrecOps* prec_ops(int precision);  // null for an unknown precision
+
 bool grid_supported(int K1, int K2, int K3);
+// Variants available to a plan (kVar* bits; 0 when unsupported), and the
+// built-in choice of each.
+unsigned variants_for(int K1, int K2, int K3, int order, int precision);
+void default_variants(int K1, int K2, int K3, int order, int precision, int* conv_mode,
+                      int* interp_mode);
 bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision, Layout* lay);
+// Energy/virial rows a convolution variant writes (0 when unsupported).
+int ev_rows_for(int K1, int K2, int K3, int precision, int conv_mode);
 
 // Raise dynamic-LDS limits of the kernels a plan will launch.
 hipError_t prepare_kernels(int K1, int K2, int K3, int order, int precision);
@@ -128,5 +163,13 @@ hipError_t launch_interp(const Args& a, hipStream_t s, const Timing& t = Timing(
                          const BatchArgs* bt = nullptr);
 hipError_t launch_clear_counts(const Args& a, hipStream_t s);
 hipError_t launch_clear_flags(const Args& a, hipStream_t s);
+
+// Plan initialisation on the device: mp[k] = M_p(k + 1), k <= p - 2.
+struct PlanInit {
+  double mp[8];
+};
+hipError_t launch_init_plan(const Args& a, const PlanInit& in, hipStream_t s);
+// Stream-ordered write of a system's arguments to their device copy.
+hipError_t launch_store_args(const Args& a, Args* dst, hipStream_t s);
 
 }  // namespace spme

@@ -10,7 +10,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PME_FP32_FIXED, PME_FP32_FIXED_BF16, PME_FP32_FIXED_HALF, PME_FP64, check
+from ._lib import (PME_EBUSY, PME_FP32_FIXED, PME_FP32_FIXED_BF16, PME_FP32_FIXED_HALF, PME_FP64,
+                   SystemDesc, Tuning, check)
 
 KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "interpolate")
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64,
@@ -171,6 +172,52 @@ class Plan:
         self._n = n
         return forces, ev
 
+    # -- kernel variants ------------------------------------------------------
+    @property
+    def tuning(self):
+        """The plan's kernel variants: {"conv", "interp", "bin_chunk"}."""
+        t = Tuning()
+        check(self._lib.pme_get_tuning(self._h, ctypes.byref(t)), "pme_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, conv=None, interp=None, bin_chunk=None):
+        cur = self.tuning
+        t = Tuning(cur["conv"] if conv is None else int(conv),
+                   cur["interp"] if interp is None else int(interp),
+                   cur["bin_chunk"] if bin_chunk is None else int(bin_chunk))
+        check(self._lib.pme_set_tuning(self._h, ctypes.byref(t)), "pme_set_tuning")
+
+    def variants(self):
+        """PME_VAR_* bits of the variants this plan's shape can run."""
+        prec = PRECISIONS[self.precision]
+        return int(self._lib.pme_tuning_variants(*self.grid, self.order, prec))
+
+    def autotune(self, pos, q, box, reps=20, forces=None, ev=None):
+        """Measure every supported variant on these inputs (pme_autotune) and
+        keep the fastest.  Returns {"best": tuning, "us": best us/step,
+        "candidates": [(tuning, us or None), ...]}."""
+        n = int(q.shape[0])
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        if ev is None:
+            ev = torch.empty(7, dtype=torch.float64, device=self.device)
+        _dev_f64(forces, (n, 3), "forces")
+        _dev_f64(ev, (7,), "ev")
+        best = Tuning()
+        best_us = ctypes.c_double(0.0)
+        times = (ctypes.c_double * len(TUNE_CANDIDATES))()
+        self._keep = (pos, q)
+        self._n = n
+        check(self._lib.pme_autotune(self._h, pos.data_ptr(), q.data_ptr(), n, _box9(box),
+                                     forces.data_ptr(), ev.data_ptr(), int(reps), ctypes.byref(best),
+                                     ctypes.byref(best_us), times, len(TUNE_CANDIDATES)),
+              "pme_autotune")
+        cands = [(dict(c), (None if times[i] < 0 else float(times[i])))
+                 for i, c in enumerate(TUNE_CANDIDATES)]
+        return {"best": best.as_dict(), "us": float(best_us.value), "candidates": cands}
+
     # -- inspection -----------------------------------------------------------
     def set_debug(self, keep_charge_grid=True):
         check(self._lib.pme_set_debug(self._h, int(bool(keep_charge_grid))), "pme_set_debug")
@@ -222,6 +269,11 @@ class Plan:
         return dict(zip(KERNEL_NAMES, list(ms))), int(steps.value)
 
 
+# Candidate order of pme_autotune: conv x interp x bin_chunk, bin_chunk fastest.
+TUNE_CANDIDATES = tuple({"conv": c, "interp": i, "bin_chunk": b}
+                        for c in (0, 1) for i in (0, 1) for b in (256, 512, 1024))
+
+
 class Batch:
     """One step of many bound plans per run: plans that share precision, grid
     and spline order share every kernel launch (pme_batch_run)."""
@@ -239,3 +291,123 @@ class Batch:
         st = stream or self.stream or torch.cuda.current_stream()
         check(self._lib.pme_batch_run(self._handles, len(self.plans), ctypes.c_void_p(st.cuda_stream)),
               "pme_batch_run")
+
+
+class BatchPool:
+    """Resident systems in one device arena (pme_batch_*): admission by
+    footprint, a slot per system, one step of any set of slots per launch.
+
+    Each admitted system owns device buffers carved from the arena
+    (positions, charges, forces, energy/virial) unless the caller passes its
+    own tensors.  All work is enqueued on `stream`."""
+
+    def __init__(self, arena_bytes, max_systems=256, device=None, stream=None):
+        self._lib = _lib.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.arena_bytes = int(arena_bytes)
+        self._arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self._arena.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(self._lib.pme_batch_create(ctypes.byref(h), int(max_systems), base, self.arena_bytes,
+                                         ctypes.c_void_p(self.stream.cuda_stream)),
+              "pme_batch_create")
+        self._h = h
+        self._io = {}    # slot -> (pos, q, forces, ev) tensors
+        self._keep = {}  # slot -> caller tensors kept alive
+
+    @staticmethod
+    def desc(K, order, beta, max_atoms, precision="fp32_fixed", box=None, n=None):
+        d = SystemDesc()
+        d.K1, d.K2, d.K3 = grid3(K)
+        d.order, d.beta = int(order), float(beta)
+        d.precision = PRECISIONS[precision]
+        d.max_atoms = int(max_atoms)
+        d.N = int(max_atoms if n is None else n)
+        b = np.eye(3) if box is None else np.asarray(box, dtype=np.float64)
+        if b.shape == (3,):
+            b = np.diag(b)
+        d.box[:] = [float(v) for v in b.reshape(9)]
+        return d
+
+    @staticmethod
+    def footprint(K, order, max_atoms, precision="fp32_fixed", own_buffers=True):
+        """Arena bytes a system takes (with its buffers carved from the arena
+        when own_buffers)."""
+        d = BatchPool.desc(K, order, 1.0, max_atoms, precision)
+        if not own_buffers:
+            d.pos = 1  # any non-NULL pointer: the caller's buffers
+        return int(_lib.load().pme_batch_footprint(ctypes.byref(d)))
+
+    def admit(self, K, order, beta, box, max_atoms, n=None, precision="fp32_fixed"):
+        """Admit a system with arena-carved buffers; returns the slot, or None
+        when no slot or arena range is free (PME_EBUSY)."""
+        d = self.desc(K, order, beta, max_atoms, precision, box, n)
+        slot = ctypes.c_int(-1)
+        rc = self._lib.pme_batch_admit(self._h, ctypes.byref(d), ctypes.byref(slot))
+        if rc == PME_EBUSY:
+            return None
+        check(rc, "pme_batch_admit")
+        s = int(slot.value)
+        self._io[s] = self._wrap_io(s, int(max_atoms))
+        return s
+
+    def _wrap_io(self, slot, max_atoms):
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
+        check(self._lib.pme_batch_io(self._h, slot, *[ctypes.byref(p) for p in ptrs]), "pme_batch_io")
+        views = []
+        for p, shape in zip(ptrs, ((max_atoms, 3), (max_atoms,), (max_atoms, 3), (7,))):
+            off = p.value - self._arena.data_ptr()  # byte offset into the arena tensor
+            nel = int(np.prod(shape))
+            views.append(self._arena[off:off + 8 * nel].view(torch.float64).view(*shape))
+        return tuple(views)
+
+    def io(self, slot):
+        """(pos, q, forces, ev) device tensors of an admitted slot."""
+        return self._io[slot]
+
+    def update(self, slot, n, box):
+        """New atom count and box of a slot whose buffers live in the arena."""
+        check(self._lib.pme_batch_update(self._h, int(slot), None, None, int(n), _box9(box), None, None),
+              "pme_batch_update")
+
+    def retire(self, slot):
+        check(self._lib.pme_batch_retire(self._h, int(slot)), "pme_batch_retire")
+        self._io.pop(slot, None)
+        self._keep.pop(slot, None)
+
+    def launch(self, slots=None):
+        """One step of the listed slots (None: every admitted system)."""
+        if slots is None:
+            check(self._lib.pme_batch_launch(self._h, None, 0), "pme_batch_launch")
+            return
+        arr = (ctypes.c_int * len(slots))(*[int(s) for s in slots])
+        check(self._lib.pme_batch_launch(self._h, arr, len(slots)), "pme_batch_launch")
+
+    def stats(self):
+        n = ctypes.c_int(0)
+        used = ctypes.c_size_t(0)
+        lf = ctypes.c_size_t(0)
+        check(self._lib.pme_batch_stats(self._h, ctypes.byref(n), ctypes.byref(used), ctypes.byref(lf)),
+              "pme_batch_stats")
+        return {"admitted": int(n.value), "bytes_used": int(used.value), "largest_free": int(lf.value)}
+
+    def check(self, slot):
+        """Synchronise; the sticky device flags of a slot's plan (cleared)."""
+        h = self._lib.pme_batch_plan(self._h, int(slot))
+        if not h:
+            raise ValueError(f"slot {slot} is not admitted")
+        flags = ctypes.c_uint(0)
+        self._lib.pme_check(ctypes.c_void_p(h), ctypes.byref(flags))
+        return int(flags.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pme_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,6 +8,7 @@ import torch
 
 from . import _lib
 from ._lib import check
+from .plan import _dev_f64
 
 
 class RealSpace:
@@ -26,6 +27,7 @@ class RealSpace:
         self._raw = raw
         self._ws = raw[off:off + nbytes]
         self._nbytes = nbytes
+        self._excl_ok = None  # exclusion tensors last checked
 
     def __call__(self, pos, q, box, beta, rcut, exclusions=None, coulomb=1.0, forces=None,
                  accumulate=False, stream=None):
@@ -33,18 +35,34 @@ class RealSpace:
         exclusions: (offsets [N+1], partners) int32 device tensors or None.
         Returns (forces [N,3], energies [3] = E_real, E_self, E_excl)."""
         n = int(q.shape[0])
-        if pos.dtype != torch.float64 or q.dtype != torch.float64 or not pos.is_contiguous():
-            raise TypeError("pos and q must be contiguous float64 device tensors")
+        if n > self.max_atoms:
+            raise ValueError(f"{n} atoms exceed this workspace's max_atoms={self.max_atoms}")
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
         if forces is None:
             forces = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _dev_f64(forces, (n, 3), "forces")
         energies = torch.empty(3, dtype=torch.float64, device=self.device)
         b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(9))
         bp = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         off = idx = None
         if exclusions is not None:
             off, idx = exclusions
-            if off.dtype != torch.int32 or idx.dtype != torch.int32 or off.shape[0] != n + 1:
-                raise TypeError("exclusions must be int32 device tensors, offsets of length N+1")
+            for t, name in ((off, "exclusion offsets"), (idx, "exclusion partners")):
+                if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 \
+                        or t.dim() != 1 or not t.is_contiguous():
+                    raise TypeError(f"{name} must be a contiguous 1-D int32 GPU tensor")
+            if off.shape[0] != n + 1:
+                raise ValueError("exclusion offsets must have length N+1")
+            # the partner list must hold exactly the entries the offsets index
+            # (the kernels read off[0..N]); checked with one host read per
+            # pair of tensors and contents, then remembered
+            key = (off.data_ptr(), idx.data_ptr(), idx.numel(), off._version, idx._version)
+            if key != self._excl_ok:
+                ends = off[[0, -1]].cpu()
+                if int(ends[0]) != 0 or int(ends[1]) != idx.numel():
+                    raise ValueError("exclusion offsets must start at 0 and end at len(partners)")
+                self._excl_ok = key
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         check(self._lib.pme_real(pos.data_ptr(), q.data_ptr(), n, bp, float(beta), float(rcut),
                                  float(coulomb), off.data_ptr() if off is not None else None,

@@ -1,15 +1,20 @@
 """Continuous-batching request loop for SPME solves of differing sizes.
 
-Requests (a system of the pool and an arrival time) are admitted into
-resident slots -- a plan with its workspace and device buffers -- while the
-device memory they hold stays within an HBM budget; a slot is kept after its
-request completes and reused by the next request for the same system.  Each
-tick launches every staged request (inputs already copied to the device) as
-one batched run (pme_batch_run) on the compute stream, while copies run on a
-separate stream and earlier ticks may still be executing: requests that
-arrive while others are on the GPU join the next tick.  Latency is the host
-time from a request's scheduled arrival to the moment its forces and energy
-are in host memory.
+Requests (a system of the pool and an arrival time) are served from
+resident slots of one device arena (BatchPool over the C batch API,
+pme_batch_*): a slot holds a system's plan workspace and its input/output
+buffers, admitted by footprint (PME_EBUSY when the arena has no free
+range), kept after its request completes and reused by the next request for
+the same system; idle slots of other systems are retired, least recently
+used first, when a new system needs room.  Slots for the pool are admitted
+before the clock starts where the arena holds them (resident grids).  Each
+tick launches every request whose input has reached the device as one
+batched step of their slots on the compute stream (pme_batch_launch: one
+launch per kernel and grid group, the groups on forked streams), while
+copies run on a separate stream and earlier ticks may still be executing:
+requests that arrive while others are on the GPU join the next tick.
+Latency is the host time from a request's scheduled arrival to the moment
+its forces and energy are in host memory.
 """
 from dataclasses import dataclass, field
 import time
@@ -17,7 +22,7 @@ import time
 import numpy as np
 import torch
 
-from .plan import Batch, Plan
+from .plan import BatchPool
 
 
 @dataclass
@@ -32,32 +37,20 @@ class PoolSystem:
 
 
 class Slot:
-    """A resident solver for one pool system."""
+    """A resident system: its batch slot, device buffers and pinned host
+    buffers for the results."""
 
-    def __init__(self, system_id, sysd, precision, device):
+    def __init__(self, system_id, slot, pool, sysd, footprint):
         n = len(sysd.q)
         self.system_id = system_id
-        self.plan = Plan(sysd.K, sysd.order, sysd.beta, max_atoms=n, precision=precision,
-                         device=device)
-        self.pos = torch.empty((n, 3), dtype=torch.float64, device=device)
-        self.q = torch.from_numpy(np.ascontiguousarray(sysd.q)).to(device)
-        self.forces, self.ev = self.plan.bind(self.pos, self.q, sysd.box)
+        self.slot = slot
+        self.pos, self.q, self.forces, self.ev = pool.io(slot)
+        self.q.copy_(torch.from_numpy(np.ascontiguousarray(sysd.q)), non_blocking=False)
         self.host_f = torch.empty((n, 3), dtype=torch.float64, pin_memory=True)
         self.host_ev = torch.empty(7, dtype=torch.float64, pin_memory=True)
-        self.footprint = slot_footprint(sysd, precision)
+        self.footprint = footprint
         self.busy = False
         self.last_used = 0.0
-
-    def release(self):
-        self.plan.close()
-        self.plan = self.pos = self.q = self.forces = self.ev = None
-
-
-def slot_footprint(sysd, precision):
-    """Device bytes one resident slot holds: plan workspace and buffers."""
-    n = len(sysd.q)
-    return (Plan.workspace_bytes_for(sysd.K, sysd.order, n, precision) + 256
-            + n * 3 * 8 * 2 + n * 8 + 7 * 8)
 
 
 @dataclass
@@ -83,6 +76,7 @@ class ServeStats:
     peak_resident_bytes: int = 0
     peak_inflight: int = 0
     slots_created: int = 0
+    slots_prewarmed: int = 0
     rejected_for_budget: int = 0
     evictions: int = 0
 
@@ -100,66 +94,90 @@ class ServeStats:
             "ticks": len(self.batch_sizes),
             "peak_resident_bytes": int(self.peak_resident_bytes),
             "peak_inflight": int(self.peak_inflight),
-            "slots_created": int(self.slots_created),
+            "slots_prewarmed": int(self.slots_prewarmed),
+            "slots_created_while_serving": int(self.slots_created),
             "waits_for_budget": int(self.rejected_for_budget),
             "evictions": int(self.evictions),
         }
 
 
 class Server:
-    """Open-loop serving of SPME solves with admission by HBM footprint."""
+    """Open-loop serving of SPME solves with admission by device footprint."""
 
     def __init__(self, pool, hbm_budget_bytes, precision="fp32_fixed", max_batch=64,
-                 slots_per_system=2, device=None, keep_forces=False):
+                 slots_per_system=2, device=None, keep_forces=None, prewarm=True):
         self.pool = list(pool)
         self.budget = int(hbm_budget_bytes)
         self.precision = precision
         self.max_batch = int(max_batch)
         self.slots_per_system = int(slots_per_system)
         self.device = torch.device(device if device is not None else "cuda")
+        # keep_forces: None (keep none), True (keep all) or a predicate on the
+        # request id
         self.keep_forces = keep_forces
-        for i, p in enumerate(self.pool):
-            if slot_footprint(p, precision) > self.budget:
+        self.compute = torch.cuda.Stream(device=self.device)
+        self.copy = torch.cuda.Stream(device=self.device)
+        self.batch = BatchPool(self.budget, max_systems=max(64, 2 * len(self.pool)),
+                               device=self.device, stream=self.compute)
+        self.fp = [self.batch.footprint(p.K, p.order, len(p.q), precision) for p in self.pool]
+        for i, f in enumerate(self.fp):
+            if f == 0 or f > self.budget:
                 raise ValueError(f"pool system {i} needs more device memory than the budget")
         self.slots = {i: [] for i in range(len(self.pool))}
         # request payloads: the inputs a client hands over, in pinned host memory
         self.inputs = [torch.from_numpy(np.ascontiguousarray(p.pos)).pin_memory() for p in self.pool]
         self.resident = 0
-        self.compute = torch.cuda.Stream(device=self.device)
-        self.copy = torch.cuda.Stream(device=self.device)
         self.stats = ServeStats()
+        if prewarm:
+            # one resident slot per pool system while the arena holds them
+            for i in range(len(self.pool)):
+                if self._new_slot(i, evict=False) is None:
+                    break
+                self.stats.slots_prewarmed += 1
+            torch.cuda.synchronize(self.device)
+            self.stats.slots_created = 0
 
     # -- admission ------------------------------------------------------------
-    def _free_slot(self, system_id, now):
-        for s in self.slots[system_id]:
-            if not s.busy:
-                return s
-        if len(self.slots[system_id]) >= self.slots_per_system:
-            return None
-        need = slot_footprint(self.pool[system_id], self.precision)
-        if self.resident + need > self.budget:
-            # evict idle slots of other systems, least recently used first
-            idle = [s for lst in self.slots.values() for s in lst if not s.busy]
-            idle.sort(key=lambda s: s.last_used)
-            for s in idle:
-                if self.resident + need <= self.budget:
+    def _new_slot(self, system_id, evict=True):
+        sysd = self.pool[system_id]
+        with torch.cuda.stream(self.compute):
+            slot = self.batch.admit(sysd.K, sysd.order, sysd.beta, sysd.box, len(sysd.q),
+                                    precision=self.precision)
+            while slot is None and evict:
+                # retire idle slots of other systems, least recently used first
+                idle = [s for lst in self.slots.values() for s in lst
+                        if not s.busy and s.system_id != system_id]
+                if not idle:
                     break
-                self.slots[s.system_id].remove(s)
-                self.resident -= s.footprint
-                s.release()
+                victim = min(idle, key=lambda s: s.last_used)
+                self.slots[victim.system_id].remove(victim)
+                self.batch.retire(victim.slot)
+                self.resident -= victim.footprint
                 self.stats.evictions += 1
-        if self.resident + need > self.budget:
-            self.stats.rejected_for_budget += 1
-            return None
-        s = Slot(system_id, self.pool[system_id], self.precision, self.device)
+                slot = self.batch.admit(sysd.K, sysd.order, sysd.beta, sysd.box, len(sysd.q),
+                                        precision=self.precision)
+            if slot is None:
+                return None
+            s = Slot(system_id, slot, self.batch, sysd, self.fp[system_id])
         self.slots[system_id].append(s)
         self.resident += s.footprint
         self.stats.slots_created += 1
         self.stats.peak_resident_bytes = max(self.stats.peak_resident_bytes, self.resident)
         return s
 
+    def _free_slot(self, system_id):
+        for s in self.slots[system_id]:
+            if not s.busy:
+                return s
+        if len(self.slots[system_id]) >= self.slots_per_system:
+            return None
+        s = self._new_slot(system_id)
+        if s is None:
+            self.stats.rejected_for_budget += 1
+        return s
+
     def _admit(self, req, now):
-        s = self._free_slot(req.system_id, now)
+        s = self._free_slot(req.system_id)
         if s is None:
             return False
         s.busy = True
@@ -171,6 +189,10 @@ class Server:
             req.h2d = torch.cuda.Event()
             req.h2d.record(self.copy)
         return True
+
+    def _keep(self, rid):
+        k = self.keep_forces
+        return bool(k(rid)) if callable(k) else bool(k)
 
     # -- the loop -------------------------------------------------------------
     def run(self, arrivals, system_ids, stall_s=30.0):
@@ -202,7 +224,7 @@ class Server:
             if ready:
                 ids = {id(r) for r in ready}
                 staged = [r for r in staged if id(r) not in ids]
-                Batch([r.slot.plan for r in ready]).run(self.compute)
+                self.batch.launch([r.slot.slot for r in ready])
                 ev = torch.cuda.Event()
                 ev.record(self.compute)
                 self.copy.wait_event(ev)
@@ -221,7 +243,7 @@ class Server:
                 if r.d2h.query():
                     r.done = time.perf_counter() - t0
                     r.energy = float(r.slot.host_ev[0])
-                    if self.keep_forces:
+                    if self._keep(r.rid):
                         r.forces = r.slot.host_f.numpy().copy()
                     r.slot.busy = False
                     r.slot.last_used = r.done
@@ -239,3 +261,6 @@ class Server:
         self.stats.wall_s = time.perf_counter() - t0
         self.stats.completed = len(done)
         return done
+
+    def close(self):
+        self.batch.close()

@@ -1,0 +1,153 @@
+"""Batch admission through the C ABI (pme_batch_*): systems admitted into one
+arena by footprint, their buffers carved from it, one launch over any set of
+slots with grid groups on forked streams; every result bit-identical to the
+system's own single step, under graph replay too; retire and re-admit reuse
+arena ranges; a full arena answers PME_EBUSY.  Also: pme_bind is
+stream-ordered (a rebind does not disturb a batched run enqueued before
+it)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2009_12617_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2009_12617_amd as pkg
+    return pkg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def single(P, m, pos, q, box):
+    plan = P.Plan(m.K, 4, 0.34, max_atoms=len(q))
+    f, e = plan.step(dev(pos), dev(q), box)
+    torch.cuda.synchronize()
+    return f.clone(), e.clone()
+
+
+def admit_all(P, pool, mix):
+    slots = []
+    for m in mix:
+        pos, q, box = m.make()
+        s = pool.admit(m.K, 4, 0.34, box, len(q))
+        assert s is not None
+        p, qq, f, e = pool.io(s)
+        p.copy_(dev(pos))
+        qq.copy_(dev(q))
+        slots.append((s, m, pos, q, box))
+    return slots
+
+
+def test_pool_matches_single_steps_and_graph(P):
+    mix = I.batch_mix(n_systems=10, seed=41, lo=600, hi=20000)
+    assert len({m.K for m in mix}) == 3  # three grid groups on the fork streams
+    stream = torch.cuda.Stream()
+    pool = P.BatchPool(1 << 30, max_systems=16, stream=stream)
+    with torch.cuda.stream(stream):
+        slots = admit_all(P, pool, mix)
+    st = pool.stats()
+    assert st["admitted"] == len(mix) and st["bytes_used"] == sum(
+        P.BatchPool.footprint(m.K, 4, len(q)) for _, m, _, q, _ in slots)
+    refs = [single(P, m, pos, q, box) for _, m, pos, q, box in slots]
+    pool.launch()
+    stream.synchronize()
+    for (s, m, *_), (fr, er) in zip(slots, refs):
+        _, _, f, e = pool.io(s)
+        assert torch.equal(f, fr) and torch.equal(e, er), m.index
+    # a subset of the slots, in another order
+    sub = [slots[k][0] for k in (7, 2, 5)]
+    for s in sub:
+        pool.io(s)[2].zero_()
+    torch.cuda.synchronize()
+    pool.launch(sub)
+    stream.synchronize()
+    for k in (7, 2, 5):
+        assert torch.equal(pool.io(slots[k][0])[2], refs[k][0])
+    # graph capture of a launch (fork/join over the grid groups), replayed
+    # with eager work in between; every replay equals the single steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        pool.launch()
+    for rep in range(3):
+        for s, *_ in slots:
+            pool.io(s)[2].fill_(float(rep))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (s, m, *_), (fr, er) in zip(slots, refs):
+            _, _, f, e = pool.io(s)
+            assert torch.equal(f, fr) and torch.equal(e, er), (rep, m.index)
+    with pytest.raises(RuntimeError):
+        pool.launch([slots[0][0], slots[0][0]])  # a slot twice
+    pool.close()
+
+
+def test_pool_busy_retire_readmit(P):
+    mix = I.batch_mix(n_systems=6, seed=5, lo=800, hi=5000)  # six 32^3 systems
+    fps = [P.BatchPool.footprint(m.K, 4, m.n_waters * 3) for m in mix]
+    arena = sum(fps[:3]) + 512
+    stream = torch.cuda.Stream()
+    pool = P.BatchPool(arena, max_systems=8, stream=stream)
+    with torch.cuda.stream(stream):
+        first = admit_all(P, pool, mix[:3])
+        m = mix[3]
+        pos, q, box = m.make()
+        if fps[3] > pool.stats()["largest_free"]:
+            assert pool.admit(m.K, 4, 0.34, box, len(q)) is None   # PME_EBUSY
+        # retire the middle system; an equal-sized one fits its range again
+        s_mid, m_mid, pos_mid, q_mid, box_mid = first[1]
+        pool.retire(s_mid)
+        assert pool.stats()["admitted"] == 2
+        s_new = pool.admit(m_mid.K, 4, 0.34, box_mid, len(q_mid))
+        assert s_new is not None
+        p, qq, _, _ = pool.io(s_new)
+        p.copy_(dev(pos_mid))
+        qq.copy_(dev(q_mid))
+        pool.launch()
+    stream.synchronize()
+    fr, er = single(P, m_mid, pos_mid, q_mid, box_mid)
+    assert torch.equal(pool.io(s_new)[2], fr) and torch.equal(pool.io(s_new)[3], er)
+    for s, mm, pos_, q_, box_ in (first[0], first[2]):
+        f2, e2 = single(P, mm, pos_, q_, box_)
+        assert torch.equal(pool.io(s)[2], f2) and torch.equal(pool.io(s)[3], e2)
+    # update: fewer atoms and a new box through the carved buffers
+    s0, m0, pos0, q0, box0 = first[0]
+    n = len(q0) - 3
+    with torch.cuda.stream(stream):
+        pool.update(s0, n, box0 * 1.01)
+        pool.launch([s0])
+    stream.synchronize()
+    f3, e3 = single(P, m0, pos0[:n], q0[:n], box0 * 1.01)
+    assert torch.equal(pool.io(s0)[2][:n], f3) and torch.equal(pool.io(s0)[3], e3)
+    assert pool.check(s0) == 0
+    pool.close()
+
+
+def test_bind_is_stream_ordered(P):
+    """Two bindings of one plan enqueued back to back on its stream, each
+    followed by a batched run: each run sees its own binding."""
+    m = I.batch_mix(n_systems=1, seed=3, lo=2000, hi=2001)[0]
+    pos, q, box = m.make()
+    pos2 = pos + 0.37
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan = P.Plan(m.K, 4, 0.34, max_atoms=len(q), stream=stream)
+        dp, dp2, dq = dev(pos), dev(pos2), dev(q)
+        fa = torch.empty((len(q), 3), dtype=torch.float64, device="cuda")
+        fb = torch.empty_like(fa)
+        plan.bind(dp, dq, box, forces=fa)
+        P.Batch([plan]).run(stream)
+        plan.bind(dp2, dq, box, forces=fb)
+        P.Batch([plan]).run(stream)
+    stream.synchronize()
+    ra, _ = single(P, m, pos, q, box)
+    rb, _ = single(P, m, pos2, q, box)
+    assert torch.equal(fa, ra) and torch.equal(fb, rb)

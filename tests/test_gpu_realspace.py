@@ -65,6 +65,53 @@ def test_real_space_matches_brute_force(P, with_excl, max_cells):
     assert e[2] == pytest.approx(want_excl, rel=1e-12, abs=1e-12)
 
 
+@pytest.mark.parametrize("edge,rcut", [(36.0, 6.0), (45.0, 7.5)])
+def test_real_space_dense_cells(P, edge, rcut):
+    # water density in a box whose 27-cell limit coarsens the cell grid to
+    # 3 x 3 x 3 cells of 12 A (about 170 atoms per cell: the 2-lane split of
+    # a home atom's candidates) and of 15 A (about 340 atoms per cell: more
+    # than 64 home atoms per pair workgroup, so its multi-pass loop runs),
+    # with the water exclusions, against the brute-force oracle
+    nw = int(round(edge ** 3 * I.WATER_DENSITY))
+    pos, q, box = I.water_box(nw, edge, 36)
+    beta = 0.34
+    rs = P.RealSpace(len(q), max_cells=27)
+    off, idx = I.water_exclusions(len(q))
+    f, e = rs(dev(pos), dev(q), box, beta, rcut, exclusions=(dev(off, np.int32), dev(idx, np.int32)))
+    f, e = f.cpu().numpy(), e.cpu().numpy()
+    w = np.mod(pos, edge)
+    ref = oracle.ewald_real(w, q, box, beta, nimg=1, rcut=rcut)
+    ex = oracle.ewald_excl(pos, q, box, beta, off, idx, rcut=rcut)
+    want = ref["forces"] + ex["forces"]
+    print(f"{len(q)} atoms, {len(q) / 27:.0f} per cell: force_rel_rms={rel_rms(f, want):.2e}", flush=True)
+    assert rel_rms(f, want) <= 1e-11
+    assert e[0] == pytest.approx(ref["E_real"], rel=1e-12)
+    assert e[2] == pytest.approx(ex["E_excl"], rel=1e-12)
+
+
+def test_real_space_rejects_bad_buffers(P):
+    pos, q, box = I.water_box(50, 12.0, 37)
+    rs = P.RealSpace(len(q))
+    dp, dq = dev(pos), dev(q)
+    with pytest.raises(TypeError):
+        rs(torch.from_numpy(pos), dq, box, 0.4, 3.9)                   # host tensor
+    with pytest.raises(ValueError):
+        rs(dp[:-1], dq, box, 0.4, 3.9)                                 # short positions
+    with pytest.raises(TypeError):
+        rs(dp, dq, box, 0.4, 3.9, forces=torch.zeros((len(q), 3), device="cuda"))  # float32
+    with pytest.raises(ValueError):
+        rs(dp, dq, box, 0.4, 3.9, forces=torch.zeros((len(q) - 1, 3), dtype=torch.float64,
+                                                      device="cuda"))
+    off, idx = I.water_exclusions(len(q))
+    with pytest.raises(TypeError):
+        rs(dp, dq, box, 0.4, 3.9, exclusions=(dev(off, np.int64), dev(idx, np.int32)))
+    with pytest.raises(ValueError):
+        rs(dp, dq, box, 0.4, 3.9, exclusions=(dev(off, np.int32), dev(idx[:-2], np.int32)))
+    big = P.RealSpace(10)
+    with pytest.raises(ValueError):
+        big(dp, dq, box, 0.4, 3.9)
+
+
 @pytest.mark.parametrize("beta", [0.05, 0.755])
 def test_real_space_screening_range(P, beta):
     # the erfc inside the cutoff comes from a Chebyshev series on

@@ -42,8 +42,7 @@ def test_serving_results_admission_and_overlap(P):
     arrivals = np.cumsum(rng.exponential(1.0 / 4000.0, size=n))
     ids = rng.integers(0, len(systems), size=n)
     # a budget for only a few resident slots forces requests to wait and reuse slots
-    from paper_2009_12617_amd.serve import slot_footprint
-    one = max(slot_footprint(s, "fp32_fixed") for s in systems)
+    one = max(P.BatchPool.footprint(s.K, s.order, len(s.q)) for s in systems)
     srv = Server(systems, hbm_budget_bytes=3 * one, max_batch=8, keep_forces=True)
     done = srv.run(arrivals, ids, stall_s=20.0)
     st = srv.stats.summary()
