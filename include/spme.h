@@ -404,6 +404,28 @@ int pme_real(const double *pos, const double *q, int N, const double box[9], dou
              double *forces, int accumulate, double *energies, void *workspace,
              size_t workspace_bytes, int max_atoms, int max_cells, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free step, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  One whole step (as pme_step on a plan with these parameters
+ * and its built-in variants) with the library's own static device scratch
+ * of PME_SCRATCH_BYTES per GPU in place of a caller workspace; nothing is
+ * allocated (no hipMalloc, no host heap) and nothing synchronises.
+ *   Size limit: pme_workspace_bytes(K1, K2, K3, order, N, precision) must
+ *   not exceed PME_SCRATCH_BYTES (about 16 MiB at 65,536 atoms on 64^3),
+ *   else PME_EWORKSPACE and nothing is enqueued.  Other arguments and
+ *   errors as pme_create (frac_bits, coulomb) and pme_step.
+ * Every call on one GPU uses that GPU's single scratch, which keeps the last
+ * call's contents (each call re-initialises what it reads before use):
+ * calls that overlap on one GPU -- on different streams, or from different
+ * threads -- race and must be ordered by the caller.  The sticky device
+ * flags of pme_check are not reported. */
+#define PME_SCRATCH_BYTES ((size_t)32 << 20)
+int pme_step_noalloc(int K1, int K2, int K3, int order, double beta, int precision,
+                     int frac_bits, double coulomb, const double *pos, const double *q, int N,
+                     const double box[9], double *forces, int accumulate, double *ev,
+                     void *stream);
+
 /* Human-readable text for a pme_status. */
 const char *pme_strerror(int code);
 

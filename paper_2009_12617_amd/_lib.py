@@ -20,6 +20,7 @@ PME_FLAG_OVERFLOW = 2
 PME_FLAG_BUCKETS = 4
 
 PME_EBUSY = 8
+PME_SCRATCH_BYTES = 32 << 20  # static scratch of pme_step_noalloc (include/spme.h)
 PME_CONV_FUSED, PME_CONV_SPLIT = 0, 1
 PME_INTERP_FUSED, PME_INTERP_SPLIT = 0, 1
 PME_VAR_CONV_FUSED, PME_VAR_CONV_SPLIT, PME_VAR_INTERP_FUSED, PME_VAR_INTERP_SPLIT = 1, 2, 4, 8
@@ -145,6 +146,8 @@ def load():
     lib.pme_batch_stats.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.pme_batch_plan.restype = vp
     lib.pme_batch_plan.argtypes = [vp, i]
+    lib.pme_step_noalloc.restype = i
+    lib.pme_step_noalloc.argtypes = [i, i, i, i, d, i, i, d, vp, vp, i, dp, vp, i, vp, vp]
     _lib = lib
     return lib
 

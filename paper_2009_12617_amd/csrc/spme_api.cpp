@@ -106,19 +106,81 @@ void apply_tuning(pme_plan* p, Args& a) {
 
 // Raises the dynamic-LDS limits of a (precision, grid, order)'s kernels once
 // per process and device (hipFuncSetAttribute is a host call of its own per
-// kernel; plans are created in serving loops).
+// kernel; plans are created in serving loops).  A fixed table, so that the
+// allocation-free step allocates no host memory either.
 hipError_t prepare_kernels_once(int K1, int K2, int K3, int order, int precision) {
   static std::mutex mu;
-  static std::set<std::array<int, 6>> done;
+  static std::array<std::array<int, 6>, 256> done;
+  static int ndone = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   const std::array<int, 6> key{dev, K1, K2, K3, order, precision};
   std::lock_guard<std::mutex> lock(mu);
-  if (done.count(key)) return hipSuccess;
+  for (int i = 0; i < ndone; ++i)
+    if (done[i] == key) return hipSuccess;
   e = spme::prepare_kernels(K1, K2, K3, order, precision);
-  if (e == hipSuccess) done.insert(key);
+  if (e == hipSuccess && ndone < (int)done.size()) done[ndone++] = key;
   return e;
+}
+
+// Fills a plan for (grid, order, beta, max_atoms, precision, F, c) over
+// `ws` and enqueues its initialisation launch on `stream`.  Arguments were
+// validated by the caller.
+int init_plan(pme_plan* p, int K1, int K2, int K3, int order, double beta, int max_atoms,
+              int precision, int frac_bits, double coulomb, char* ws, size_t ws_bytes,
+              hipStream_t stream, const Layout& L) {
+  p->K1 = K1;
+  p->K2 = K2;
+  p->K3 = K3;
+  p->order = order;
+  p->precision = precision;
+  p->frac_bits = frac_bits;
+  p->max_atoms = max_atoms;
+  p->beta = beta;
+  p->coulomb = coulomb;
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  p->stream = stream;
+  p->lay = L;
+  spme::default_variants(K1, K2, K3, order, precision, &p->conv_mode, &p->interp_mode);
+  Args& a = p->cur;
+  a.K1 = K1;
+  a.K2 = K2;
+  a.K3 = K3;
+  a.order = order;
+  a.precision = precision;
+  a.frac_bits = frac_bits;
+  a.beta = beta;
+  a.coulomb = coulomb;
+  a.ws = p->ws;
+  a.lay = L;
+  apply_tuning(p, a);
+  // the plan tables are computed on the device from M_p at the integers
+  spme::PlanInit init{};
+  for (int k = 0; k <= order - 2; ++k) init.mp[k] = bspline_at(order, k + 1.0);
+  hipError_t e = prepare_kernels_once(K1, K2, K3, order, precision);
+  if (e == hipSuccess) e = spme::launch_init_plan(a, init, p->stream);
+  return e == hipSuccess ? PME_OK : PME_EDEVICE;
+}
+
+// Argument checks shared by pme_create and the allocation-free step:
+// PME_OK with *L filled, or the status to return.
+int check_plan_args(int K1, int K2, int K3, int order, double beta, int max_atoms, int precision,
+                    int* frac_bits, double* coulomb, Layout* L) {
+  if (K1 < 2 || K2 < 2 || K3 < 2 || order < 3 || !(beta > 0.0) || !is_fin(beta) ||
+      max_atoms < 0 ||
+      (precision != PME_FP64 && precision != PME_FP32_FIXED && precision != PME_FP32_FIXED_HALF &&
+       precision != PME_FP32_FIXED_BF16) ||
+      !is_fin(*coulomb))
+    return PME_EINVAL;
+  if (*frac_bits == 0) *frac_bits = 32;
+  if (*frac_bits < 16 || *frac_bits > 40) return PME_EINVAL;
+  if (*coulomb == 0.0) *coulomb = 1.0;
+  if (!spme::grid_supported(K1, K2, K3) || (order != 4 && order != 6) || max_atoms > kMaxAtoms)
+    return PME_EUNSUPPORTED;
+  if (!spme::layout_for(K1, K2, K3, order, max_atoms, precision, L)) return PME_EUNSUPPORTED;
+  return PME_OK;
 }
 
 }  // namespace
@@ -154,64 +216,25 @@ int pme_create(pme_plan** out, int K1, int K2, int K3, int order, double beta, i
                size_t workspace_bytes, void* stream) {
   if (out == nullptr) return PME_EINVAL;
   *out = nullptr;
-  if (K1 < 2 || K2 < 2 || K3 < 2 || order < 3 || !(beta > 0.0) || !is_fin(beta) ||
-      max_atoms < 0 ||
-      (precision != PME_FP64 && precision != PME_FP32_FIXED && precision != PME_FP32_FIXED_HALF &&
-       precision != PME_FP32_FIXED_BF16) ||
-      !is_fin(coulomb))
-    return PME_EINVAL;
-  if (frac_bits == 0) frac_bits = 32;
-  if (frac_bits < 16 || frac_bits > 40) return PME_EINVAL;
-  if (coulomb == 0.0) coulomb = 1.0;
-  if (!spme::grid_supported(K1, K2, K3) || (order != 4 && order != 6) || max_atoms > kMaxAtoms)
-    return PME_EUNSUPPORTED;
   Layout L;
-  if (!spme::layout_for(K1, K2, K3, order, max_atoms, precision, &L)) return PME_EUNSUPPORTED;
+  const int rc = check_plan_args(K1, K2, K3, order, beta, max_atoms, precision, &frac_bits,
+                                 &coulomb, &L);
+  if (rc != PME_OK) return rc;
   if (workspace == nullptr || workspace_bytes < L.total ||
       (reinterpret_cast<uintptr_t>(workspace) & 255u) != 0)
     return PME_EWORKSPACE;
-
   pme_plan* p = new (std::nothrow) pme_plan();
   if (p == nullptr) return PME_EDEVICE;
-  p->K1 = K1;
-  p->K2 = K2;
-  p->K3 = K3;
-  p->order = order;
-  p->precision = precision;
-  p->frac_bits = frac_bits;
-  p->max_atoms = max_atoms;
-  p->beta = beta;
-  p->coulomb = coulomb;
-  p->ws = static_cast<char*>(workspace);
-  p->ws_bytes = workspace_bytes;
-  p->stream = static_cast<hipStream_t>(stream);
-  p->lay = L;
-
-  spme::default_variants(K1, K2, K3, order, precision, &p->conv_mode, &p->interp_mode);
-  Args& a = p->cur;
-  a.K1 = K1;
-  a.K2 = K2;
-  a.K3 = K3;
-  a.order = order;
-  a.precision = precision;
-  a.frac_bits = frac_bits;
-  a.beta = beta;
-  a.coulomb = coulomb;
-  a.ws = p->ws;
-  a.lay = L;
-  apply_tuning(p, a);
-  // the plan tables are computed on the device from M_p at the integers
-  spme::PlanInit init{};
-  for (int k = 0; k <= order - 2; ++k) init.mp[k] = bspline_at(order, k + 1.0);
-  hipError_t e = prepare_kernels_once(K1, K2, K3, order, precision);
-  if (e == hipSuccess) e = spme::launch_init_plan(a, init, p->stream);
-  if (e != hipSuccess) {
+  if (init_plan(p, K1, K2, K3, order, beta, max_atoms, precision, frac_bits, coulomb,
+                static_cast<char*>(workspace), workspace_bytes, static_cast<hipStream_t>(stream),
+                L) != PME_OK) {
     delete p;
     return PME_EDEVICE;
   }
   *out = p;
   return PME_OK;
 }
+
 int pme_destroy(pme_plan* p) {
   if (p == nullptr) return PME_EINVAL;
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
@@ -1024,3 +1047,59 @@ pme_plan* pme_batch_plan(pme_batch* b, int slot) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free step: the library's own static device scratch stands in
+// for the caller's workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = PME_SCRATCH_BYTES;
+// One copy per device, held until the process ends.  In host code this name
+// is only a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];
+
+hipError_t scratch_on_current_device(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int pme_step_noalloc(int K1, int K2, int K3, int order, double beta, int precision,
+                                int frac_bits, double coulomb, const double* pos, const double* q,
+                                int N, const double box[9], double* forces, int accumulate,
+                                double* ev, void* stream) {
+  Layout L;
+  int rc = check_plan_args(K1, K2, K3, order, beta, N, precision, &frac_bits, &coulomb, &L);
+  if (rc != PME_OK) return rc;
+  if (L.total > kScratchBytes) return PME_EWORKSPACE;
+  if (box == nullptr || (N > 0 && (pos == nullptr || q == nullptr || forces == nullptr)))
+    return PME_EINVAL;
+  char* ws = nullptr;
+  if (scratch_on_current_device(&ws) != hipSuccess) return PME_EDEVICE;
+  // a host plan on the stack (no heap), over this device's scratch; the
+  // initialisation launch rewrites the tables and clears every counter the
+  // step relies on, whatever an earlier call left there
+  pme_plan p;
+  rc = init_plan(&p, K1, K2, K3, order, beta, N, precision, frac_bits, coulomb, ws, kScratchBytes,
+                 static_cast<hipStream_t>(stream), L);
+  if (rc != PME_OK) return rc;
+  return pme_step(&p, pos, q, N, box, forces, accumulate, ev);
+}

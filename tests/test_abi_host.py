@@ -7,6 +7,8 @@ import re
 
 import pytest
 
+from paper_2009_12617_amd import _lib
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -110,3 +112,22 @@ def test_product_package_never_touches_the_oracle():
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "spme_oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_noalloc_step_answers_without_a_device(lib):
+    # the size limit and argument checks answer before any device work
+    fake = 0x7f0000000000
+    box = (ctypes.c_double * 9)(128, 0, 0, 0, 128, 0, 0, 0, 128)
+    need = lib.pme_workspace_bytes(128, 128, 128, 4, 209715, 1)
+    assert need > _lib.PME_SCRATCH_BYTES
+    assert lib.pme_step_noalloc(128, 128, 128, 4, 0.32, 1, 0, 0.0, fake, fake, 209715, box,
+                                fake, 0, fake, None) == 3          # PME_EWORKSPACE
+    assert lib.pme_workspace_bytes(64, 64, 64, 4, 65536, 1) <= _lib.PME_SCRATCH_BYTES
+    assert lib.pme_step_noalloc(64, 64, 64, 4, 0.0, 1, 0, 0.0, fake, fake, 100, box,
+                                fake, 0, fake, None) == 1          # beta
+    assert lib.pme_step_noalloc(50, 50, 50, 4, 0.3, 1, 0, 0.0, fake, fake, 100, box,
+                                fake, 0, fake, None) == 2          # radix 5
+    assert lib.pme_step_noalloc(64, 64, 64, 4, 0.3, 1, 0, 0.0, fake, fake, 100, None,
+                                fake, 0, fake, None) == 1          # no box
+    assert lib.pme_step_noalloc(64, 64, 64, 4, 0.3, 1, 0, 0.0, fake, fake, 100, box,
+                                None, 0, fake, None) == 1          # no forces
