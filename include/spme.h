@@ -201,6 +201,12 @@ int pme_batch_run(pme_plan *const *plans, int n, void *stream);
 #define PME_CONV_SPLIT 1   /* the same in three launches of row-chunk workgroups (forward y;
                               z, influence function, inverse z; inverse y), the half
                               spectrum in the workspace between them */
+#define PME_CONV_REG 2     /* one workgroup per x' column (FP32 precisions, y and z pencils of
+                              32 or 64 points): each pencil held in registers by a few lanes
+                              of one wavefront, radix-8 and radix-4/8 DFTs in registers with
+                              one transpose through LDS between them; the forward z
+                              transform, the influence function and the inverse z transform
+                              on the same registers (one launch) */
 #define PME_INTERP_FUSED 0 /* each (z-plane, y-slice) tile transforms the potential rows its
                               atoms read back along x in LDS, then interpolates (one launch) */
 #define PME_INTERP_SPLIT 1 /* inverse x transform once per plane into the workspace, then
@@ -210,9 +216,10 @@ int pme_batch_run(pme_plan *const *plans, int n, void *stream);
 #define PME_VAR_CONV_SPLIT 2u
 #define PME_VAR_INTERP_FUSED 4u
 #define PME_VAR_INTERP_SPLIT 8u
+#define PME_VAR_CONV_REG 16u
 
 typedef struct {
-  int conv;       /* PME_CONV_FUSED or PME_CONV_SPLIT */
+  int conv;       /* PME_CONV_FUSED, PME_CONV_SPLIT or PME_CONV_REG */
   int interp;     /* PME_INTERP_FUSED or PME_INTERP_SPLIT */
   int bin_chunk;  /* atoms per binning workgroup: 256, 512 or 1024 */
 } pme_tuning;
@@ -233,8 +240,9 @@ int pme_get_tuning(pme_plan *plan, pme_tuning *out);
 int pme_set_tuning(pme_plan *plan, const pme_tuning *t);
 
 /* Autotuning: runs whole steps (pme_step with these arguments) of every
- * variant the plan supports -- each conv x interp x bin_chunk combination,
- * in that nesting order, bin_chunk fastest -- `reps` timed steps each
+ * variant the plan supports -- each conv (fused, split, reg) x interp
+ * (fused, split) x bin_chunk (256, 512, 1024) combination, in that nesting
+ * order, bin_chunk fastest: 18 candidates -- `reps` timed steps each
  * (after 3 untimed), measured with HIP events on the plan's stream; repeats
  * the sweep three times and keeps each candidate's best mean.  Leaves the
  * plan set to the fastest and returns it in *best with its time in
@@ -349,9 +357,14 @@ size_t pme_debug_grid_bytes(pme_plan *plan, int which);
 int pme_check(pme_plan *plan, unsigned *flags);
 
 /* Per-kernel timing with HIP events on the plan's stream (off by default).
- * While enabled every launch carries a start and a stop event attached to
- * the dispatch itself (hipExtLaunchKernel), so the elapsed time is the
- * kernel's own execution; pme_kernel_times
+ * enable 1: every launch carries a start and a stop event attached to the
+ * dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
+ * own execution.  enable 2: external events are recorded on the stream
+ * before and after every launch (hipEventRecordWithFlags with
+ * hipEventRecordExternal), which stream capture keeps as event nodes, so the
+ * steps of a captured graph are timed kernel by kernel at replay (capture,
+ * replay once, then read the times; the events are reused after that).
+ * Changing the mode drops unread times.  pme_kernel_times
  * synchronises, adds the elapsed times of all completed launches into
  * ms[0..n-1] (kernel order: 0 bin, 1 spread + x FFT, 2 y/z FFTs with the
  * influence function and the inverse z/y FFTs, 3 inverse x FFT + force

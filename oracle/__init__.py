@@ -43,9 +43,10 @@ def _load():
     lib.orc_ewald_real.argtypes = [_dp, _dp, i, _dp, d, d, i, d, _dp, _dp, _dp]
     _ip = ctypes.POINTER(ctypes.c_int)
     lib.orc_ewald_excl.argtypes = [_dp, _dp, i, _dp, d, d, d, _ip, _ip, _dp, _dp]
+    lib.orc_ewald_real_atoms.argtypes = [_dp, _dp, i, _dp, d, d, i, d, _ip, i, _dp]
     for name in ("orc_bspline", "orc_moduli", "orc_fft1d", "orc_fft3d", "orc_spme",
                  "orc_mirror_grid", "orc_mirror_spline", "orc_ewald_recip", "orc_ewald_real",
-                 "orc_ewald_excl"):
+                 "orc_ewald_excl", "orc_ewald_real_atoms"):
         getattr(lib, name).restype = i
     _lib = lib
     return lib
@@ -197,6 +198,22 @@ def ewald_real(pos, q, box, beta, nimg=1, rcut=0.0, coulomb=1.0):
                                   int(nimg), float(rcut), _ptr(forces), _ptr(er), _ptr(es)),
            "orc_ewald_real")
     return {"forces": forces, "E_real": float(er[0]), "E_self": float(es[0])}
+
+
+def ewald_real_atoms(pos, q, box, beta, atoms, nimg=1, rcut=0.0, coulomb=1.0):
+    """Real-space forces on the listed atoms only: rows of ewald_real's forces."""
+    pos = _f64(pos)
+    N = pos.shape[0]
+    pos = pos.reshape(N, 3)
+    q = _f64(q, (N,))
+    b = _box(box)
+    at = np.ascontiguousarray(atoms, dtype=np.int32)
+    forces = np.zeros((len(at), 3))
+    _check(_load().orc_ewald_real_atoms(_ptr(pos), _ptr(q), N, _ptr(b), float(beta),
+                                        float(coulomb), int(nimg), float(rcut),
+                                        at.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(at),
+                                        _ptr(forces)), "orc_ewald_real_atoms")
+    return forces
 
 
 def ewald_excl(pos, q, box, beta, excl_off, excl_idx, rcut=0.0, coulomb=1.0):

@@ -596,6 +596,35 @@ int orc_ewald_recip(const double *pos, const double *q, int N, const double box[
 /*            the prime dropping i == j at n == 0                      */
 /*   E_self = -c beta/sqrt(pi) sum_i q_i^2                             */
 /* ------------------------------------------------------------------ */
+/* The real-space terms of atom i: its pair energies added to *E (each pair
+ * term halved, in the order j, n1, n2, n3) and its force added to f[3]
+ * (when f is not NULL). */
+static void real_terms_of(int i, const double *pos, const double *q, int N, const double box[9],
+                          double beta, double coulomb, int nimg, double rcut, double *E,
+                          double *f) {
+  for (int j = 0; j < N; ++j) {
+    for (int n1 = -nimg; n1 <= nimg; ++n1)
+      for (int n2 = -nimg; n2 <= nimg; ++n2)
+        for (int n3 = -nimg; n3 <= nimg; ++n3) {
+          if (i == j && n1 == 0 && n2 == 0 && n3 == 0) continue;
+          double d[3];
+          for (int c = 0; c < 3; ++c)
+            d[c] = pos[3 * i + c] - pos[3 * j + c] + n1 * box[0 + c] + n2 * box[3 + c] +
+                   n3 * box[6 + c];
+          double r = sqrt(dot3(d, d));
+          if (rcut > 0.0 && r > rcut) continue;
+          *E += 0.5 * coulomb * q[i] * q[j] * erfc(beta * r) / r;
+          if (f) {
+            double a = coulomb * q[i] * q[j] *
+                       (erfc(beta * r) / (r * r) +
+                        2.0 * beta / sqrt(ORC_PI) * exp(-beta * beta * r * r) / r) /
+                       r;
+            for (int c = 0; c < 3; ++c) f[c] += a * d[c];
+          }
+        }
+  }
+}
+
 int orc_ewald_real(const double *pos, const double *q, int N, const double box[9],
                    double beta, double coulomb, int nimg, double rcut, double *forces,
                    double *e_real, double *e_self) {
@@ -605,30 +634,27 @@ int orc_ewald_real(const double *pos, const double *q, int N, const double box[9
     for (int i = 0; i < 3 * N; ++i) forces[i] = 0.0;
   for (int i = 0; i < N; ++i) {
     S += q[i] * q[i];
-    for (int j = 0; j < N; ++j) {
-      for (int n1 = -nimg; n1 <= nimg; ++n1)
-        for (int n2 = -nimg; n2 <= nimg; ++n2)
-          for (int n3 = -nimg; n3 <= nimg; ++n3) {
-            if (i == j && n1 == 0 && n2 == 0 && n3 == 0) continue;
-            double d[3];
-            for (int c = 0; c < 3; ++c)
-              d[c] = pos[3 * i + c] - pos[3 * j + c] + n1 * box[0 + c] + n2 * box[3 + c] +
-                     n3 * box[6 + c];
-            double r = sqrt(dot3(d, d));
-            if (rcut > 0.0 && r > rcut) continue;
-            E += 0.5 * coulomb * q[i] * q[j] * erfc(beta * r) / r;
-            if (forces) {
-              double a = coulomb * q[i] * q[j] *
-                         (erfc(beta * r) / (r * r) +
-                          2.0 * beta / sqrt(ORC_PI) * exp(-beta * beta * r * r) / r) /
-                         r;
-              for (int c = 0; c < 3; ++c) forces[3 * i + c] += a * d[c];
-            }
-          }
-    }
+    real_terms_of(i, pos, q, N, box, beta, coulomb, nimg, rcut, &E,
+                  forces ? forces + 3 * i : NULL);
   }
   if (e_real) *e_real = E;
   if (e_self) *e_self = -coulomb * beta / sqrt(ORC_PI) * S;
+  return 0;
+}
+
+/* Real-space forces on the listed atoms only (the rows of orc_ewald_real's
+ * forces for those atoms, same arithmetic): checks of large systems on a
+ * sample of atoms. */
+int orc_ewald_real_atoms(const double *pos, const double *q, int N, const double box[9],
+                         double beta, double coulomb, int nimg, double rcut, const int *atoms,
+                         int n_atoms, double *forces) {
+  if (N < 0 || nimg < 0 || !(beta > 0.0) || n_atoms < 0) return -1;
+  for (int k = 0; k < n_atoms; ++k) {
+    if (atoms[k] < 0 || atoms[k] >= N) return -1;
+    double E = 0.0;
+    for (int c = 0; c < 3; ++c) forces[3 * k + c] = 0.0;
+    real_terms_of(atoms[k], pos, q, N, box, beta, coulomb, nimg, rcut, &E, forces + 3 * k);
+  }
   return 0;
 }
 

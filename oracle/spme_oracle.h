@@ -77,6 +77,12 @@ int orc_ewald_real(const double *pos, const double *q, int N,
                    int nimg, double rcut, double *forces, double *e_real,
                    double *e_self);
 
+/* The real-space forces of orc_ewald_real on the n_atoms listed atoms only
+ * (forces [n_atoms][3], same arithmetic as the full sum's rows). */
+int orc_ewald_real_atoms(const double *pos, const double *q, int N, const double box[9],
+                         double beta, double coulomb, int nimg, double rcut, const int *atoms,
+                         int n_atoms, double *forces);
+
 /* Exclusion correction: removes, for every excluded pair listed in the
  * symmetric CSR lists (excl_off[N+1], excl_idx), the erfc/r real-space part
  * (r <= rcut) and the erf/r reciprocal part of its Ewald interaction at the

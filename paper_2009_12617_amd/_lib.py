@@ -21,9 +21,10 @@ PME_FLAG_BUCKETS = 4
 
 PME_EBUSY = 8
 PME_SCRATCH_BYTES = 32 << 20  # static scratch of pme_step_noalloc (include/spme.h)
-PME_CONV_FUSED, PME_CONV_SPLIT = 0, 1
+PME_CONV_FUSED, PME_CONV_SPLIT, PME_CONV_REG = 0, 1, 2
 PME_INTERP_FUSED, PME_INTERP_SPLIT = 0, 1
 PME_VAR_CONV_FUSED, PME_VAR_CONV_SPLIT, PME_VAR_INTERP_FUSED, PME_VAR_INTERP_SPLIT = 1, 2, 4, 8
+PME_VAR_CONV_REG = 16
 
 STATUS = {0: "PME_OK", 1: "PME_EINVAL", 2: "PME_EUNSUPPORTED", 3: "PME_EWORKSPACE",
           4: "PME_EOVERFLOW", 5: "PME_EDEVICE", 6: "PME_ENONFINITE", 7: "PME_ESTATE",

@@ -82,8 +82,10 @@ hipEvent_t next_event(pme_plan* p) {
   return p->event_pool[p->event_next++];
 }
 
-// Run one launch; with timing on, events are attached to the dispatch and
-// queued for pme_kernel_times.
+// Run one launch; with timing on, events are attached to the dispatch
+// (mode 1) or recorded on the stream around it as external events, which a
+// graph capture keeps as event nodes (mode 2), and queued for
+// pme_kernel_times.
 template <class F>
 int timed(pme_plan* p, int kernel, F&& launch) {
   if (!p->timing) return device_error(launch(spme::Timing()));
@@ -91,7 +93,14 @@ int timed(pme_plan* p, int kernel, F&& launch) {
   t.start = next_event(p);
   t.stop = next_event(p);
   if (!t.start || !t.stop) return PME_EDEVICE;
-  if (launch(t) != hipSuccess) return PME_EDEVICE;
+  if (p->timing == 2) {
+    if (hipEventRecordWithFlags(t.start, p->stream, hipEventRecordExternal) != hipSuccess ||
+        launch(spme::Timing()) != hipSuccess ||
+        hipEventRecordWithFlags(t.stop, p->stream, hipEventRecordExternal) != hipSuccess)
+      return PME_EDEVICE;
+  } else if (launch(t) != hipSuccess) {
+    return PME_EDEVICE;
+  }
   p->pending.push_back({kernel, t.start, t.stop});
   return PME_OK;
 }
@@ -181,6 +190,14 @@ int check_plan_args(int K1, int K2, int K3, int order, double beta, int max_atom
     return PME_EUNSUPPORTED;
   if (!spme::layout_for(K1, K2, K3, order, max_atoms, precision, L)) return PME_EUNSUPPORTED;
   return PME_OK;
+}
+
+// PME_VAR_* bits a tuning needs.
+unsigned variant_bits(const pme_tuning& t) {
+  const unsigned c = t.conv == PME_CONV_FUSED ? PME_VAR_CONV_FUSED
+                     : t.conv == PME_CONV_SPLIT ? PME_VAR_CONV_SPLIT
+                                                : PME_VAR_CONV_REG;
+  return c | (t.interp == PME_INTERP_FUSED ? PME_VAR_INTERP_FUSED : PME_VAR_INTERP_SPLIT);
 }
 
 }  // namespace
@@ -649,8 +666,11 @@ int pme_check(pme_plan* p, unsigned* flags) {
 }
 
 int pme_kernel_timing(pme_plan* p, int enable) {
-  if (p == nullptr) return PME_EINVAL;
-  p->timing = enable ? 1 : 0;
+  if (p == nullptr || enable < 0 || enable > 2) return PME_EINVAL;
+  p->timing = enable;
+  p->pending.clear();
+  p->event_next = 0;
+  p->timed_steps = 0;
   return PME_OK;
 }
 
@@ -693,12 +713,11 @@ int pme_get_tuning(pme_plan* p, pme_tuning* out) {
 int pme_set_tuning(pme_plan* p, const pme_tuning* t) {
   if (p == nullptr || t == nullptr) return PME_EINVAL;
   if (t->bin_chunk != 256 && t->bin_chunk != 512 && t->bin_chunk != 1024) return PME_EINVAL;
-  if ((t->conv != PME_CONV_FUSED && t->conv != PME_CONV_SPLIT) ||
+  if ((t->conv != PME_CONV_FUSED && t->conv != PME_CONV_SPLIT && t->conv != PME_CONV_REG) ||
       (t->interp != PME_INTERP_FUSED && t->interp != PME_INTERP_SPLIT))
     return PME_EINVAL;
   const unsigned v = spme::variants_for(p->K1, p->K2, p->K3, p->order, p->precision);
-  const unsigned need = (t->conv == PME_CONV_FUSED ? PME_VAR_CONV_FUSED : PME_VAR_CONV_SPLIT) |
-                        (t->interp == PME_INTERP_FUSED ? PME_VAR_INTERP_FUSED : PME_VAR_INTERP_SPLIT);
+  const unsigned need = variant_bits(*t);
   if ((v & need) != need) return PME_EUNSUPPORTED;
   // the convolution of a spread step must match its spread (energy rows)
   if (p->state == kSpread) return PME_ESTATE;
@@ -715,7 +734,7 @@ int pme_autotune(pme_plan* p, const double* pos, const double* q, int N, const d
   if (p == nullptr || reps < 1 || (max_times > 0 && times_us == nullptr)) return PME_EINVAL;
   if (N > 0 && forces == nullptr) return PME_EINVAL;
   const unsigned v = spme::variants_for(p->K1, p->K2, p->K3, p->order, p->precision);
-  const int convs[2] = {PME_CONV_FUSED, PME_CONV_SPLIT};
+  const int convs[3] = {PME_CONV_FUSED, PME_CONV_SPLIT, PME_CONV_REG};
   const int interps[2] = {PME_INTERP_FUSED, PME_INTERP_SPLIT};
   const int chunks[3] = {256, 512, 1024};
   std::vector<pme_tuning> cand;
@@ -735,9 +754,7 @@ int pme_autotune(pme_plan* p, const double* pos, const double* q, int N, const d
   for (int round = 0; round < 3 && rc == PME_OK; ++round) {
     for (size_t k = 0; k < cand.size() && rc == PME_OK; ++k) {
       const pme_tuning& t = cand[k];
-      const unsigned need =
-          (t.conv == PME_CONV_FUSED ? PME_VAR_CONV_FUSED : PME_VAR_CONV_SPLIT) |
-          (t.interp == PME_INTERP_FUSED ? PME_VAR_INTERP_FUSED : PME_VAR_INTERP_SPLIT);
+      const unsigned need = variant_bits(t);
       if ((v & need) != need) continue;
       if (p->state == kSpread) p->state = kDirty;  // (a failed step left counts behind)
       rc = pme_set_tuning(p, &t);

@@ -84,7 +84,7 @@ struct Args {
   int N, n_chunks;
   int accumulate, keep_grid;
   int reduce_ev;  // the last launch's extra workgroup adds the energy/virial rows
-  int conv_mode;    // kConvFused or kConvSplit
+  int conv_mode;    // kConvFused, kConvSplit or kConvReg
   int interp_mode;  // kInterpFused or kInterpSplit
   int bin_chunk;    // atoms per binning workgroup (kMinChunk .. kBinThreads, a multiple of 64)
   int ev_rows;      // energy/virial rows the convolution variant writes (from row 0)
@@ -112,10 +112,11 @@ struct BatchArgs {
 // tuning picks one of each among those its shape supports).
 constexpr int kConvFused = 0;    // one workgroup per x' column, all y/z work in LDS
 constexpr int kConvSplit = 1;    // three launches of row-chunk workgroups
+constexpr int kConvReg = 2;      // one workgroup per column, transforms held in registers
 constexpr int kInterpFused = 0;  // inverse x transform of a bin's rows + interpolation, one launch
 constexpr int kInterpSplit = 1;  // inverse x transform per plane, then a gather launch
 constexpr unsigned kVarConvFused = 1u, kVarConvSplit = 2u, kVarInterpFused = 4u,
-                   kVarInterpSplit = 8u;
+                   kVarInterpSplit = 8u, kVarConvReg = 16u;
 
 // Optional events attached to one kernel dispatch (both null: untimed).
 struct Timing {

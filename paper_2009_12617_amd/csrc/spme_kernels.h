@@ -618,66 +618,115 @@ __device__ __forceinline__ void keep_counts(const Args& a, double* wred) {
 // Szz, Sxy, Sxz, Syz), so that P_aa = S0 - 2 S_aa and P_ab = -2 S_ab.  A
 // Nyquist index aliases +K_a/2 and -K_a/2 equally, so its sign-odd
 // (off-diagonal) products vanish.
+// Constants of one x' column for the influence function.
+struct InflCol {
+  double fac, mvx, nx, wx, mvx2, A;
+};
+template <class G>
+__device__ __forceinline__ InflCol infl_col(const Args& a, int xp, const double* bs) {
+  constexpr double PI = 3.14159265358979323846;
+  InflCol c;
+  const double pref = a.coulomb / (PI * a.volume);
+  c.fac = PI * PI / (a.beta * a.beta);
+  c.mvx = xp * a.invL[0];
+  c.nx = (2 * xp == G::K1) ? 0.0 : c.mvx;
+  c.wx = (xp == 0 || 2 * xp == G::K1) ? 0.5 : 1.0;
+  c.mvx2 = c.mvx * c.mvx;
+  c.A = pref * bs[xp];
+  return c;
+}
+
+// One mode (xp, y, z) of an orthorhombic cell: returns G(m) F(m) and adds
+// the mode's energy/virial terms to acc.
+template <class G, typename T>
+__device__ __forceinline__ cplx<T> infl_ortho(const Args& a, const InflCol& c, int xp, int y,
+                                              int z, const double* bs, cplx<T> f, double* acc) {
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
+  const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
+  const double ny = (2 * y == K2) ? 0.0 : mvy, nz = (2 * z == K3) ? 0.0 : mvz;
+  // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and its
+  // G by 0, without a branch
+  const bool m0 = (xp == 0) && (y == 0) && (z == 0);
+  const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, c.mvx2));
+  // 1/msq: hardware reciprocal and two Newton steps
+  double r = __builtin_amdgcn_rcp(msq);
+  r = fma(r, fma(-msq, r, 1.0), r);
+  r = fma(r, fma(-msq, r, 1.0), r);
+  const double gm = m0 ? 0.0 : c.A * bs[K1 + y] * bs[K1 + K2 + z] * r;  // G(m)
+  const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+  const double e = c.wx * gm * f2;
+  const double eu = e * (r + c.fac);
+  const double eux = eu * c.mvx, euy = eu * mvy, eun = eu * c.nx;
+  acc[0] += e;
+  acc[1] = fma(eux, c.mvx, acc[1]);
+  acc[2] = fma(euy, mvy, acc[2]);
+  acc[3] = fma(eu * mvz, mvz, acc[3]);
+  acc[4] = fma(eun, ny, acc[4]);
+  acc[5] = fma(eun, nz, acc[5]);
+  acc[6] = fma(eu * ny, nz, acc[6]);
+  const T g = (T)gm;
+  return {f.x * g, f.y * g};
+}
+
+// One mode of a general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not
+// separate; each Nyquist index is averaged over its two signs explicitly.
+template <class G, typename T>
+__device__ __forceinline__ cplx<T> infl_general(const Args& a, const InflCol& c, int xp, int y,
+                                                int z, const double* bs, cplx<T> f, double* acc) {
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
+  const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
+  const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
+  const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
+  const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
+  double gm = 0.0;  // G(m), averaged over the Nyquist signs
+  if (xp != 0 || y != 0 || z != 0) {
+    const double Bw = c.A * bs[K1 + y] * bs[K1 + K2 + z] / nvar;
+    for (int v = 0; v < nvar; ++v) {
+      double ms[3];
+      int bit = 0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        ms[ax] = ms0[ax];
+        if (ny3[ax]) {
+          if ((v >> bit) & 1) ms[ax] = -ms[ax];
+          ++bit;
+        }
+      }
+      double mv[3];
+#pragma unroll
+      for (int c2 = 0; c2 < 3; ++c2)
+        mv[c2] = ms[0] * a.rec[c2] + ms[1] * a.rec[3 + c2] + ms[2] * a.rec[6 + c2];
+      const double msq = mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2];
+      double r = __builtin_amdgcn_rcp(msq);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      r = fma(r, fma(-msq, r, 1.0), r);
+      const double Gv = Bw * exp(-c.fac * msq) * r;
+      const double e = c.wx * Gv * f2;
+      const double eu = e * (r + c.fac);
+      acc[0] += e;
+      acc[1] = fma(eu * mv[0], mv[0], acc[1]);
+      acc[2] = fma(eu * mv[1], mv[1], acc[2]);
+      acc[3] = fma(eu * mv[2], mv[2], acc[3]);
+      acc[4] = fma(eu * mv[0], mv[1], acc[4]);
+      acc[5] = fma(eu * mv[0], mv[2], acc[5]);
+      acc[6] = fma(eu * mv[1], mv[2], acc[6]);
+      gm += Gv;
+    }
+  }
+  const T g = (T)gm;
+  return {f.x * g, f.y * g};
+}
+
 template <class P, class G, int CY, int PZ, int VT>
 __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>* buf, int xp,
                                           int y0, const double* bs, double* acc, int vt) {
-  using T = typename P::real;
-  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
-  constexpr double PI = 3.14159265358979323846;
-  const double pref = a.coulomb / (PI * a.volume);
-  const double fac = PI * PI / (a.beta * a.beta);
-  const double mvx = xp * a.invL[0];
-  const double nx = (2 * xp == K1) ? 0.0 : mvx;
-  const double wx = (xp == 0 || 2 * xp == K1) ? 0.5 : 1.0;
-  const double mvx2 = mvx * mvx;
-  const double A = pref * bs[xp];
+  constexpr int K3 = G::K3;
+  const InflCol c = infl_col<G>(a, xp, bs);
   if (a.triclinic) {
-    // general cell: m = m1 a*_1 + m2 a*_2 + m3 a*_3 does not separate;
-    // each Nyquist index is averaged over its two signs explicitly
     for (int i = vt; i < K3 * CY; i += VT) {
-      const int z = i / CY, yy = i - z * CY, y = y0 + yy;
-      const int ms0[3] = {xp, (2 * y <= K2) ? y : y - K2, (2 * z <= K3) ? z : z - K3};
-      const int ny3[3] = {2 * xp == K1, 2 * y == K2, 2 * z == K3};
-      const int nvar = 1 << (ny3[0] + ny3[1] + ny3[2]);
-      const cplx<T> f = buf[z * PZ + yy];
-      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-      double gm = 0.0;  // G(m), averaged over the Nyquist signs
-      if (xp != 0 || y != 0 || z != 0) {
-        const double Bw = A * bs[K1 + y] * bs[K1 + K2 + z] / nvar;
-        for (int v = 0; v < nvar; ++v) {
-          double ms[3];
-          int bit = 0;
-#pragma unroll
-          for (int ax = 0; ax < 3; ++ax) {
-            ms[ax] = ms0[ax];
-            if (ny3[ax]) {
-              if ((v >> bit) & 1) ms[ax] = -ms[ax];
-              ++bit;
-            }
-          }
-          double mv[3];
-#pragma unroll
-          for (int c2 = 0; c2 < 3; ++c2)
-            mv[c2] = ms[0] * a.rec[c2] + ms[1] * a.rec[3 + c2] + ms[2] * a.rec[6 + c2];
-          const double msq = mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2];
-          double r = __builtin_amdgcn_rcp(msq);
-          r = fma(r, fma(-msq, r, 1.0), r);
-          r = fma(r, fma(-msq, r, 1.0), r);
-          const double Gv = Bw * exp(-fac * msq) * r;
-          const double e = wx * Gv * f2;
-          const double eu = e * (r + fac);
-          acc[0] += e;
-          acc[1] = fma(eu * mv[0], mv[0], acc[1]);
-          acc[2] = fma(eu * mv[1], mv[1], acc[2]);
-          acc[3] = fma(eu * mv[2], mv[2], acc[3]);
-          acc[4] = fma(eu * mv[0], mv[1], acc[4]);
-          acc[5] = fma(eu * mv[0], mv[2], acc[5]);
-          acc[6] = fma(eu * mv[1], mv[2], acc[6]);
-          gm += Gv;
-        }
-      }
-      const T g = (T)gm;
-      buf[z * PZ + yy] = {f.x * g, f.y * g};
+      const int z = i / CY, yy = i - z * CY;
+      buf[z * PZ + yy] = infl_general<G>(a, c, xp, y0 + yy, z, bs, buf[z * PZ + yy], acc);
     }
   } else {
     constexpr int NIT = (K3 * CY + VT - 1) / VT;
@@ -686,33 +735,8 @@ __device__ __forceinline__ void influence(const Args& a, cplx<typename P::real>*
     for (int it = 0; it < NIT; ++it) {
       const int i = vt + it * VT;
       if ((K3 * CY) % VT != 0 && i >= K3 * CY) break;
-      const int z = i / CY, yy = i - z * CY, y = y0 + yy;
-      const int my = (2 * y <= K2) ? y : y - K2, mz = (2 * z <= K3) ? z : z - K3;
-      const double mvy = my * a.invL[1], mvz = mz * a.invL[2];
-      const double ny = (2 * y == K2) ? 0.0 : mvy, nz = (2 * z == K3) ? 0.0 : mvz;
-      const cplx<T> f = buf[z * PZ + yy];
-      // m = 0 carries no energy (G(0) = 0): its |m|^2 is replaced by 1 and
-      // its G by 0, without a branch
-      const bool m0 = (xp == 0) && (y == 0) && (z == 0);
-      const double msq = m0 ? 1.0 : fma(mvz, mvz, fma(mvy, mvy, mvx2));
-      // 1/msq: hardware reciprocal and two Newton steps
-      double r = __builtin_amdgcn_rcp(msq);
-      r = fma(r, fma(-msq, r, 1.0), r);
-      r = fma(r, fma(-msq, r, 1.0), r);
-      const double gm = m0 ? 0.0 : A * bs[K1 + y] * bs[K1 + K2 + z] * r;  // G(m)
-      const double f2 = fma((double)f.x, (double)f.x, (double)f.y * (double)f.y);
-      const double e = wx * gm * f2;
-      const double eu = e * (r + fac);
-      const double eux = eu * mvx, euy = eu * mvy, eun = eu * nx;
-      acc[0] += e;
-      acc[1] = fma(eux, mvx, acc[1]);
-      acc[2] = fma(euy, mvy, acc[2]);
-      acc[3] = fma(eu * mvz, mvz, acc[3]);
-      acc[4] = fma(eun, ny, acc[4]);
-      acc[5] = fma(eun, nz, acc[5]);
-      acc[6] = fma(eu * ny, nz, acc[6]);
-      const T g = (T)gm;
-      buf[z * PZ + yy] = {f.x * g, f.y * g};
+      const int z = i / CY, yy = i - z * CY;
+      buf[z * PZ + yy] = infl_ortho<G>(a, c, xp, y0 + yy, z, bs, buf[z * PZ + yy], acc);
     }
   }
 }
@@ -1007,6 +1031,210 @@ __global__ __launch_bounds__(kPassThreads) void k_conv_z(Args a_in, BatchArgs bt
   }
   ev_row(a, acc, blockIdx.x * (NT / 64) + (tid >> 6));
   TRACE(4, 15);
+}
+
+// ---------------------------------------------------------------------------
+// k_conv_reg: the column convolution with register-resident transforms
+// (FP32 precisions; y and z pencils of 32 or 64 points).  A pencil of
+// N = 8 R points is held by R lanes of one wavefront, 8 values per lane
+// (lane j holds points j + R r): a radix-8 DFT over r in registers, the
+// twiddles W_N^(j s), an R x 8 transpose through the wavefront's own LDS
+// scratch, then radix-R DFTs over the lanes in registers (Cooley-Tukey with
+// N = 8 R), which leaves lane j with the modes jE + e + 8t (E = 8/R, e < E,
+// t < R).  The inverse runs the same steps backwards from that layout.  The
+// forward z transform, the influence function and the inverse z transform
+// work on the same registers, so LDS carries only the two corner turns and
+// the transposes (the one-workgroup column of k_conv moves every element
+// through LDS twice per radix stage).  One workgroup per x' column.
+// ---------------------------------------------------------------------------
+template <class G>
+__host__ __device__ constexpr bool conv_reg_shape() {
+  return (G::K2 == 32 || G::K2 == 64) && (G::K3 == 32 || G::K3 == 64);
+}
+template <class G>
+__host__ __device__ constexpr int conv_reg_threads() {  // pencils x lanes, either pass
+  return G::K2 * G::K3 / 8;
+}
+template <class G>
+__host__ __device__ constexpr int conv_reg_pitch() {  // column row pitch (complex)
+  return G::K2 + 8;
+}
+template <class P, class G>
+__host__ __device__ constexpr size_t conv_reg_lds_bytes() {
+  // the column, then the transposes' scratch (a row of 8 values, pitch 9, per
+  // lane), then the y and z twiddles
+  return ((size_t)G::K3 * conv_reg_pitch<G>() + (size_t)conv_reg_threads<G>() * 9 + G::K2 +
+          G::K3) * sizeof(cplx<typename P::real>) +
+         (size_t)(G::K1 + G::K2 + G::K3) * sizeof(double) + 16 * 8 * sizeof(double);
+}
+
+// Forward (S = -1) or inverse (S = +1) N-point DFT, N = 8 R, of the pencil
+// whose points j + R r (r < 8) lane j (< R) holds in v[r]; on return v[eR + t]
+// holds mode jE + e + 8t.  scr: the pencil's LDS scratch (R rows of pitch
+// 9, starting at the pencil's first lane x 9); tw[k] = exp(-2 pi i k / N).
+template <typename T, int N, int S>
+__device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const cplx<T>* tw) {
+  constexpr int R = N / 8, E = 8 / R;
+  Dft<8, S, T>::run(v);
+#pragma unroll
+  for (int s = 1; s < 8; ++s) {
+    const cplx<T> w = tw[j * s];
+    v[s] = S < 0 ? c_mul(v[s], w) : c_mulc(v[s], w);
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) scr[j * 9 + s] = v[s];
+  lds_order();
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int l = 0; l < R; ++l) v[e * R + l] = scr[l * 9 + j * E + e];
+  lds_order();
+#pragma unroll
+  for (int e = 0; e < E; ++e) Dft<R, S, T>::run(v + e * R);
+}
+
+// The inverse direction of rfft_fwd's layouts: v[eR + t] holds mode
+// jE + e + 8t on entry; on return v[r] holds point j + R r.
+template <typename T, int N, int S>
+__device__ __forceinline__ void rfft_inv(cplx<T>* v, int j, cplx<T>* scr, const cplx<T>* tw) {
+  constexpr int R = N / 8, E = 8 / R;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    Dft<R, S, T>::run(v + e * R);
+    const int s = j * E + e;
+#pragma unroll
+    for (int l = 1; l < R; ++l) {
+      const cplx<T> w = tw[l * s];
+      v[e * R + l] = S < 0 ? c_mul(v[e * R + l], w) : c_mulc(v[e * R + l], w);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int l = 0; l < R; ++l) scr[l * 9 + j * E + e] = v[e * R + l];
+  lds_order();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = scr[j * 9 + s];
+  lds_order();
+  Dft<8, S, T>::run(v);
+}
+
+template <class P, class G, bool BATCH>
+__global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, BatchArgs bt) {
+  const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  using T = typename P::real;
+  using S = typename P::spec;
+  constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3, KH = K1 / 2 + 1;
+  constexpr int NT = conv_reg_threads<G>(), PB = conv_reg_pitch<G>();
+  constexpr int RY = K2 / 8, EY = 8 / RY, RZ = K3 / 8, EZ = 8 / RZ;
+  static_assert(conv_reg_shape<G>() && P::fixed, "register transforms: FP32, 32 or 64 points");
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);         // [z][y], pitch PB
+  cplx<T>* scr0 = buf + K3 * PB;                            // transposes: 9 per lane
+  cplx<T>* twy = scr0 + NT * 9;
+  cplx<T>* twz = twy + K2;
+  double* bs = reinterpret_cast<double*>(twz + K3);         // x, y, z factors
+  double* wred = bs + K1 + K2 + K3;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == KH) {
+    keep_counts<P, G, NT>(a, wred);
+    return;
+  }
+  const int xp = blockIdx.x;  // m1
+  S* col = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)xp * K3 * K2;  // [z][y]
+  const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
+
+  // --- forward y: pencil z = tid / RY, lane j loads points j + RY r
+  cplx<T> v[8];
+  {
+    const int z = tid / RY, j = tid - z * RY;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = spec_ld(&col[(size_t)z * K2 + j + RY * r]);
+  }
+  for (int i = tid; i < K2 + K3; i += NT) twy[i] = twg[K1 + i];
+  axis_factors<G, NT>(a, bs);
+  __syncthreads();
+  {
+    const int z = tid / RY, j = tid - z * RY;
+    rfft_fwd<T, K2, -1>(v, j, scr0 + (tid - j) * 9, twy);
+#pragma unroll
+    for (int e = 0; e < EY; ++e)
+#pragma unroll
+      for (int t = 0; t < RY; ++t) buf[z * PB + j * EY + e + 8 * t] = v[e * RY + t];
+  }
+  __syncthreads();
+
+  // --- z: forward transform, influence function, inverse transform
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  {
+    const int y = tid / RZ, j = tid - y * RZ;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = buf[(j + RZ * r) * PB + y];
+    rfft_fwd<T, K3, -1>(v, j, scr0 + (tid - j) * 9, twz);
+    const InflCol c = infl_col<G>(a, xp, bs);
+    if (a.triclinic) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int z = j * EZ + k / RZ + 8 * (k % RZ);
+        v[k] = infl_general<G>(a, c, xp, y, z, bs, v[k], acc);
+      }
+    } else {
+      // orthorhombic: the lane's modes share m1 and m2, so the factors of
+      // x and y are taken once per lane and the virial sums are kept as
+      // S0 = sum e, Su = sum eu, Sz = sum eu nz, Szz = sum eu mz^2, from
+      // which P_xx, P_yy, P_xy (m1^2 Su, m2^2 Su, n1 n2 Su) and P_xz, P_yz
+      // (n1 Sz, n2 Sz) follow
+      const int my = (2 * y <= K2) ? y : y - K2;
+      const double mvy = my * a.invL[1], ny = (2 * y == K2) ? 0.0 : mvy;
+      const double Ay = c.A * bs[K1 + y], base = fma(mvy, mvy, c.mvx2);
+      double s0 = 0.0, su = 0.0, sz = 0.0, szz = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int z = j * EZ + k / RZ + 8 * (k % RZ);
+        const int mz = (2 * z <= K3) ? z : z - K3;
+        const double mvz = mz * a.invL[2], nz = (2 * z == K3) ? 0.0 : mvz;
+        const bool m0 = (xp == 0) && (y == 0) && (z == 0);
+        const double msq = m0 ? 1.0 : fma(mvz, mvz, base);
+        double r = __builtin_amdgcn_rcp(msq);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        r = fma(r, fma(-msq, r, 1.0), r);
+        const double gm = m0 ? 0.0 : Ay * bs[K1 + K2 + z] * r;  // G(m)
+        const double f2 = fma((double)v[k].x, (double)v[k].x, (double)v[k].y * (double)v[k].y);
+        const double e = c.wx * gm * f2;
+        const double eu = e * (r + c.fac);
+        s0 += e;
+        su += eu;
+        sz = fma(eu, nz, sz);
+        szz = fma(eu * mvz, mvz, szz);
+        const T g = (T)gm;
+        v[k] = {v[k].x * g, v[k].y * g};
+      }
+      acc[0] = s0;
+      acc[1] = c.mvx2 * su;
+      acc[2] = (mvy * mvy) * su;
+      acc[3] = szz;
+      acc[4] = (c.nx * ny) * su;
+      acc[5] = c.nx * sz;
+      acc[6] = ny * sz;
+    }
+    rfft_inv<T, K3, 1>(v, j, scr0 + (tid - j) * 9, twz);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[(j + RZ * r) * PB + y] = v[r];
+  }
+  __syncthreads();
+
+  // --- inverse y, stored back to the column
+  {
+    const int z = tid / RY, j = tid - z * RY;
+#pragma unroll
+    for (int e = 0; e < EY; ++e)
+#pragma unroll
+      for (int t = 0; t < RY; ++t) v[e * RY + t] = buf[z * PB + j * EY + e + 8 * t];
+    rfft_inv<T, K2, 1>(v, j, scr0 + (tid - j) * 9, twy);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) spec_st(&col[(size_t)z * K2 + j + RY * r], v[r]);
+  }
+  ev_row(a, acc, xp * (NT / 64) + (tid >> 6));
 }
 
 // Sum of the energy/virial partial rows the step's convolution variant wrote,
@@ -1400,6 +1628,10 @@ __host__ __device__ constexpr bool conv_split_ok() {
          G::K2 % pass_cy<G>() == 0 && pass_cy<G>() * fft_lanes(G::K3) == kPassThreads &&
          conv_y_lds_bytes<P, G>() <= kMaxLds && conv_z_lds_bytes<P, G>() <= kMaxLds;
 }
+template <class P, class G>
+__host__ __device__ constexpr bool conv_reg_ok() {
+  return P::fixed && conv_reg_shape<G>() && conv_reg_lds_bytes<P, G>() <= kMaxLds;
+}
 template <class P, class G, int ORDER>
 __host__ __device__ constexpr bool interp_fused_ok() {
   return interp_lds_bytes<P, G, ORDER>() <= kMaxLds;
@@ -1423,6 +1655,11 @@ hipError_t raise_all_lds_limits() {
   if constexpr (conv_fused_ok<P, G>()) {
     if (e == hipSuccess)
       e = hipFuncSetAttribute((const void*)k_conv<P, G, B>, attr, (int)conv_lds_bytes<P, G>());
+  }
+  if constexpr (conv_reg_ok<P, G>()) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_conv_reg<P, G, B>, attr,
+                              (int)conv_reg_lds_bytes<P, G>());
   }
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_inv_x<P, G, O, B>, attr, (int)inv_x_lds_bytes<P, G>());
@@ -1454,6 +1691,7 @@ unsigned variants_p(int K1, int K2, int K3, int order) {
     return with_order(order, [&](auto oc) {
       constexpr int O = decltype(oc)::value;
       v = (conv_fused_ok<P, G>() ? kVarConvFused : 0u) | (conv_split_ok<P, G>() ? kVarConvSplit : 0u) |
+          (conv_reg_ok<P, G>() ? kVarConvReg : 0u) |
           (interp_fused_ok<P, G, O>() ? kVarInterpFused : 0u) | kVarInterpSplit;
       return hipSuccess;
     });
@@ -1512,6 +1750,11 @@ hipError_t launch_conv_p(const Args& a, hipStream_t s, const Timing& t, const Ba
           const int blocks = KH + 1;  // columns and the counts/headroom workgroup
           return launch(k_conv<P, G, B>, dim3(blocks), dim3(conv_block<P, G, B>()),
                         conv_lds_bytes<P, G>(), s, t, a, bt);
+        }
+      } else if (a.conv_mode == kConvReg) {
+        if constexpr (conv_reg_ok<P, G>()) {
+          return launch(k_conv_reg<P, G, B>, dim3(KH + 1), dim3(conv_reg_threads<G>()),
+                        conv_reg_lds_bytes<P, G>(), s, t, a, bt);
         }
       }
       return hipErrorInvalidValue;

@@ -100,16 +100,21 @@ unsigned variants_for(int K1, int K2, int K3, int order, int precision) {
   return ops->variants(K1, K2, K3, order);
 }
 
-// Built-in choices (measured on MI355X): the fused column wherever a column
-// has fewer than 8192 points (each extra launch costs more than the LDS work
-// it spreads out), the fused interpolation except for p >= 6 on grids with
-// K2 K3 >= 16384 (where redoing the inverse x transform per bin costs 6.8x
-// the grid).
+// Built-in choices (measured on MI355X): one workgroup per column wherever a
+// column has fewer than 8192 points (each extra launch costs more than the
+// LDS work it spreads out) -- the register-resident transforms where the
+// pencils allow them (FP32, 32 or 64 points), else the LDS-resident ones --
+// and the fused interpolation except for p >= 6 on grids with K2 K3 >= 16384
+// (where redoing the inverse x transform per bin costs 6.8x the grid).
 void default_variants(int K1, int K2, int K3, int order, int precision, int* conv_mode,
                       int* interp_mode) {
   const unsigned v = variants_for(K1, K2, K3, order, precision);
   const bool big = (long)K2 * K3 >= 8192;
-  *conv_mode = ((big && (v & kVarConvSplit)) || !(v & kVarConvFused)) ? kConvSplit : kConvFused;
+  if (!big && (v & kVarConvReg))
+    *conv_mode = kConvReg;
+  else
+    *conv_mode =
+        ((big && (v & kVarConvSplit)) || !(v & kVarConvFused)) ? kConvSplit : kConvFused;
   const bool isplit = order >= 6 && (long)K2 * K3 >= 16384;
   *interp_mode = (isplit || !(v & kVarInterpFused)) ? kInterpSplit : kInterpFused;
 }
@@ -128,6 +133,8 @@ int ev_rows_for(int K1, int K2, int K3, int precision, int conv_mode) {
         if (conv_mode == kConvSplit) w = (G::K2 / pass_cy<G>()) * (kPassThreads / 64);
       if constexpr (conv_fused_ok<P, G>())
         if (conv_mode == kConvFused) w = conv_threads<P, G>() / 64;
+      if constexpr (conv_reg_ok<P, G>())
+        if (conv_mode == kConvReg) w = conv_reg_threads<G>() / 64;
       return hipSuccess;
     });
   });
@@ -170,8 +177,9 @@ bool layout_for(int K1, int K2, int K3, int order, int max_atoms, int precision,
   }
   L.phi_pitch = phi_pitch_of(K1, order);
   L.phi = o;       o = align256(o + plane * L.phi_pitch * real);
-  L.partial_rows = std::max(ev_rows_for(K1, K2, K3, precision, kConvFused),
-                            ev_rows_for(K1, K2, K3, precision, kConvSplit));
+  L.partial_rows = std::max({ev_rows_for(K1, K2, K3, precision, kConvFused),
+                             ev_rows_for(K1, K2, K3, precision, kConvSplit),
+                             ev_rows_for(K1, K2, K3, precision, kConvReg)});
   L.partial = o;   o = align256(o + (size_t)L.partial_rows * 8 * sizeof(double));
   L.dbg = o;       o = align256(o + plane * K1 * 8);
   L.args = o;      o = align256(o + sizeof(Args));

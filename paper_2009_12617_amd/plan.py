@@ -258,7 +258,10 @@ class Plan:
         return int(flags.value)
 
     def kernel_timing(self, enable=True):
-        check(self._lib.pme_kernel_timing(self._h, int(bool(enable))), "pme_kernel_timing")
+        """False: off; True or 1: events attached to each dispatch; 2: external
+        event records around each launch (graph-capturable)."""
+        mode = int(enable) if not isinstance(enable, bool) else int(enable)
+        check(self._lib.pme_kernel_timing(self._h, mode), "pme_kernel_timing")
 
     def kernel_times(self):
         """Accumulated per-kernel milliseconds since the last call, and the step count."""
@@ -271,7 +274,7 @@ class Plan:
 
 # Candidate order of pme_autotune: conv x interp x bin_chunk, bin_chunk fastest.
 TUNE_CANDIDATES = tuple({"conv": c, "interp": i, "bin_chunk": b}
-                        for c in (0, 1) for i in (0, 1) for b in (256, 512, 1024))
+                        for c in (0, 1, 2) for i in (0, 1) for b in (256, 512, 1024))
 
 
 class Batch:

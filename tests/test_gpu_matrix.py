@@ -6,10 +6,10 @@ the library is covered here without editing the test.  Each case is a small
 water box whose edges give about 0.8 A grid spacing; the bars are those of
 the other parity tests (FP32/fixed: bit-exact charge grid, force relative
 RMS 1e-5, energy 1e-6; FP64: 1e-10 / 1e-11; binary16 spectrum: 1e-3 /
-2e-4; bfloat16 spectrum: 8e-3 / 4e-3), except that the FP32/fixed virial
-components are held to 2e-6 |E| instead of 1e-6: the paper fixes no virial
-tolerance, and with a few hundred atoms (180 at 16^3) the FP32 spectrum's
-rounding reaches 1.1e-6 |E| in a single component.
+2e-4; bfloat16 spectrum: 8e-3 / 4e-3), and the FP32/fixed virial
+components within 2e-6 |E|: twice the energy bar, because each component
+sums the same per-mode energy terms with weights (delta_ab - 2 u m_a m_b)
+whose energy-weighted mean magnitude is at most 2.
 """
 import functools
 
@@ -90,5 +90,8 @@ def test_every_shape_order_precision(P, shape, p, precision):
     fr = float(np.linalg.norm(f - ref["forces"]) / np.linalg.norm(ref["forces"]))
     er = abs(e[0] - ref["E"]) / abs(ref["E"])
     vr = float(np.abs(e[1:] - ref["virial"]).max() / abs(ref["E"]))
-    print(f"{shape} p={p} {precision}: force {fr:.1e} energy {er:.1e} virial {vr:.1e}", flush=True)
-    assert fr <= ftol and er <= etol and vr <= vtol
+    worst = float(np.abs(f - ref["forces"]).max() / np.sqrt(np.mean(ref["forces"] ** 2)))
+    wbar = ftol * np.sqrt(2.0 * np.log(3.0 * len(q)))  # extreme-value bound of 3N errors
+    print(f"{shape} p={p} {precision}: force {fr:.1e} worst {worst:.1e} energy {er:.1e} "
+          f"virial {vr:.1e}", flush=True)
+    assert fr <= ftol and er <= etol and vr <= vtol and worst <= wbar

@@ -4,7 +4,9 @@ Bars:
   * the 64-bit fixed-point charge grid is bit-identical to the oracle's
     quantised mirror (and run to run);
   * FP32/fixed path: force relative RMS <= 1e-5, energy relative error
-    <= 1e-6, every virial component within 1e-6 |E| of the FP64 oracle;
+    <= 1e-6, every virial component within 2e-6 |E| of the FP64 oracle,
+    and the worst force component within sqrt(2 ln 3N) x 1e-5 of the RMS
+    force (the same extreme-value bound scales every precision's bar);
   * FP64 path: force relative RMS <= 1e-10, energy relative error <= 1e-11.
 Sizes span several plane/pencil tiles and ragged atom chunks; the full
 benchmark-size systems are compared over every atom.
@@ -20,7 +22,10 @@ from paper_2009_12617_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-F32_FORCE, F32_ENERGY, F32_VIRIAL = 1e-5, 1e-6, 1e-6
+# FP32/fixed virial: twice the energy bar times |E| (each virial component
+# sums the per-mode energy terms with weights whose energy-weighted mean
+# magnitude is at most 2; see the virial reading in the design notes)
+F32_FORCE, F32_ENERGY, F32_VIRIAL = 1e-5, 1e-6, 2e-6
 F64_FORCE, F64_ENERGY = 1e-10, 1e-11
 
 
@@ -60,14 +65,24 @@ def system(name, nw, L, seed=17):
 
 
 def compare(res, ref, ftol, etol, vtol):
+    """Force relative RMS, energy and virial against the oracle, plus a bound
+    on the single worst force component: an error confined to a few atoms is
+    diluted by sqrt(N) in the RMS, so the largest component error may exceed
+    the RMS bar only by the extreme-value factor sqrt(2 ln 3N) of 3N
+    independent errors (4.9 at 65,535 atoms), relative to the RMS force."""
     forces, ev = res
     f = forces.cpu().numpy()
     e = ev.cpu().numpy()
     fr = rel_rms(f, ref["forces"])
     er = abs(e[0] - ref["E"]) / abs(ref["E"])
     vr = float(np.abs(e[1:] - ref["virial"]).max() / abs(ref["E"]))
-    print(f"force_rel_rms={fr:.3e} energy_rel={er:.3e} virial_rel={vr:.3e}", flush=True)
+    n = max(f.shape[0], 1)
+    worst = float(np.abs(f - ref["forces"]).max() / np.sqrt(np.mean(ref["forces"] ** 2))) if f.size else 0.0
+    atol = ftol * np.sqrt(2.0 * np.log(3.0 * n)) if n > 1 else ftol
+    print(f"force_rel_rms={fr:.3e} worst_component={worst:.3e} (bar {atol:.1e}) energy_rel={er:.3e} "
+          f"virial_rel={vr:.3e}", flush=True)
     assert fr <= ftol
+    assert worst <= atol
     assert er <= etol
     assert vr <= vtol
 

@@ -1,10 +1,12 @@
 """Kernel variants and autotuning (pme_set_tuning, pme_autotune).
 
-Every variant computes the same step: the y/z transforms, the influence
-function and the interpolation perform the same per-element arithmetic in
-each, so forces are bit-identical across variants and energy/virial agree
-to summation order (bit-identical within one convolution variant), and each
-variant matches the FP64 oracle at the FP32 bars.  The autotuner's choice is
+Every variant computes the same step and matches the FP64 oracle at the
+FP32 bars.  The fused and split convolutions, both interpolations and every
+binning chunk perform the same per-element arithmetic, so their forces are
+bit-identical and their energy/virial agree to summation order
+(bit-identical within one convolution variant); the register-resident
+convolution factors its transforms differently (radix 8 x 8 with its own
+twiddle order), so it agrees with them to FP32 rounding.  The autotuner's choice is
 re-timed against the built-in default on the full-size workloads."""
 import ctypes
 import json
@@ -36,7 +38,7 @@ def dev(a):
 
 def variants(plan):
     v = plan.variants()
-    convs = [c for c, bit in ((0, 1), (1, 2)) if v & bit]
+    convs = [c for c, bit in ((0, 1), (1, 2), (2, 16)) if v & bit]
     interps = [i for i, bit in ((0, 4), (1, 8)) if v & bit]
     return [(c, i, b) for c in convs for i in interps for b in (256, 512, 1024)]
 
@@ -83,6 +85,11 @@ def test_every_variant_same_step(P, case):
         assert er <= (F32_ENERGY if fixed else 1e-11)
         if base is None:
             base = (c, fc, ec)
+            continue
+        if c == 2:
+            # another factorisation of the FFTs: FP32 rounding apart
+            assert np.linalg.norm(fc - base[1]) <= 2e-6 * np.linalg.norm(base[1])
+            assert abs(ec[0] - base[2][0]) <= 1e-6 * abs(base[2][0])
             continue
         if fixed:
             assert np.array_equal(fc, base[1]), (c, i, b)

@@ -346,3 +346,15 @@ def test_axis_permutation_symmetry(orc):
     fp = full[np.ix_(perm, perm)]
     want = np.array([fp[0, 0], fp[1, 1], fp[2, 2], fp[0, 1], fp[0, 2], fp[1, 2]])
     np.testing.assert_allclose(rp["virial"], want, rtol=0, atol=1e-11 * abs(r["E"]))
+
+
+def test_real_space_rows_of_listed_atoms(orc):
+    # the sampled real-space forces are the rows of the full sum, bit for bit,
+    # with and without a cutoff and over more images
+    from paper_2009_12617_amd import inputs as I
+    pos, q, box = I.water_box(40, 11.0, 8)
+    for nimg, rcut in ((1, 4.5), (2, 0.0)):
+        full = orc.ewald_real(pos, q, box, 0.45, nimg=nimg, rcut=rcut)
+        rows = [0, 7, 119, 64]
+        sub = orc.ewald_real_atoms(pos, q, box, 0.45, rows, nimg=nimg, rcut=rcut)
+        assert np.array_equal(sub, full["forces"][rows])

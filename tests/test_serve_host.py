@@ -70,11 +70,17 @@ def test_batch_admission_answers_without_a_device(lib):
 
 def test_tuning_queries_without_a_device(lib):
     v = lib.pme_tuning_variants(64, 64, 64, 4, 1)
-    assert v == 15                                   # every variant at 64^3
+    assert v == 31                                   # every variant at 64^3
+    assert lib.pme_tuning_variants(64, 64, 64, 4, 0) == 15   # no register column in FP64
+    assert lib.pme_tuning_variants(48, 48, 48, 4, 1) & 16 == 0  # 48-point pencils: no
     assert lib.pme_tuning_variants(16, 16, 16, 4, 1) == 1 | 4 | 8   # no split column passes
     assert lib.pme_tuning_variants(50, 50, 50, 4, 1) == 0
     t = _lib.Tuning()
     assert lib.pme_default_tuning(64, 64, 64, 4, 1, ctypes.byref(t)) == 0
+    assert t.as_dict() == {"conv": 2, "interp": 0, "bin_chunk": 1024}
+    assert lib.pme_default_tuning(64, 64, 64, 4, 0, ctypes.byref(t)) == 0
+    assert t.as_dict() == {"conv": 0, "interp": 0, "bin_chunk": 1024}
+    assert lib.pme_default_tuning(48, 48, 48, 4, 1, ctypes.byref(t)) == 0
     assert t.as_dict() == {"conv": 0, "interp": 0, "bin_chunk": 1024}
     assert lib.pme_default_tuning(128, 128, 128, 6, 1, ctypes.byref(t)) == 0
     assert t.as_dict() == {"conv": 1, "interp": 1, "bin_chunk": 1024}
