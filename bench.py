@@ -9,9 +9,10 @@ function + energy/virial + inverse z/y FFTs, inverse x FFT + force
 interpolation: four launches) on the next frame, stream-ordered after the
 previous one; the timed region replays one HIP graph of all timed steps.
 
-Prints one JSON line.  Beside the headline: per-kernel times from a graph
-replay with event nodes between the launches (the roofline entry is the
-dominant kernel's), the autotuner's table for the workload, the plain FP64
+Prints one JSON line.  Beside the headline: per-kernel times inside graph
+replay, by difference against steps that launch one kernel twice (the
+roofline entry is the dominant kernel's; `--profile` runs only those graph
+replays, for rocprofv3), the autotuner's table for the workload, the plain FP64
 path and the binary16/bfloat16 spectra on the same frames, per-step latency,
 the real-space term, the 64x64x128 and 128^3 workloads, the 64-system batch
 (batch admission API, grid groups on forked streams), serving at the
@@ -171,33 +172,92 @@ def run_graph(torch, dev, plan, fr, steps, warmup, exact=True):
     return ms, wall / steps * 1e3, ok
 
 
-def kernel_slots(torch, dev, plan, fr, steps, first=0):
-    """Per-kernel time of graph-replayed steps: external event nodes recorded
-    before and after every launch (pme_kernel_timing mode 2, no events on
-    the dispatches themselves); microseconds per step per kernel."""
+def graph_us(torch, dev, plan, fr, steps, repeat, first=0, reps=3):
+    """Microseconds per step of one replayed graph of `steps` probe steps
+    (pme_step_probe with kernel `repeat` launched twice; 0: plain steps),
+    best of `reps` replays."""
     forces = torch.empty((fr.N, 3), dtype=torch.float64, device=dev)
     ev = torch.empty(7, dtype=torch.float64, device=dev)
-    plan.kernel_timing(2)
-    g = capture(torch, dev, plan, fr, first, steps, forces, ev)
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream(device=dev)
+    with torch.cuda.graph(g, stream=cs):
+        plan.set_stream(torch.cuda.current_stream(dev))
+        for t in range(steps):
+            plan.step_probe(fr.pos(first + t), fr.dev_q, fr.box, forces, ev, repeat)
+    plan.set_stream(torch.cuda.current_stream(dev))
     g.replay()
     torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    kms, ksteps = plan.kernel_times()
-    plan.kernel_timing(False)
+    stream = torch.cuda.current_stream(dev)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        g.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e3 / steps)
     del g
-    return {k: v / max(ksteps, 1) * 1e3 for k, v in kms.items()}
+    return best
 
 
-def roofline_entry(N, K, kus, traffic_fn=None):
+def kernel_times(torch, dev, plan, fr, steps):
+    """Per-kernel time inside graph-replayed steps, by difference: replays of
+    steps that launch one kernel a second time (pme_step_probe; the results
+    are unchanged) against replays of plain steps, timed with events around
+    each replay.  Binning is repeated together with a one-workgroup clearing
+    launch, which is timed alone and subtracted.  Microseconds per launch."""
+    from paper_2009_12617_amd.plan import PROBE
+    base = graph_us(torch, dev, plan, fr, steps, PROBE["none"])
+    t = {k: graph_us(torch, dev, plan, fr, steps, PROBE[k]) - base
+         for k in ("spread_x", "convolve_yz", "interpolate", "bin", "clear")}
+    out = {"bin": t["bin"] - t["clear"], "spread_x": t["spread_x"], "convolve_yz": t["convolve_yz"],
+           "interpolate": t["interpolate"]}
+    # leave the plan with a whole step done
+    plan.step(fr.pos(0), fr.dev_q, fr.box)
+    torch.cuda.synchronize()
+    return out, base
+
+
+def profiled_kernel_us(workload="water_65535_k64"):
+    """Per-kernel average durations (us per launch slot) from the committed
+    rocprofv3 summary of this workload, or None when it is missing or was
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if line.startswith("BENCH_KERNELS_JSON "):
+            d = json.loads(line.split(" ", 1)[1])
+            if d.get("source_digest") != source_digest():
+                return None
+            return d.get("kernels_us")
+    return None
+
+
+def roofline_entry(N, K, live_us, traffic_fn=None, profiled=None):
+    """The dominant kernel's achieved algorithmic bandwidth.  Its duration is
+    the rocprofv3 average of the committed profile when that profile was
+    taken on the current kernel sources, else the live graph-replay time;
+    both are reported."""
+    kus = profiled if profiled else live_us
     dom = max(kus, key=kus.get)
     b = algorithmic_bytes(N, K, dom)
     achieved = b / (kus[dom] * 1e-6) / 1e9
-    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_fn(dom) if traffic_fn else None,
-            "algorithmic_bytes_per_launch": b, "kernel_us": kus[dom],
-            "timing": "graph replay, external event nodes around each launch"}
+    out = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": traffic_fn(dom) if traffic_fn else None,
+           "algorithmic_bytes_per_launch": b, "kernel_us": kus[dom],
+           "duration_source": ("rocprofv3 kernel statistics of the committed profile "
+                               "(same kernel sources)" if profiled else
+                               "live: graph-replayed steps repeating the kernel minus plain steps"),
+           "live_kernel_us": live_us,
+           "live_frac": {k: algorithmic_bytes(N, K, k) / (v * 1e-6) / 1e9 / HBM_PEAK_GBS
+                         for k, v in live_us.items()}}
+    if profiled:
+        out["profiled_kernel_us"] = profiled
+    return out
 
 
 def graph_latency(torch, dev, plan, fr, steps):
@@ -221,8 +281,8 @@ def graph_latency(torch, dev, plan, fr, steps):
 def bench_system(torch, dev, Plan, I, pos, q, box, K, order, beta, steps, warmup, name,
                  jitter_seed):
     """One more single-system workload, FP32/fixed path: one graph of `steps`
-    steps over 16 jittered frames, per-kernel times from a graph with event
-    nodes around the launches, each kernel's algorithmic GB/s against
+    steps over 16 jittered frames, per-kernel times by difference of
+    graph-replayed probe steps, each kernel's algorithmic GB/s against
     8 TB/s; returns the last frame's forces for the oracle leg."""
     class F:
         pass
@@ -234,7 +294,7 @@ def bench_system(torch, dev, Plan, I, pos, q, box, K, order, beta, steps, warmup
     fr.pos = lambda t: fr.dev_pos[t % fr.F]
     plan = Plan(K, order, beta, max_atoms=fr.N, device=dev)
     ms, _, same = run_graph(torch, dev, plan, fr, steps, warmup)
-    kus = kernel_slots(torch, dev, plan, fr, min(steps, 50))
+    kus, _ = kernel_times(torch, dev, plan, fr, min(steps, 100))
     kfrac = {k: algorithmic_bytes(fr.N, K, k) / (kus[k] * 1e-6) / 1e9 / HBM_PEAK_GBS for k in kus}
     last = (warmup + steps - 1) % fr.F
     fe, ee = plan.step(fr.pos(last), fr.dev_q, box)
@@ -529,7 +589,7 @@ def main():
     ap.add_argument("--no-half", action="store_true", help="skip the binary16- and bfloat16-spectrum variants")
     ap.add_argument("--no-real", action="store_true", help="skip the real-space term")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for a profiler: the headline graph replays only")
+                    help="for a profiler: only the headline's graph replays of plain and probe steps")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched run")
     ap.add_argument("--no-noncubic", action="store_true", help="skip the 64 x 64 x 128 grid run")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 (209,715-atom) runs")
@@ -571,18 +631,13 @@ def main():
           f"{torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
 
     plan = Plan(K, w.order, w.beta, max_atoms=N, precision="fp32_fixed", device=dev)
-    ms_step, wall_ms, graph_ok = run_graph(torch, dev, plan, fr, args.steps, args.warmup)
-    print(f"# fp32_fixed graph replay: {ms_step * 1e3:.2f} us/step, replay == eager: {graph_ok}",
-          file=sys.stderr, flush=True)
-    if not graph_ok:
-        print("bench.py: graph replay differs from host-launched steps", file=sys.stderr)
-        sys.exit(1)
-    kus = kernel_slots(torch, dev, plan, fr, min(args.steps, 100))
-    print("# per-kernel us (graph replay): " + ", ".join(f"{k}={v:.2f}" for k, v in kus.items()),
-          file=sys.stderr, flush=True)
-    roof = roofline_entry(N, K, kus, measured_traffic)
-    kfrac = {k: algorithmic_bytes(N, K, k) / (kus[k] * 1e-6) / 1e9 / HBM_PEAK_GBS for k in kus}
     if args.profile:
+        # for a profiler: the headline's graph replays (plain steps and the
+        # probe steps of the per-kernel times) and nothing else
+        for t in range(args.warmup):
+            plan.step(fr.pos(t), fr.dev_q, fr.box)
+        torch.cuda.synchronize()
+        kus, base = kernel_times(torch, dev, plan, fr, args.steps)
         if args.copy_mib > 0:
             n = args.copy_mib * (1 << 20) // 8
             src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -592,11 +647,22 @@ def main():
             torch.cuda.synchronize()
             print(f"# calibration copy: {args.copy_mib} MiB read + {args.copy_mib} MiB written",
                   file=sys.stderr, flush=True)
-        print(json.dumps({"metric": "us/PME step (65,535 atoms, 64^3)", "value": ms_step * 1e3,
-                          "unit": "us/step", "mode": "profile", "kernels_us": kus,
-                          "roofline": roof, "source_digest": source_digest()}))
+        print(json.dumps({"mode": "profile", "steps": args.steps, "us_per_step": base,
+                          "kernels_us": kus, "tuning": plan.tuning, "source_digest": source_digest()}))
         return
-
+    ms_step, wall_ms, graph_ok = run_graph(torch, dev, plan, fr, args.steps, args.warmup)
+    print(f"# fp32_fixed graph replay: {ms_step * 1e3:.2f} us/step, replay == eager: {graph_ok}",
+          file=sys.stderr, flush=True)
+    if not graph_ok:
+        print("bench.py: graph replay differs from host-launched steps", file=sys.stderr)
+        sys.exit(1)
+    kus, _ = kernel_times(torch, dev, plan, fr, 100)
+    print("# per-kernel us (graph replay, by difference): " + ", ".join(f"{k}={v:.2f}" for k, v in kus.items()),
+          file=sys.stderr, flush=True)
+    prof = profiled_kernel_us()
+    roof = roofline_entry(N, K, kus, measured_traffic, prof)
+    kfrac = {k: algorithmic_bytes(N, K, k) / (v * 1e-6) / 1e9 / HBM_PEAK_GBS
+             for k, v in (prof or kus).items()}
     lat = graph_latency(torch, dev, plan, fr, min(args.steps, 1000))
     tuned = None
     if not args.no_autotune:
@@ -775,6 +841,8 @@ def main():
         "host_wall_us_per_step": wall_ms * 1e3,
         "timed_region": "one HIP graph replay of all timed steps (captured pme_step calls)",
         "kernels_us": kus,
+        "kernels_us_what": "live: graph-replayed steps repeating the kernel minus plain steps",
+        "kernels_us_profiled": prof,
         "kernels_roofline_frac": kfrac,
         "roofline": roof,
         "step_roofline_frac": step_bytes(N, K) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,

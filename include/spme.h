@@ -356,21 +356,43 @@ size_t pme_debug_grid_bytes(pme_plan *plan, int which);
  * was set, else PME_OK. */
 int pme_check(pme_plan *plan, unsigned *flags);
 
+/* Timing diagnostics for graph-replayed steps: pme_step (overwriting the
+ * forces) with one kernel launched a second time where that leaves the
+ * step's forces, energy and virial unchanged --
+ *   PME_PROBE_SPREAD  spreading + x transform again right after the first
+ *   PME_PROBE_INTERP  inverse x transform + interpolation again at the end
+ *   PME_PROBE_CONV    the y/z convolution again at the end, on the spectrum
+ *                     the next spread rewrites (a pme_gather after it
+ *                     returns PME_ESTATE)
+ *   PME_PROBE_BIN     binning again at the end, then its bucket counts
+ *                     cleared for the next step (a one-workgroup launch)
+ *   PME_PROBE_CLEAR   that clearing launch alone
+ * so that the difference between replays of captured probe steps and of
+ * plain steps is the repeated kernel's time in the step's stream (for
+ * binning, the PME_PROBE_BIN difference less the PME_PROBE_CLEAR one).
+ * Enqueues kernel launches only (capturable). */
+#define PME_PROBE_NONE 0
+#define PME_PROBE_BIN 1
+#define PME_PROBE_SPREAD 2
+#define PME_PROBE_CONV 3
+#define PME_PROBE_INTERP 4
+#define PME_PROBE_CLEAR 5
+int pme_step_probe(pme_plan *plan, const double *pos, const double *q, int N,
+                   const double box[9], double *forces, double *ev, int repeat);
+
 /* Per-kernel timing with HIP events on the plan's stream (off by default).
- * enable 1: every launch carries a start and a stop event attached to the
- * dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
- * own execution.  enable 2: external events are recorded on the stream
- * before and after every launch (hipEventRecordWithFlags with
- * hipEventRecordExternal), which stream capture keeps as event nodes, so the
- * steps of a captured graph are timed kernel by kernel at replay (capture,
- * replay once, then read the times; the events are reused after that).
- * Changing the mode drops unread times.  pme_kernel_times
+ * While enabled every launch carries a start and a stop event attached to
+ * the dispatch itself (hipExtLaunchKernel), so the elapsed time is the
+ * kernel's own execution, the interval a profiler reports for the dispatch
+ * (host-launched steps; not for stream capture).  Changing the setting drops
+ * unread times.  pme_kernel_times
  * synchronises, adds the elapsed times of all completed launches into
  * ms[0..n-1] (kernel order: 0 bin, 1 spread + x FFT, 2 y/z FFTs with the
  * influence function and the inverse z/y FFTs, 3 inverse x FFT + force
  * interpolation) and returns the number of steps accumulated in *steps.
- * Where the y/z work takes three launches (K2 K3 >= 8192), slot 2 runs from
- * the start of the first to the end of the last, gaps included. */
+ * Where a slot takes several launches (the split convolution, the split
+ * interpolation), it runs from the start of the first to the end of the
+ * last, gaps included. */
 int pme_kernel_timing(pme_plan *plan, int enable);
 int pme_kernel_times(pme_plan *plan, double *ms, int n, int *steps);
 

@@ -147,6 +147,8 @@ def load():
     lib.pme_batch_stats.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.pme_batch_plan.restype = vp
     lib.pme_batch_plan.argtypes = [vp, i]
+    lib.pme_step_probe.restype = i
+    lib.pme_step_probe.argtypes = [vp, vp, vp, i, dp, vp, vp, i]
     lib.pme_step_noalloc.restype = i
     lib.pme_step_noalloc.argtypes = [i, i, i, i, d, i, i, d, vp, vp, i, dp, vp, i, vp, vp]
     _lib = lib

@@ -82,10 +82,8 @@ hipEvent_t next_event(pme_plan* p) {
   return p->event_pool[p->event_next++];
 }
 
-// Run one launch; with timing on, events are attached to the dispatch
-// (mode 1) or recorded on the stream around it as external events, which a
-// graph capture keeps as event nodes (mode 2), and queued for
-// pme_kernel_times.
+// Run one launch; with timing on, events are attached to the dispatch and
+// queued for pme_kernel_times.
 template <class F>
 int timed(pme_plan* p, int kernel, F&& launch) {
   if (!p->timing) return device_error(launch(spme::Timing()));
@@ -93,14 +91,7 @@ int timed(pme_plan* p, int kernel, F&& launch) {
   t.start = next_event(p);
   t.stop = next_event(p);
   if (!t.start || !t.stop) return PME_EDEVICE;
-  if (p->timing == 2) {
-    if (hipEventRecordWithFlags(t.start, p->stream, hipEventRecordExternal) != hipSuccess ||
-        launch(spme::Timing()) != hipSuccess ||
-        hipEventRecordWithFlags(t.stop, p->stream, hipEventRecordExternal) != hipSuccess)
-      return PME_EDEVICE;
-  } else if (launch(t) != hipSuccess) {
-    return PME_EDEVICE;
-  }
+  if (launch(t) != hipSuccess) return PME_EDEVICE;
   p->pending.push_back({kernel, t.start, t.stop});
   return PME_OK;
 }
@@ -419,6 +410,44 @@ int pme_step(pme_plan* p, const double* pos, const double* q, int N, const doubl
   return rc;
 }
 
+int pme_step_probe(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
+                   double* forces, double* ev, int repeat) {
+  if (p == nullptr) return PME_EINVAL;
+  if (repeat < PME_PROBE_NONE || repeat > PME_PROBE_CLEAR) return PME_EINVAL;
+  if (N > 0 && forces == nullptr) return PME_EINVAL;
+  int rc = pme_spread(p, pos, q, N, box);
+  if (rc == PME_OK && repeat == PME_PROBE_SPREAD)
+    rc = device_error(spme::launch_spread_x(p->cur, p->stream));
+  if (rc == PME_OK) rc = solve_impl(p, ev, true);
+  if (rc == PME_OK) rc = gather_impl(p, forces, 0);
+  if (rc != PME_OK) return rc;
+  const Args& a = p->cur;
+  switch (repeat) {
+    case PME_PROBE_INTERP:
+      // the same forces again (the energy rows were already summed)
+      rc = device_error(spme::launch_interp(a, p->stream));
+      break;
+    case PME_PROBE_CONV:
+      // on the spectrum the interpolation has used; the next spread rewrites
+      // it, and the counts it moves on are already zero
+      rc = device_error(spme::launch_conv(a, p->stream));
+      p->state = kDirty;
+      break;
+    case PME_PROBE_BIN:
+      // binning into the buckets the interpolation has used, its counts
+      // cleared again for the next step
+      rc = device_error(spme::launch_bin(a, p->stream));
+      if (rc == PME_OK) rc = device_error(spme::launch_clear_counts(a, p->stream));
+      break;
+    case PME_PROBE_CLEAR:
+      rc = device_error(spme::launch_clear_counts(a, p->stream));
+      break;
+    default:
+      break;
+  }
+  return rc;
+}
+
 int pme_bind(pme_plan* p, const double* pos, const double* q, int N, const double box[9],
              double* forces, int accumulate, double* ev) {
   if (p == nullptr) return PME_EINVAL;
@@ -666,8 +695,8 @@ int pme_check(pme_plan* p, unsigned* flags) {
 }
 
 int pme_kernel_timing(pme_plan* p, int enable) {
-  if (p == nullptr || enable < 0 || enable > 2) return PME_EINVAL;
-  p->timing = enable;
+  if (p == nullptr) return PME_EINVAL;
+  p->timing = enable ? 1 : 0;
   p->pending.clear();
   p->event_next = 0;
   p->timed_steps = 0;

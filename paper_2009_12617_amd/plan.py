@@ -14,6 +14,8 @@ from ._lib import (PME_EBUSY, PME_FP32_FIXED, PME_FP32_FIXED_BF16, PME_FP32_FIXE
                    SystemDesc, Tuning, check)
 
 KERNEL_NAMES = ("bin", "spread_x", "convolve_yz", "interpolate")
+# pme_step_probe: which kernel a probe step launches twice
+PROBE = {"none": 0, "bin": 1, "spread_x": 2, "convolve_yz": 3, "interpolate": 4, "clear": 5}
 PRECISIONS = {"fp32_fixed": PME_FP32_FIXED, "fp64": PME_FP64,
               "fp32_fixed_half": PME_FP32_FIXED_HALF, "fp32_fixed_bf16": PME_FP32_FIXED_BF16}
 
@@ -154,6 +156,20 @@ class Plan:
               "pme_step")
         return forces, ev
 
+    def step_probe(self, pos, q, box, forces, ev, repeat):
+        """pme_step_probe: a step with one kernel launched twice (timing
+        diagnostics; repeat is one of PROBE)."""
+        n = int(q.shape[0])
+        _dev_f64(pos, (n, 3), "pos")
+        _dev_f64(q, (n,), "q")
+        _dev_f64(forces, (n, 3), "forces")
+        _dev_f64(ev, (7,), "ev")
+        self._keep = (pos, q)
+        self._n = n
+        check(self._lib.pme_step_probe(self._h, pos.data_ptr(), q.data_ptr(), n, _box9(box),
+                                       forces.data_ptr(), ev.data_ptr(), int(repeat)),
+              "pme_step_probe")
+
     def bind(self, pos, q, box, forces=None, ev=None, accumulate=False):
         """Bind the buffers of this plan's batched steps (see Batch); returns (forces, ev)."""
         n = int(q.shape[0])
@@ -258,10 +274,8 @@ class Plan:
         return int(flags.value)
 
     def kernel_timing(self, enable=True):
-        """False: off; True or 1: events attached to each dispatch; 2: external
-        event records around each launch (graph-capturable)."""
-        mode = int(enable) if not isinstance(enable, bool) else int(enable)
-        check(self._lib.pme_kernel_timing(self._h, mode), "pme_kernel_timing")
+        """Events attached to every dispatch (host-launched steps)."""
+        check(self._lib.pme_kernel_timing(self._h, int(bool(enable))), "pme_kernel_timing")
 
     def kernel_times(self):
         """Accumulated per-kernel milliseconds since the last call, and the step count."""
