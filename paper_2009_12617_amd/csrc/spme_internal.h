@@ -10,7 +10,10 @@ namespace spme {
 constexpr int kBinThreads = 1024;    // largest binning chunk (one atom per thread)
 constexpr int kMinChunk = 256;       // smallest binning chunk
 constexpr int kMaxBins = 2048;       // (z, y slice, head/body) bins: 2 K3 nq <= 2048
-constexpr int kSpreadThreads = 512;  // one y slice of one z-plane per workgroup
+// threads of a spreading tile (one y slice of one z-plane per workgroup):
+// 1024 for one system (halves each thread's chain of records), 512 for
+// batched launches (where many tiles share each CU, measured faster)
+constexpr int kSpreadThreads = 1024, kSpreadThreadsBatch = 512;
 constexpr int kPlaneThreads = 512;   // one z-plane per workgroup (debug potential copy)
 constexpr int kInterpThreads = 512;  // one (z-plane, y slice) bin per workgroup
 constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950

@@ -329,9 +329,15 @@ __device__ __forceinline__ void spread_atom(typename P::acc* tile, const typenam
   }
 }
 
+template <bool BATCH>
+__host__ __device__ constexpr int spread_threads() {
+  return BATCH ? kSpreadThreadsBatch : kSpreadThreads;
+}
+
 template <class P, class G, int ORDER, bool BATCH>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArgs bt) {
+__global__ __launch_bounds__(spread_threads<BATCH>()) void k_spread_x(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
+  constexpr int NTS = spread_threads<BATCH>();
   using T = typename P::real;
   using Acc = typename P::acc;
   using Rec = typename P::rec;
@@ -376,8 +382,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
                          (unsigned)a.lay.orec_max);
   }
   const cplx<T>* twg = reinterpret_cast<const cplx<T>*>(a.ws + a.lay.tw);
-  for (int i = tid; i < K1; i += kSpreadThreads) tw[i] = twg[i];
-  for (int i = tid; i < R * PITCH; i += kSpreadThreads) tile[i] = Acc(0);
+  for (int i = tid; i < K1; i += NTS) tw[i] = twg[i];
+  for (int i = tid; i < R * PITCH; i += NTS) tile[i] = Acc(0);
   const double scale = ldexp(1.0, a.frac_bits);
   __syncthreads();
   if (tid == 0) {
@@ -398,11 +404,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   int pre[NBK + 1];
 #pragma unroll
   for (int k = 0; k <= NBK; ++k) pre[k] = bk_pre[k];
-  for (int it = 0; it < total; it += kItems * kSpreadThreads) {
+  for (int it = 0; it < total; it += kItems * NTS) {
     int idx[kItems], jz[kItems];
 #pragma unroll
     for (int u = 0; u < kItems; ++u) {
-      const int t = it + u * kSpreadThreads + tid;
+      const int t = it + u * NTS + tid;
       jz[u] = -1;
       idx[u] = 0;
       if (t < total) {
@@ -424,7 +430,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   // atoms of full buckets: the whole overflow list, each atom taken if it
   // belongs to this tile
   const int novf = bk_n[NBK];
-  for (int o = tid; o < novf; o += kSpreadThreads) {
+  for (int o = tid; o < novf; o += NTS) {
     const Rec r = orec[o];
     const int gy = (r.g >> 10) & 1023, gz = (r.g >> 20) & 1023;
     int j = gz - z;
@@ -440,13 +446,13 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
 
   if (a.keep_grid) {
     Acc* dbg = reinterpret_cast<Acc*>(a.ws + a.lay.dbg) + ((size_t)z * K2 + y0) * K1;
-    for (int i = tid; i < R * K1; i += kSpreadThreads) dbg[i] = tile[(i / K1) * PITCH + (i % K1)];
+    for (int i = tid; i < R * K1; i += NTS) dbg[i] = tile[(i / K1) * PITCH + (i % K1)];
     __syncthreads();  // the x transform below overwrites the tile in place
   }
 
   // --- x: real-to-complex, one row per group of fft_lanes(M) lanes.
   constexpr int TM = fft_lanes(M);
-  for (int task = tid; task < R * TM; task += kSpreadThreads) {
+  for (int task = tid; task < R * TM; task += NTS) {
     const int y = task / TM, l = task - y * TM;
     cplx<T>* row = reinterpret_cast<cplx<T>*>(tile + y * PITCH);
     if constexpr (P::fixed) {
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_x(Args a_in, BatchArg
   S* spec = reinterpret_cast<S*>(a.ws + a.lay.spec) + (size_t)z * K2 + y0;
   constexpr int PC = P::fixed ? PITCH : PITCH / 2;
   const cplx<T>* tc = reinterpret_cast<const cplx<T>*>(tile);
-  for (int i = tid; i < R * KH; i += kSpreadThreads) {
+  for (int i = tid; i < R * KH; i += NTS) {
     const int x = i / R, y = i - x * R;
     spec_st(&spec[(size_t)x * K3 * K2 + y], tc[y * PC + x]);
   }
@@ -1068,19 +1074,40 @@ __host__ __device__ constexpr size_t conv_reg_lds_bytes() {
          (size_t)(G::K1 + G::K2 + G::K3) * sizeof(double) + 16 * 8 * sizeof(double);
 }
 
+// The twiddles lane j (< R) of a register-resident N-point transform
+// (N = 8 R) uses, kept in registers: wf[s] = W^(j s), s < 8, for the forward
+// direction and wi[eR + l] = W^(l (jE + e)), l < R, e < E = 8/R, for the
+// inverse one, W = exp(-2 pi i / N) from the table tw[k] = W^k (for R = 8 the
+// two sets coincide).
+template <typename T, int N>
+struct RegTw {
+  static constexpr int R = N / 8, E = 8 / R;
+  cplx<T> wf[8], wi[8];
+  __device__ __forceinline__ void load(int j, const cplx<T>* tw) {
+#pragma unroll
+    for (int s = 1; s < 8; ++s) wf[s] = tw[j * s];
+    if constexpr (R == 8) {
+#pragma unroll
+      for (int l = 1; l < 8; ++l) wi[l] = wf[l];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int l = 1; l < R; ++l) wi[e * R + l] = tw[l * (j * E + e)];
+    }
+  }
+};
+
 // Forward (S = -1) or inverse (S = +1) N-point DFT, N = 8 R, of the pencil
 // whose points j + R r (r < 8) lane j (< R) holds in v[r]; on return v[eR + t]
 // holds mode jE + e + 8t.  scr: the pencil's LDS scratch (R rows of pitch
-// 9, starting at the pencil's first lane x 9); tw[k] = exp(-2 pi i k / N).
+// 9, starting at the pencil's first lane x 9); w: the lane's twiddles.
 template <typename T, int N, int S>
-__device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const cplx<T>* tw) {
+__device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
   constexpr int R = N / 8, E = 8 / R;
   Dft<8, S, T>::run(v);
 #pragma unroll
-  for (int s = 1; s < 8; ++s) {
-    const cplx<T> w = tw[j * s];
-    v[s] = S < 0 ? c_mul(v[s], w) : c_mulc(v[s], w);
-  }
+  for (int s = 1; s < 8; ++s) v[s] = S < 0 ? c_mul(v[s], w.wf[s]) : c_mulc(v[s], w.wf[s]);
 #pragma unroll
   for (int s = 0; s < 8; ++s) scr[j * 9 + s] = v[s];
   lds_order();
@@ -1096,17 +1123,14 @@ __device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const 
 // The inverse direction of rfft_fwd's layouts: v[eR + t] holds mode
 // jE + e + 8t on entry; on return v[r] holds point j + R r.
 template <typename T, int N, int S>
-__device__ __forceinline__ void rfft_inv(cplx<T>* v, int j, cplx<T>* scr, const cplx<T>* tw) {
+__device__ __forceinline__ void rfft_inv(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
   constexpr int R = N / 8, E = 8 / R;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     Dft<R, S, T>::run(v + e * R);
-    const int s = j * E + e;
 #pragma unroll
-    for (int l = 1; l < R; ++l) {
-      const cplx<T> w = tw[l * s];
-      v[e * R + l] = S < 0 ? c_mul(v[e * R + l], w) : c_mulc(v[e * R + l], w);
-    }
+    for (int l = 1; l < R; ++l)
+      v[e * R + l] = S < 0 ? c_mul(v[e * R + l], w.wi[e * R + l]) : c_mulc(v[e * R + l], w.wi[e * R + l]);
   }
 #pragma unroll
   for (int e = 0; e < E; ++e)
@@ -1136,6 +1160,7 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
   double* bs = reinterpret_cast<double*>(twz + K3);         // x, y, z factors
   double* wred = bs + K1 + K2 + K3;
   const int tid = threadIdx.x;
+  TRACE(2, 0);
   if (blockIdx.x == KH) {
     keep_counts<P, G, NT>(a, wred);
     return;
@@ -1154,15 +1179,27 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
   for (int i = tid; i < K2 + K3; i += NT) twy[i] = twg[K1 + i];
   axis_factors<G, NT>(a, bs);
   __syncthreads();
+  TRACE(2, 1);
+  // each lane's twiddles for both directions (shared by the two passes when
+  // the y and z pencils have one length)
+  RegTw<T, K2> wy;
+  wy.load(tid % RY, twy);
+  RegTw<T, K3> wz_own;
+  if constexpr (K2 != K3) wz_own.load(tid % RZ, twz);
+  const RegTw<T, K3>& wz = [&]() -> const RegTw<T, K3>& {
+    if constexpr (K2 == K3) return wy;
+    else return wz_own;
+  }();
   {
     const int z = tid / RY, j = tid - z * RY;
-    rfft_fwd<T, K2, -1>(v, j, scr0 + (tid - j) * 9, twy);
+    rfft_fwd<T, K2, -1>(v, j, scr0 + (tid - j) * 9, wy);
 #pragma unroll
     for (int e = 0; e < EY; ++e)
 #pragma unroll
       for (int t = 0; t < RY; ++t) buf[z * PB + j * EY + e + 8 * t] = v[e * RY + t];
   }
   __syncthreads();
+  TRACE(2, 2);
 
   // --- z: forward transform, influence function, inverse transform
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -1170,7 +1207,7 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
     const int y = tid / RZ, j = tid - y * RZ;
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = buf[(j + RZ * r) * PB + y];
-    rfft_fwd<T, K3, -1>(v, j, scr0 + (tid - j) * 9, twz);
+    rfft_fwd<T, K3, -1>(v, j, scr0 + (tid - j) * 9, wz);
     const InflCol c = infl_col<G>(a, xp, bs);
     if (a.triclinic) {
 #pragma unroll
@@ -1217,11 +1254,12 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
       acc[5] = c.nx * sz;
       acc[6] = ny * sz;
     }
-    rfft_inv<T, K3, 1>(v, j, scr0 + (tid - j) * 9, twz);
+    rfft_inv<T, K3, 1>(v, j, scr0 + (tid - j) * 9, wz);
 #pragma unroll
     for (int r = 0; r < 8; ++r) buf[(j + RZ * r) * PB + y] = v[r];
   }
   __syncthreads();
+  TRACE(2, 3);
 
   // --- inverse y, stored back to the column
   {
@@ -1230,11 +1268,13 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
     for (int e = 0; e < EY; ++e)
 #pragma unroll
       for (int t = 0; t < RY; ++t) v[e * RY + t] = buf[z * PB + j * EY + e + 8 * t];
-    rfft_inv<T, K2, 1>(v, j, scr0 + (tid - j) * 9, twy);
+    rfft_inv<T, K2, 1>(v, j, scr0 + (tid - j) * 9, wy);
 #pragma unroll
     for (int r = 0; r < 8; ++r) spec_st(&col[(size_t)z * K2 + j + RY * r], v[r]);
   }
+  TRACE(2, 4);
   ev_row(a, acc, xp * (NT / 64) + (tid >> 6));
+  TRACE(2, 15);
 }
 
 // Sum of the energy/virial partial rows the step's convolution variant wrote,
@@ -1717,7 +1757,7 @@ hipError_t launch_spread_x_p(const Args& a, hipStream_t s, const Timing& t, cons
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
         return launch(k_spread_x<P, G, O, B>, dim3(G::K3 * nq_of(G::K2, P::fixed)),
-                      dim3(kSpreadThreads), spread_lds_bytes<P, G>(), s, t, a, bt);
+                      dim3(spread_threads<B>()), spread_lds_bytes<P, G>(), s, t, a, bt);
       });
     });
   });

@@ -17,6 +17,7 @@ Latency is the host time from a request's scheduled arrival to the moment
 its forces and energy are in host memory.
 """
 from dataclasses import dataclass, field
+import gc
 import time
 
 import numpy as np
@@ -38,16 +39,16 @@ class PoolSystem:
 
 class Slot:
     """A resident system: its batch slot, device buffers and pinned host
-    buffers for the results."""
+    buffers for the results (taken from the server's per-system cache:
+    page-locking host memory takes milliseconds, so it never happens inside
+    the request loop once a system has been seen)."""
 
-    def __init__(self, system_id, slot, pool, sysd, footprint):
-        n = len(sysd.q)
+    def __init__(self, system_id, slot, pool, sysd, footprint, host_bufs):
         self.system_id = system_id
         self.slot = slot
         self.pos, self.q, self.forces, self.ev = pool.io(slot)
         self.q.copy_(torch.from_numpy(np.ascontiguousarray(sysd.q)), non_blocking=False)
-        self.host_f = torch.empty((n, 3), dtype=torch.float64, pin_memory=True)
-        self.host_ev = torch.empty(7, dtype=torch.float64, pin_memory=True)
+        self.host_f, self.host_ev = host_bufs
         self.footprint = footprint
         self.busy = False
         self.last_used = 0.0
@@ -128,12 +129,30 @@ class Server:
         self.inputs = [torch.from_numpy(np.ascontiguousarray(p.pos)).pin_memory() for p in self.pool]
         self.resident = 0
         self.stats = ServeStats()
+        # completion events, recycled: creating one inside the loop can stall
+        # the host for milliseconds when the runtime grows its signal pool
+        self._events = [torch.cuda.Event() for _ in range(256)]
+        self.host_cache = {}
         if prewarm:
-            # one resident slot per pool system while the arena holds them
-            for i in range(len(self.pool)):
-                if self._new_slot(i, evict=False) is None:
+            # resident slots for the pool while the arena holds them (one per
+            # system, then a second, ...), each run once with its inputs in
+            # place so that no kernel is loaded and no host memory is pinned
+            # for the first time inside the timed loop
+            full = False
+            for k in range(self.slots_per_system):
+                for i in range(len(self.pool)):
+                    sl = self._new_slot(i, evict=False)
+                    if sl is None:
+                        full = True
+                        break
+                    with torch.cuda.stream(self.compute):
+                        sl.pos.copy_(self.inputs[i])
+                    self.stats.slots_prewarmed += 1
+                if full:
                     break
-                self.stats.slots_prewarmed += 1
+            resident = [sl.slot for lst in self.slots.values() for sl in lst]
+            if resident:
+                self.batch.launch(resident)
             torch.cuda.synchronize(self.device)
             self.stats.slots_created = 0
 
@@ -158,12 +177,27 @@ class Server:
                                         precision=self.precision)
             if slot is None:
                 return None
-            s = Slot(system_id, slot, self.batch, sysd, self.fp[system_id])
+            s = Slot(system_id, slot, self.batch, sysd, self.fp[system_id],
+                     self._host_bufs(system_id))
         self.slots[system_id].append(s)
         self.resident += s.footprint
         self.stats.slots_created += 1
         self.stats.peak_resident_bytes = max(self.stats.peak_resident_bytes, self.resident)
         return s
+
+    def _host_bufs(self, system_id):
+        """Pinned result buffers for a new slot of this system: one of the
+        system's cached pairs that no live slot holds, else a new pair."""
+        cache = self.host_cache.setdefault(system_id, [])
+        held = {id(sl.host_f) for sl in self.slots[system_id]}
+        for pair in cache:
+            if id(pair[0]) not in held:
+                return pair
+        n = len(self.pool[system_id].q)
+        pair = (torch.empty((n, 3), dtype=torch.float64, pin_memory=True),
+                torch.empty(7, dtype=torch.float64, pin_memory=True))
+        cache.append(pair)
+        return pair
 
     def _free_slot(self, system_id):
         for s in self.slots[system_id]:
@@ -186,9 +220,12 @@ class Server:
         req.admitted = now
         with torch.cuda.stream(self.copy):
             s.pos.copy_(self.inputs[req.system_id], non_blocking=True)
-            req.h2d = torch.cuda.Event()
+            req.h2d = self._event()
             req.h2d.record(self.copy)
         return True
+
+    def _event(self):
+        return self._events.pop() if self._events else torch.cuda.Event()
 
     def _keep(self, rid):
         k = self.keep_forces
@@ -200,6 +237,17 @@ class Server:
         Raises if no request completes for stall_s seconds."""
         reqs = [Request(i, int(k), float(t)) for i, (t, k) in enumerate(zip(arrivals, system_ids))]
         waiting, staged, running, done = [], [], [], []
+        # no garbage-collector pauses inside the loop (its objects are
+        # few and acyclic); restored on exit
+        gc_was = gc.isenabled()
+        gc.disable()
+        try:
+            return self._loop(reqs, waiting, staged, running, done, stall_s)
+        finally:
+            if gc_was:
+                gc.enable()
+
+    def _loop(self, reqs, waiting, staged, running, done, stall_s):
         nxt = 0
         t0 = time.perf_counter()
         last_progress = 0.0
@@ -224,15 +272,19 @@ class Server:
             if ready:
                 ids = {id(r) for r in ready}
                 staged = [r for r in staged if id(r) not in ids]
+                for r in ready:
+                    self._events.append(r.h2d)  # complete: free for reuse
+                    r.h2d = None
                 self.batch.launch([r.slot.slot for r in ready])
-                ev = torch.cuda.Event()
+                ev = self._event()
                 ev.record(self.compute)
                 self.copy.wait_event(ev)
+                self._events.insert(0, ev)  # reused only after later events
                 with torch.cuda.stream(self.copy):
                     for r in ready:
                         r.slot.host_f.copy_(r.slot.forces, non_blocking=True)
                         r.slot.host_ev.copy_(r.slot.ev, non_blocking=True)
-                        r.d2h = torch.cuda.Event()
+                        r.d2h = self._event()
                         r.d2h.record(self.copy)
                 running.extend(ready)
                 self.stats.batch_sizes.append(len(ready))
@@ -242,6 +294,8 @@ class Server:
             for r in running:
                 if r.d2h.query():
                     r.done = time.perf_counter() - t0
+                    self._events.append(r.d2h)
+                    r.d2h = None
                     r.energy = float(r.slot.host_ev[0])
                     if self._keep(r.rid):
                         r.forces = r.slot.host_f.numpy().copy()

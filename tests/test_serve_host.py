@@ -121,7 +121,8 @@ class FakePool:
 
 @pytest.fixture
 def srv(monkeypatch):
-    monkeypatch.setattr(S, "Slot", lambda system_id, slot, pool, sysd, fp: FakeSlot(system_id, slot))
+    monkeypatch.setattr(S, "Slot", lambda system_id, slot, pool, sysd, fp, bufs: FakeSlot(system_id, slot))
+    monkeypatch.setattr(S.Server, "_host_bufs", lambda self, system_id: None)
     s = S.Server.__new__(S.Server)
     s.pool = [S.PoolSystem(None, [0.0], None, 32)] * 5
     s.budget = 250
