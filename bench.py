@@ -336,10 +336,11 @@ def stacked_water(I):
 
 def bench_batched(torch, dev, Plan, BatchPool, Batch, I, reps=100):
     """64 independent water boxes of uneven size (3k..65k atoms, grids 32/48/64
-    by ~1 A spacing) admitted into one arena (pme_batch_admit), one step of
-    all of them per launch (pme_batch_launch: grid groups on forked streams),
-    timed as graph replays; each system's result is checked against its own
-    single step.  The same systems through pme_batch_run (one stream) for
+    by ~1 A spacing) admitted into one arena (pme_batch_admit), kernel
+    variants per grid group autotuned on the batch, one step of all of them
+    per launch (pme_batch_launch: grid groups on forked streams), timed as
+    graph replays; each system's result (from a replay into poisoned
+    outputs) is checked against its own single step.  The same systems through pme_batch_run (one stream) for
     comparison."""
     mix = I.batch_mix()
     stream = torch.cuda.Stream(device=dev)
@@ -354,25 +355,36 @@ def bench_batched(torch, dev, Plan, BatchPool, Batch, I, reps=100):
             io[1].copy_(torch.from_numpy(q))
             members.append((m, s, pos, q, box))
     stream.synchronize()
+    # variants per grid group measured on the whole batch
+    tuned = pool.autotune()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
         pool.launch()
-    for _ in range(3):
-        g.replay()
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    # replays and their events on one stream (a replay runs on the current one)
     with torch.cuda.stream(stream):
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         curtain(torch, dev)
-    evs[0].record(stream)
-    for r in range(reps):
+        evs[0].record(stream)
+        for r in range(reps):
+            g.replay()
+            evs[r + 1].record(stream)
+        torch.cuda.synchronize()
+    # every system once more from poisoned outputs: the replay itself computes them
+    for m, s, pos, q, box in members:
+        pool.io(s)[2].fill_(float("nan"))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
         g.replay()
-        evs[r + 1].record(stream)
     torch.cuda.synchronize()
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]) * 1e3
     same = True
     checks = []
     for k, (m, s, pos, q, box) in enumerate(members):
         plan = Plan(m.K, 4, 0.34, max_atoms=len(q), device=dev)
+        plan.set_tuning(**pool.tuning_of(s))
         fa, ea = plan.step(torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev), box)
         fb, eb = pool.io(s)[2], pool.io(s)[3]
         same &= bool(torch.equal(fa, fb)) and bool(torch.equal(ea, eb))
@@ -380,10 +392,11 @@ def bench_batched(torch, dev, Plan, BatchPool, Batch, I, reps=100):
             checks.append({"pos": pos, "q": q, "box": box, "K": m.K, "order": 4, "beta": 0.34,
                            "forces": fb.cpu().numpy(), "E": float(eb[0].item())})
     del g
-    # the same systems through pme_batch_run on one stream
+    # the same systems through pme_batch_run on one stream (same variants)
     plans, keep = [], []
     for m, s, pos, q, box in members:
         p = Plan(m.K, 4, 0.34, max_atoms=len(q), device=dev)
+        p.set_tuning(**pool.tuning_of(s))
         dp, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
         p.bind(dp, dq, box)
         plans.append(p)
@@ -421,6 +434,7 @@ def bench_batched(torch, dev, Plan, BatchPool, Batch, I, reps=100):
         "launch": "pme_batch_launch in one HIP graph: one binning launch, then spreading, "
                   "convolution and interpolation per grid group, the groups on three forked streams",
         "one_stream_pme_batch_run_us": one_stream,
+        "autotune": tuned,
     }
     return out, checks
 

@@ -331,6 +331,8 @@ class BatchPool:
               "pme_batch_create")
         self._h = h
         self._io = {}    # slot -> (pos, q, forces, ev) tensors
+        self._n, self._box = {}, {}  # slot -> bound atom count and box
+        self._grid, self._order, self._prec = {}, {}, {}
         self._keep = {}  # slot -> caller tensors kept alive
 
     @staticmethod
@@ -367,6 +369,9 @@ class BatchPool:
         check(rc, "pme_batch_admit")
         s = int(slot.value)
         self._io[s] = self._wrap_io(s, int(max_atoms))
+        self._n[s] = int(max_atoms if n is None else n)
+        self._box[s] = np.asarray(box, dtype=np.float64)
+        self._grid[s], self._order[s], self._prec[s] = grid3(K), int(order), PRECISIONS[precision]
         return s
 
     def _wrap_io(self, slot, max_atoms):
@@ -387,11 +392,13 @@ class BatchPool:
         """New atom count and box of a slot whose buffers live in the arena."""
         check(self._lib.pme_batch_update(self._h, int(slot), None, None, int(n), _box9(box), None, None),
               "pme_batch_update")
+        self._n[slot] = int(n)
+        self._box[slot] = np.asarray(box, dtype=np.float64)
 
     def retire(self, slot):
         check(self._lib.pme_batch_retire(self._h, int(slot)), "pme_batch_retire")
-        self._io.pop(slot, None)
-        self._keep.pop(slot, None)
+        for d in (self._io, self._keep, self._n, self._box, self._grid, self._order, self._prec):
+            d.pop(slot, None)
 
     def launch(self, slots=None):
         """One step of the listed slots (None: every admitted system)."""
@@ -408,6 +415,89 @@ class BatchPool:
         check(self._lib.pme_batch_stats(self._h, ctypes.byref(n), ctypes.byref(used), ctypes.byref(lf)),
               "pme_batch_stats")
         return {"admitted": int(n.value), "bytes_used": int(used.value), "largest_free": int(lf.value)}
+
+    def set_tuning(self, slot, conv=None, interp=None, bin_chunk=None):
+        """Kernel variants of an admitted system's plan (pme_set_tuning); a
+        batched launch groups systems whose variants agree."""
+        h = self._lib.pme_batch_plan(self._h, int(slot))
+        if not h:
+            raise ValueError(f"slot {slot} is not admitted")
+        cur = Tuning()
+        check(self._lib.pme_get_tuning(ctypes.c_void_p(h), ctypes.byref(cur)), "pme_get_tuning")
+        t = Tuning(cur.conv if conv is None else int(conv), cur.interp if interp is None else int(interp),
+                   cur.bin_chunk if bin_chunk is None else int(bin_chunk))
+        check(self._lib.pme_set_tuning(ctypes.c_void_p(h), ctypes.byref(t)), "pme_set_tuning")
+        # the bound arguments carry the variants: rebind with the same inputs
+        check(self._lib.pme_batch_update(self._h, int(slot), None, None, int(self._n[slot]),
+                                         _box9(self._box[slot]), None, None), "pme_batch_update")
+
+    def tuning_of(self, slot):
+        h = self._lib.pme_batch_plan(self._h, int(slot))
+        if not h:
+            raise ValueError(f"slot {slot} is not admitted")
+        t = Tuning()
+        check(self._lib.pme_get_tuning(ctypes.c_void_p(h), ctypes.byref(t)), "pme_get_tuning")
+        return t.as_dict()
+
+    def launch_us(self, launches=5, reps=3):
+        """Microseconds per pme_batch_launch of every admitted system: one
+        graph of `launches` launches replayed on the pool's stream, best of
+        `reps`."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.stream):
+            for _ in range(launches):
+                self.launch()
+        best = float("inf")
+        with torch.cuda.stream(self.stream):
+            g.replay()
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                torch.cuda._sleep(250000)  # untimed: the graph is submitted meanwhile
+                a.record(self.stream)
+                g.replay()
+                b.record(self.stream)
+                b.synchronize()
+                best = min(best, a.elapsed_time(b) * 1e3 / launches)
+        del g
+        return best
+
+    def autotune(self, launches=5):
+        """Kernel variants per grid group chosen on the whole batch: starting
+        from each plan's own variants, the groups are visited largest first
+        (atoms) and each takes the (convolution, interpolation) variant under
+        which the graph-replayed launch of the batch is fastest, the other
+        groups held.  Returns {"us": final, "default_us": initial,
+        "groups": {grid: tuning}}."""
+        groups = {}
+        for s in self._io:
+            groups.setdefault(tuple(self._grid[s]) + (self._order[s], self._prec[s]), []).append(s)
+        base = self.launch_us(launches)
+        best_us = base
+        order = sorted(groups, key=lambda k: -sum(self._n[s] for s in groups[k]))
+        chosen = {}
+        for key in order:
+            slots = groups[key]
+            K1, K2, K3, p, prec = key
+            v = int(self._lib.pme_tuning_variants(K1, K2, K3, p, prec))
+            cur = self.tuning_of(slots[0])
+            best_t = dict(cur)
+            for conv, cbit in ((0, 1), (1, 2), (2, 16)):
+                for interp, ibit in ((0, 4), (1, 8)):
+                    if not (v & cbit and v & ibit):
+                        continue
+                    if conv == best_t["conv"] and interp == best_t["interp"]:
+                        continue
+                    for s in slots:
+                        self.set_tuning(s, conv=conv, interp=interp)
+                    us = self.launch_us(launches)
+                    if us < best_us:
+                        best_us, best_t = us, {"conv": conv, "interp": interp,
+                                               "bin_chunk": cur["bin_chunk"]}
+            for s in slots:
+                self.set_tuning(s, **best_t)
+            chosen["x".join(map(str, key[:3]))] = best_t
+        return {"us": best_us, "default_us": base, "groups": chosen}
 
     def check(self, slot):
         """Synchronise; the sticky device flags of a slot's plan (cleared)."""
