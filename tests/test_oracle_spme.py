@@ -358,3 +358,53 @@ def test_real_space_rows_of_listed_atoms(orc):
         rows = [0, 7, 119, 64]
         sub = orc.ewald_real_atoms(pos, q, box, 0.45, rows, nimg=nimg, rcut=rcut)
         assert np.array_equal(sub, full["forces"][rows])
+
+
+def _mode_energies_and_weights(orc, w):
+    """Per-mode energies E_m of the SPME sum and the virial weights
+    w_ab(m) = delta_ab - 2 (1 + pi^2 m^2 / beta^2) m_a m_b / m^2 (Essmann et
+    al. 1995, the method the paper cites in section II), recomputed here from
+    the oracle's FP64 charge grid; a Nyquist index counts +K/2 and -K/2
+    alike, which zeroes its sign-odd products."""
+    pos, q, box = w.make()
+    K, p, beta = w.K, w.order, w.beta
+    r = orc.spme(pos, q, box, K, p, beta, want_grids=True)
+    S2 = np.abs(np.fft.fftn(r["Q"])) ** 2  # axes z, y, x
+    L = np.diag(np.asarray(box, dtype=float).reshape(3, 3))
+    idx = np.fft.fftfreq(K, 1.0 / K)
+    iz, iy, ix = np.meshgrid(idx, idx, idx, indexing="ij")
+    m = [ix / L[0], iy / L[1], iz / L[2]]
+    nyq = [np.abs(ix) == K // 2, np.abs(iy) == K // 2, np.abs(iz) == K // 2]
+    m2 = m[0] ** 2 + m[1] ** 2 + m[2] ** 2
+    m2[0, 0, 0] = 1.0
+    b = orc.moduli(p, K)
+    B = b[:, None, None] * b[None, :, None] * b[None, None, :]
+    x = np.pi ** 2 * m2 / beta ** 2
+    Em = B * np.exp(-x) / m2 * S2 / (2.0 * np.pi * L.prod())
+    Em[0, 0, 0] = 0.0
+    fac = 2.0 * (1.0 + x) / m2
+    W = []
+    for a_, b_ in [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]:
+        prod = m[a_] * m[b_]
+        if a_ != b_:
+            prod = np.where(nyq[a_] | nyq[b_], 0.0, prod)
+        W.append((1.0 if a_ == b_ else 0.0) - fac * prod)
+    return r, Em, W
+
+
+@pytest.mark.parametrize("wl", ["water_4095_k32", "water_65535_k64"])
+def test_virial_weights_energy_weighted_mean_below_two(orc, wl):
+    # the reading behind the FP32 virial bar (2 x the energy bar times |E|):
+    # a virial component is the per-mode energy terms summed with the
+    # weights w_ab(m), so rounding errors of relative size eps in the E_m
+    # reach it scaled by the energy-weighted mean of |w_ab|, which stays
+    # below 2 on the water workloads.  The recomputed E_m and w_ab are first
+    # checked against the oracle's energy and virial, so the mean is taken
+    # over the sums the oracle itself forms.
+    w = {x.name: x for x in (inputs.SMALL_32, inputs.HEADLINE_64)}[wl]
+    r, Em, W = _mode_energies_and_weights(orc, w)
+    assert Em.sum() == pytest.approx(r["E"], rel=1e-11)
+    for c in range(6):
+        assert (Em * W[c]).sum() == pytest.approx(r["virial"][c], abs=1e-10 * abs(r["E"]))
+        mean_w = float((Em * np.abs(W[c])).sum() / Em.sum())
+        assert mean_w < 2.0
