@@ -278,8 +278,9 @@ __device__ __forceinline__ void fft_pencil(cplx<T>* buf, int stride, int lane,
 // O_k = (Z_k - conj Z_{M-k})/(2i), k = 0..M (W_N^M = -1).  Each lane handles
 // the pairs (k, M-k) for k = lane, lane + NT, ... <= M/2.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__device__ __forceinline__ void r2c_post(cplx<T>* row, int lane, const cplx<T>* twN) {
+template <typename T, int N, class Sink>
+__device__ __forceinline__ void r2c_post(const cplx<T>* row, int lane, const cplx<T>* twN,
+                                         Sink&& sink) {
   constexpr int M = N / 2;
   constexpr int NT = fft_lanes(M);
   constexpr int NP = M / 2 + 1;
@@ -304,19 +305,24 @@ __device__ __forceinline__ void r2c_post(cplx<T>* row, int lane, const cplx<T>* 
       cplx<T> d = c_sub(zk, c_conj(zm));
       cplx<T> o = {T(0.5) * d.y, T(-0.5) * d.x};  // d / (2i)
       if (k == 0) {
-        row[0] = c_add(e, o);
-        row[M] = c_sub(e, o);
+        sink(0, c_add(e, o));
+        sink(M, c_sub(e, o));
       } else {
-        row[k] = c_add(e, c_mul(twN[k], o));
+        sink(k, c_add(e, c_mul(twN[k], o)));
         if (k != M - k) {
           cplx<T> e2 = c_scale(c_add(zm, c_conj(zk)), T(0.5));
           cplx<T> d2 = c_sub(zm, c_conj(zk));
           cplx<T> o2 = {T(0.5) * d2.y, T(-0.5) * d2.x};
-          row[M - k] = c_add(e2, c_mul(twN[M - k], o2));
+          sink(M - k, c_add(e2, c_mul(twN[M - k], o2)));
         }
       }
     }
   }
+}
+// ... in place: X_0 .. X_M into the row.
+template <typename T, int N>
+__device__ __forceinline__ void r2c_post(cplx<T>* row, int lane, const cplx<T>* twN) {
+  r2c_post<T, N>(row, lane, twN, [&](int k, const cplx<T>& x) { row[k] = x; });
   lds_order();
 }
 

@@ -270,14 +270,153 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(Args a_in, BatchArgs bt) {
   TRACE(0, 15);
 }
 
+// The twiddles lane j (< R) of a register-resident N-point transform
+// (N = 8 R) uses, kept in registers: wf[s] = W^(j s), s < 8, for the forward
+// direction and wi[eR + l] = W^(l (jE + e)), l < R, e < E = 8/R, for the
+// inverse one, W = exp(-2 pi i / N) from the table tw[k] = W^k (for R = 8 the
+// two sets coincide).
+template <typename T, int N>
+struct RegTw {
+  static constexpr int R = N / 8, E = 8 / R;
+  cplx<T> wf[8], wi[8];
+  // STEP: table stride (a table of W_{STEP N}^k serves the N-point transform)
+  template <int STEP = 1>
+  __device__ __forceinline__ void load(int j, const cplx<T>* tw) {
+#pragma unroll
+    for (int s = 1; s < 8; ++s) wf[s] = tw[STEP * j * s];
+    if constexpr (R == 8) {
+#pragma unroll
+      for (int l = 1; l < 8; ++l) wi[l] = wf[l];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int l = 1; l < R; ++l) wi[e * R + l] = tw[STEP * l * (j * E + e)];
+    }
+  }
+};
+
+// Forward (S = -1) or inverse (S = +1) N-point DFT, N = 8 R, of the pencil
+// whose points j + R r (r < 8) lane j (< R) holds in v[r]; on return v[eR + t]
+// holds mode jE + e + 8t.  scr: the pencil's LDS scratch (R rows of pitch
+// 9, starting at the pencil's first lane x 9); w: the lane's twiddles.
+template <typename T, int N, int S>
+__device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
+  constexpr int R = N / 8, E = 8 / R;
+  Dft<8, S, T>::run(v);
+#pragma unroll
+  for (int s = 1; s < 8; ++s) v[s] = S < 0 ? c_mul(v[s], w.wf[s]) : c_mulc(v[s], w.wf[s]);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) scr[j * 9 + s] = v[s];
+  lds_order();
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int l = 0; l < R; ++l) v[e * R + l] = scr[l * 9 + j * E + e];
+  lds_order();
+#pragma unroll
+  for (int e = 0; e < E; ++e) Dft<R, S, T>::run(v + e * R);
+}
+
+// The inverse direction of rfft_fwd's layouts: v[eR + t] holds mode
+// jE + e + 8t on entry; on return v[r] holds point j + R r.
+template <typename T, int N, int S>
+__device__ __forceinline__ void rfft_inv(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
+  constexpr int R = N / 8, E = 8 / R;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    Dft<R, S, T>::run(v + e * R);
+#pragma unroll
+    for (int l = 1; l < R; ++l)
+      v[e * R + l] = S < 0 ? c_mul(v[e * R + l], w.wi[e * R + l]) : c_mulc(v[e * R + l], w.wi[e * R + l]);
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int l = 0; l < R; ++l) scr[l * 9 + j * E + e] = v[e * R + l];
+  lds_order();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = scr[j * 9 + s];
+  lds_order();
+  Dft<8, S, T>::run(v);
+}
+
+
+// Register-resident x transforms of one row of K1 = 2M reals (M = 32 or 64):
+// the M-point complex transform of the packed sequence z_n = x_{2n} +
+// i x_{2n+1} runs in registers (rfft_fwd / rfft_inv, RX = M/8 lanes per row,
+// lane j holding points j + RX r), the packing identities of r2c_post and
+// c2r_pre go through the row in LDS.  The decomposition (radix 8, twiddles
+// W_M^(j s), radix RX) and the twiddle table entries are those of the
+// Stockham stages of fft_pencil for these lengths.
+template <int K1>
+__host__ __device__ constexpr bool reg_x_ok() {
+  return K1 == 64 || K1 == 128;
+}
+
+// Forward: v holds points j + RX r of the row; the half spectrum X_0 .. X_M
+// goes to sink(k, X_k) (each k once, over the row's lanes); the row (complex,
+// in LDS) is overwritten with the M-point transform on the way.  scr: the
+// row's scratch (RX rows of pitch 9); tw: W_K1^k, k < K1.  Every lane of the
+// row must be in one wavefront.
+template <typename T, int K1, class Sink>
+__device__ __forceinline__ void r2c_row_reg(cplx<T>* v, cplx<T>* row, int j, cplx<T>* scr,
+                                            const cplx<T>* tw, Sink&& sink) {
+  constexpr int M = K1 / 2, RX = M / 8, EX = 8 / RX;
+  RegTw<T, M> w;
+  w.template load<2>(j, tw);
+  rfft_fwd<T, M, -1>(v, j, scr, w);
+  lds_order();
+#pragma unroll
+  for (int e = 0; e < EX; ++e)
+#pragma unroll
+    for (int t = 0; t < RX; ++t) row[j * EX + e + 8 * t] = v[e * RX + t];
+  lds_order();
+  r2c_post<T, K1>(row, j, tw, sink);
+}
+
+// Inverse: the row (complex, in LDS) holds X_0 .. X_M of a real row; on
+// return it holds z_n = x_{2n} + i x_{2n+1}, n < M (unnormalised).  The
+// c2r_pre identity is formed per mode in registers (Im X_0, Im X_M dropped).
+template <typename T, int K1>
+__device__ __forceinline__ void c2r_row_reg(cplx<T>* row, int j, cplx<T>* scr, const cplx<T>* tw) {
+  constexpr int M = K1 / 2, RX = M / 8, EX = 8 / RX;
+  cplx<T> v[8];
+#pragma unroll
+  for (int e = 0; e < EX; ++e)
+#pragma unroll
+    for (int t = 0; t < RX; ++t) {
+      const int k = j * EX + e + 8 * t;
+      cplx<T> xk = row[k], xm = row[M - k];
+      if (k == 0) {
+        xk.y = T(0);
+        xm.y = T(0);
+      }
+      const cplx<T> am = c_add(xk, c_conj(xm));
+      const cplx<T> bm = c_mulc(c_sub(xk, c_conj(xm)), tw[k]);
+      v[e * RX + t] = {am.x - bm.y, am.y + bm.x};  // A + i B
+    }
+  RegTw<T, M> w;
+  w.template load<2>(j, tw);
+  lds_order();
+  rfft_inv<T, M, 1>(v, j, scr, w);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) row[j + RX * r] = v[r];
+  lds_order();
+}
+
 // ---------------------------------------------------------------------------
 // k_spread_x: charge spreading of one y slice of one z-plane, then the x
 // real-to-complex FFT of its rows.
 // ---------------------------------------------------------------------------
 template <class P, class G>
 __host__ __device__ constexpr size_t spread_lds_bytes() {
-  return (size_t)(G::K2 / nq_of(G::K2, P::fixed)) * tile_pitch<P>(G::K1) * 8 +
-         (size_t)G::K1 * sizeof(cplx<typename P::real>) + 64 * sizeof(int);
+  // the tile, the twiddles, the bucket table, then (register x transforms)
+  // the rows' transpose scratch: 9 complex per lane
+  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed);
+  return R * tile_pitch<P>(G::K1) * 8 + (size_t)G::K1 * sizeof(cplx<typename P::real>) +
+         64 * sizeof(int) +
+         (reg_x_ok<G::K1>() ? R * (G::K1 / 16) * 9 * sizeof(cplx<typename P::real>) : 0);
 }
 
 // Contributions of one atom to the plane of support point jz (z order) of
@@ -352,6 +491,7 @@ __global__ __launch_bounds__(spread_threads<BATCH>()) void k_spread_x(Args a_in,
   int* bk_pre = reinterpret_cast<int*>(tw + K1);  // [NBK + 1] item offsets
   int* bk_base = bk_pre + 24;                     // [NBK] first record
   int* bk_n = bk_base + 20;                       // [NBK] counts, then the overflow count
+  cplx<T>* xscr = reinterpret_cast<cplx<T>*>(bk_pre + 64);  // register x transforms
 
   TRACE(1, 0);
   static_assert((K3 * NQ) % kXcds == 0, "spreading tiles do not split over the XCDs");
@@ -452,6 +592,36 @@ __global__ __launch_bounds__(spread_threads<BATCH>()) void k_spread_x(Args a_in,
 
   // --- x: real-to-complex, one row per group of fft_lanes(M) lanes.
   constexpr int TM = fft_lanes(M);
+  if constexpr (reg_x_ok<K1>()) {
+    static_assert(TM == M / 8 && R * TM <= NTS, "register x rows");
+    if (tid < R * TM) {
+      const int y = tid / TM, j = tid - y * TM;
+      cplx<T> v[8];
+      if constexpr (P::fixed) {
+        // int64 -> FP64 -> FP32: x_{2n} and x_{2n+1} of points n = j + TM r
+        const double inv_scale = ldexp(1.0, -a.frac_bits);
+        const Acc* ri = tile + y * PITCH;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int n = j + TM * r;
+          v[r] = {(float)((double)(long long)ri[2 * n] * inv_scale),
+                  (float)((double)(long long)ri[2 * n + 1] * inv_scale)};
+        }
+      } else {
+        const cplx<T>* rz = reinterpret_cast<const cplx<T>*>(tile + y * PITCH);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = rz[j + TM * r];
+      }
+      // X_k of row y straight to column k (runs of R rows per x' across the
+      // wavefront's rows)
+      typename P::spec* sp = reinterpret_cast<typename P::spec*>(a.ws + a.lay.spec) +
+                             (size_t)z * K2 + y0 + y;
+      r2c_row_reg<T, K1>(v, reinterpret_cast<cplx<T>*>(tile + y * PITCH), j, xscr + (tid - j) * 9,
+                         tw, [&](int k, const cplx<T>& x) { spec_st(&sp[(size_t)k * K3 * K2], x); });
+    }
+    TRACE(1, 15);
+    return;
+  } else
   for (int task = tid; task < R * TM; task += NTS) {
     const int y = task / TM, l = task - y * TM;
     cplx<T>* row = reinterpret_cast<cplx<T>*>(tile + y * PITCH);
@@ -1072,75 +1242,6 @@ __host__ __device__ constexpr size_t conv_reg_lds_bytes() {
   return ((size_t)G::K3 * conv_reg_pitch<G>() + (size_t)conv_reg_threads<G>() * 9 + G::K2 +
           G::K3) * sizeof(cplx<typename P::real>) +
          (size_t)(G::K1 + G::K2 + G::K3) * sizeof(double) + 16 * 8 * sizeof(double);
-}
-
-// The twiddles lane j (< R) of a register-resident N-point transform
-// (N = 8 R) uses, kept in registers: wf[s] = W^(j s), s < 8, for the forward
-// direction and wi[eR + l] = W^(l (jE + e)), l < R, e < E = 8/R, for the
-// inverse one, W = exp(-2 pi i / N) from the table tw[k] = W^k (for R = 8 the
-// two sets coincide).
-template <typename T, int N>
-struct RegTw {
-  static constexpr int R = N / 8, E = 8 / R;
-  cplx<T> wf[8], wi[8];
-  __device__ __forceinline__ void load(int j, const cplx<T>* tw) {
-#pragma unroll
-    for (int s = 1; s < 8; ++s) wf[s] = tw[j * s];
-    if constexpr (R == 8) {
-#pragma unroll
-      for (int l = 1; l < 8; ++l) wi[l] = wf[l];
-    } else {
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-#pragma unroll
-        for (int l = 1; l < R; ++l) wi[e * R + l] = tw[l * (j * E + e)];
-    }
-  }
-};
-
-// Forward (S = -1) or inverse (S = +1) N-point DFT, N = 8 R, of the pencil
-// whose points j + R r (r < 8) lane j (< R) holds in v[r]; on return v[eR + t]
-// holds mode jE + e + 8t.  scr: the pencil's LDS scratch (R rows of pitch
-// 9, starting at the pencil's first lane x 9); w: the lane's twiddles.
-template <typename T, int N, int S>
-__device__ __forceinline__ void rfft_fwd(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
-  constexpr int R = N / 8, E = 8 / R;
-  Dft<8, S, T>::run(v);
-#pragma unroll
-  for (int s = 1; s < 8; ++s) v[s] = S < 0 ? c_mul(v[s], w.wf[s]) : c_mulc(v[s], w.wf[s]);
-#pragma unroll
-  for (int s = 0; s < 8; ++s) scr[j * 9 + s] = v[s];
-  lds_order();
-#pragma unroll
-  for (int e = 0; e < E; ++e)
-#pragma unroll
-    for (int l = 0; l < R; ++l) v[e * R + l] = scr[l * 9 + j * E + e];
-  lds_order();
-#pragma unroll
-  for (int e = 0; e < E; ++e) Dft<R, S, T>::run(v + e * R);
-}
-
-// The inverse direction of rfft_fwd's layouts: v[eR + t] holds mode
-// jE + e + 8t on entry; on return v[r] holds point j + R r.
-template <typename T, int N, int S>
-__device__ __forceinline__ void rfft_inv(cplx<T>* v, int j, cplx<T>* scr, const RegTw<T, N>& w) {
-  constexpr int R = N / 8, E = 8 / R;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    Dft<R, S, T>::run(v + e * R);
-#pragma unroll
-    for (int l = 1; l < R; ++l)
-      v[e * R + l] = S < 0 ? c_mul(v[e * R + l], w.wi[e * R + l]) : c_mulc(v[e * R + l], w.wi[e * R + l]);
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e)
-#pragma unroll
-    for (int l = 0; l < R; ++l) scr[l * 9 + j * E + e] = v[e * R + l];
-  lds_order();
-#pragma unroll
-  for (int s = 0; s < 8; ++s) v[s] = scr[j * 9 + s];
-  lds_order();
-  Dft<8, S, T>::run(v);
 }
 
 template <class P, class G, bool BATCH>
