@@ -1402,10 +1402,27 @@ static __device__ void reduce_ev(const Args& a) {
 // rows of the workspace (with a (p-1)-point wrap halo in front).  Used on
 // large grids before k_interp_phi, and for the debug copy of the potential.
 // ---------------------------------------------------------------------------
+// (the plane, the twiddles, then the register transforms' scratch, 9
+// complex per transform lane, where it still fits)
 template <class P, class G>
-__host__ __device__ constexpr size_t inv_x_lds_bytes() {
+__host__ __device__ constexpr size_t inv_x_lds_base() {
   return (size_t)G::K2 * (G::K1 / 2 + 2) * sizeof(cplx<typename P::real>) +
          (size_t)G::K1 * sizeof(cplx<typename P::real>);
+}
+template <class P, class G>
+__host__ __device__ constexpr size_t inv_x_scratch() {
+  constexpr size_t XL = (size_t)fft_lanes(G::K1 / 2) * G::K2;  // lanes of the x transforms
+  return (XL < kPlaneThreads ? XL : kPlaneThreads) * 9 * sizeof(cplx<typename P::real>);
+}
+template <class P, class G>
+__host__ __device__ constexpr bool inv_x_reg() {
+  return reg_x_ok<G::K1>() && inv_x_lds_base<P, G>() + inv_x_scratch<P, G>() <= kMaxLds;
+}
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr bool x_inv_reg();  // both interpolations alike
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr size_t inv_x_lds_bytes() {
+  return inv_x_lds_base<P, G>() + (x_inv_reg<P, G, ORDER>() ? inv_x_scratch<P, G>() : 0);
 }
 
 template <class P, class G, int ORDER, bool BATCH>
@@ -1430,11 +1447,19 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
   for (int i = tid; i < K1; i += kPlaneThreads) tw[i] = twg[i];
   __syncthreads();
   constexpr int TM = fft_lanes(M);
-  for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
-    const int y = task / TM, l = task - y * TM;
-    cplx<T>* row = pl + y * PC;
-    c2r_pre<T, K1>(row, l, tw);
-    fft_pencil<T, M, 1>(row, 1, l, tw, 2);
+  if constexpr (x_inv_reg<P, G, ORDER>()) {
+    cplx<T>* xscr = tw + K1;  // 9 per transform lane
+    for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
+      const int y = task / TM, l = task - y * TM;
+      c2r_row_reg<T, K1>(pl + y * PC, l, xscr + (tid - l) * 9, tw);
+    }
+  } else {
+    for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
+      const int y = task / TM, l = task - y * TM;
+      cplx<T>* row = pl + y * PC;
+      c2r_pre<T, K1>(row, l, tw);
+      fft_pencil<T, M, 1>(row, 1, l, tw, 2);
+    }
   }
   __syncthreads();
   T* phi = reinterpret_cast<T*>(a.ws + a.lay.phi) + (size_t)z * K2 * PP;
@@ -1455,12 +1480,35 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
 // interpolates those atoms from LDS, one per thread; forces go to the
 // caller's atom order.
 // ---------------------------------------------------------------------------
+// (the rows, the twiddles, the counts, then the register transforms'
+// scratch, 9 complex per transform lane, where it still fits)
 template <class P, class G, int ORDER>
-__host__ __device__ constexpr size_t interp_lds_bytes() {
+__host__ __device__ constexpr size_t interp_lds_base() {
   constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
   constexpr size_t PC = G::K1 / 2 + 2;
   return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)G::K1 * sizeof(cplx<typename P::real>) +
          4 * sizeof(int);
+}
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr size_t interp_scratch() {
+  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
+  constexpr size_t XL = (size_t)fft_lanes(G::K1 / 2) * NROW;  // lanes of the x transforms
+  return (XL < kInterpThreads ? XL : kInterpThreads) * 9 * sizeof(cplx<typename P::real>);
+}
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr bool interp_reg() {
+  return reg_x_ok<G::K1>() &&
+         interp_lds_base<P, G, ORDER>() + interp_scratch<P, G, ORDER>() <= kMaxLds;
+}
+// The register inverse x transform where both interpolations can hold its
+// scratch, so that the fused and the split interpolation stay bit-identical.
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr bool x_inv_reg() {
+  return inv_x_reg<P, G>() && interp_reg<P, G, ORDER>();
+}
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr size_t interp_lds_bytes() {
+  return interp_lds_base<P, G, ORDER>() + (x_inv_reg<P, G, ORDER>() ? interp_scratch<P, G, ORDER>() : 0);
 }
 
 // Force on one atom from the potential: rows(jz, jy) points at the potential
@@ -1575,10 +1623,18 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   Rec r;
   if (tid < total) r = rec[tid < n0 ? (size_t)b0 * cap + tid : (size_t)(b0 + 1) * cap + (tid - n0)];
   constexpr int TM = fft_lanes(M);
-  for (int task = tid; task < NROW * TM; task += NT) {
-    const int row = task / TM, l = task - row * TM;
-    c2r_pre<T, K1>(buf + row * PC, l, tw);
-    fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
+  if constexpr (x_inv_reg<P, G, ORDER>()) {
+    cplx<T>* xscr = reinterpret_cast<cplx<T>*>(nb + 4);  // 9 per transform lane
+    for (int task = tid; task < NROW * TM; task += NT) {
+      const int row = task / TM, l = task - row * TM;
+      c2r_row_reg<T, K1>(buf + row * PC, l, xscr + (tid - l) * 9, tw);
+    }
+  } else {
+    for (int task = tid; task < NROW * TM; task += NT) {
+      const int row = task / TM, l = task - row * TM;
+      c2r_pre<T, K1>(buf + row * PC, l, tw);
+      fft_pencil<T, M, 1>(buf + row * PC, 1, l, tw, 2);
+    }
   }
   __syncthreads();
   TRACE(3, 2);
@@ -1803,7 +1859,7 @@ hipError_t raise_all_lds_limits() {
                               (int)conv_reg_lds_bytes<P, G>());
   }
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_inv_x<P, G, O, B>, attr, (int)inv_x_lds_bytes<P, G>());
+    e = hipFuncSetAttribute((const void*)k_inv_x<P, G, O, B>, attr, (int)inv_x_lds_bytes<P, G, O>());
   if constexpr (interp_fused_ok<P, G, O>()) {
     if (e == hipSuccess)
       e = hipFuncSetAttribute((const void*)k_interp<P, G, O, B>, attr,
@@ -1912,7 +1968,7 @@ hipError_t launch_inv_x_p(const Args& a, hipStream_t s, const Timing& t, const B
       return with_batch(bt, [&](auto bc) {
         constexpr bool B = decltype(bc)::value;
         return launch(k_inv_x<P, G, O, B>, dim3(G::K3), dim3(kPlaneThreads),
-                      inv_x_lds_bytes<P, G>(), s, t, a, bt);
+                      inv_x_lds_bytes<P, G, O>(), s, t, a, bt);
       });
     });
   });
@@ -1932,7 +1988,7 @@ hipError_t launch_interp_p(const Args& a, hipStream_t s, const Timing& t, const 
           // window spans both launches
           const Timing first{t.start, nullptr}, last{nullptr, t.stop};
           hipError_t e = launch(k_inv_x<P, G, O, B>, dim3(G::K3), dim3(kPlaneThreads),
-                                inv_x_lds_bytes<P, G>(), s, first, a, bt);
+                                inv_x_lds_bytes<P, G, O>(), s, first, a, bt);
           if (e == hipSuccess)
             e = launch(k_interp_phi<P, G, O, B>, dim3(blocks), dim3(kInterpThreads), 0, s, last,
                        a, bt);
