@@ -1359,6 +1359,8 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
 #pragma unroll
     for (int r = 0; r < 8; ++r) buf[(j + RZ * r) * PB + y] = v[r];
   }
+  // the wavefront's energy/virial row, while the others finish their z pass
+  ev_row(a, acc, xp * (NT / 64) + (tid >> 6));
   __syncthreads();
   TRACE(2, 3);
 
@@ -1373,8 +1375,6 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
 #pragma unroll
     for (int r = 0; r < 8; ++r) spec_st(&col[(size_t)z * K2 + j + RY * r], v[r]);
   }
-  TRACE(2, 4);
-  ev_row(a, acc, xp * (NT / 64) + (tid >> 6));
   TRACE(2, 15);
 }
 
