@@ -810,7 +810,9 @@ def main():
             serving_pool[label] = pool
             print(f"# serving ({label}): {st['throughput_per_s']:.0f} req/s, p50 {st['latency_us']['p50']:.0f} us, "
                   f"p99 {st['latency_us']['p99']:.0f} us, max {st['latency_us']['max']:.0f} us, "
-                  f"mean batch {st['mean_batch']:.2f}", file=sys.stderr, flush=True)
+                  f"mean batch {st['mean_batch']:.2f}; longest loop turn {st['longest_loop_turn_us']:.0f} us "
+                  f"at {st['longest_loop_turn_at_s']:.4f} s; worst request {st['worst_request']}",
+                  file=sys.stderr, flush=True)
 
     # sampled frames of the headline for the oracle leg (host-launched steps)
     got_frames = []

@@ -388,6 +388,18 @@ class BatchPool:
         """(pos, q, forces, ev) device tensors of an admitted slot."""
         return self._io[slot]
 
+    def results_span(self, slot):
+        """(span, ev_offset): a uint8 device view of the arena from the slot's
+        forces to the end of its energy/virial vector, so that one copy
+        fetches both, and the byte offset of the energy/virial vector in it;
+        None when they are not carved one after the other."""
+        _, _, f, ev = self._io[slot]
+        base = self._arena.data_ptr()
+        of, oe = f.data_ptr() - base, ev.data_ptr() - base
+        if oe < of + f.numel() * 8 or oe - of - f.numel() * 8 >= 256:
+            return None
+        return self._arena[of:oe + 56], oe - of
+
     def update(self, slot, n, box):
         """New atom count and box of a slot whose buffers live in the arena."""
         check(self._lib.pme_batch_update(self._h, int(slot), None, None, int(n), _box9(box), None, None),

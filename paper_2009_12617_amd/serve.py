@@ -17,13 +17,41 @@ Latency is the host time from a request's scheduled arrival to the moment
 its forces and energy are in host memory.
 """
 from dataclasses import dataclass, field
+import ctypes
 import gc
 import time
 
 import numpy as np
 import torch
 
+from . import _lib
 from .plan import BatchPool
+
+# Request copies go straight to the HIP runtime the step library is linked
+# against (the process's one): torch's non-blocking copies of pinned memory
+# record a new event in its host allocator each time, and the runtime now
+# and then stalls the host for milliseconds growing the pool those events
+# draw on.
+_H2D, _D2H = 1, 2  # hipMemcpyKind
+
+
+def _hip():
+    lib = _lib.load()
+    f = lib.hipMemcpyAsync
+    if f.argtypes is None:
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    return f
+
+
+def _copy(dst, src, kind, stream):
+    """Asynchronous copy of src's bytes into dst (same size, contiguous) on
+    stream, through the HIP runtime."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n and dst.is_contiguous() and src.is_contiguous()
+    rc = _hip()(dst.data_ptr(), src.data_ptr(), n, kind, stream.cuda_stream)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
 
 
 @dataclass
@@ -48,7 +76,12 @@ class Slot:
         self.slot = slot
         self.pos, self.q, self.forces, self.ev = pool.io(slot)
         self.q.copy_(torch.from_numpy(np.ascontiguousarray(sysd.q)), non_blocking=False)
-        self.host_f, self.host_ev = host_bufs
+        # results: forces and E/virial in one copy when the arena holds them
+        # back to back (host_raw is then the pinned bytes both are views of)
+        self.host_raw, self.host_f, self.host_ev = host_bufs
+        sp = pool.results_span(slot)
+        self.span = sp[0] if sp is not None and self.host_raw is not None \
+            and sp[0].numel() == self.host_raw.numel() else None
         self.footprint = footprint
         self.busy = False
         self.last_used = 0.0
@@ -66,6 +99,7 @@ class Request:
     done: float = None
     energy: float = None
     forces: np.ndarray = None
+    copied: int = 0  # atoms of forces copied out of the slot's host buffer so far
 
 
 @dataclass
@@ -78,6 +112,9 @@ class ServeStats:
     peak_inflight: int = 0
     slots_created: int = 0
     slots_prewarmed: int = 0
+    longest_turn_s: float = 0.0  # longest single pass of the request loop (host stalls)
+    longest_turn_at_s: float = 0.0
+    worst_request: dict = field(default_factory=dict)
     rejected_for_budget: int = 0
     evictions: int = 0
 
@@ -99,6 +136,9 @@ class ServeStats:
             "slots_created_while_serving": int(self.slots_created),
             "waits_for_budget": int(self.rejected_for_budget),
             "evictions": int(self.evictions),
+            "longest_loop_turn_us": float(self.longest_turn_s * 1e6),
+            "longest_loop_turn_at_s": float(self.longest_turn_at_s),
+            "worst_request": self.worst_request,
         }
 
 
@@ -116,8 +156,14 @@ class Server:
         # keep_forces: None (keep none), True (keep all) or a predicate on the
         # request id
         self.keep_forces = keep_forces
+        # three streams: inputs in, the batched steps, results out.  Inputs
+        # of new requests are copied while earlier batches compute and copy
+        # their results back (one stream for both directions would queue an
+        # input copy behind the previous batch's result copy, and so behind
+        # its compute)
         self.compute = torch.cuda.Stream(device=self.device)
-        self.copy = torch.cuda.Stream(device=self.device)
+        self.h2d = torch.cuda.Stream(device=self.device)
+        self.d2h = torch.cuda.Stream(device=self.device)
         self.batch = BatchPool(self.budget, max_systems=max(64, 2 * len(self.pool)),
                                device=self.device, stream=self.compute)
         self.fp = [self.batch.footprint(p.K, p.order, len(p.q), precision) for p in self.pool]
@@ -186,16 +232,21 @@ class Server:
         return s
 
     def _host_bufs(self, system_id):
-        """Pinned result buffers for a new slot of this system: one of the
-        system's cached pairs that no live slot holds, else a new pair."""
+        """Pinned result buffers (bytes, forces view, E/virial view) for a new
+        slot of this system: a cached set that no live slot holds, else a new
+        one."""
         cache = self.host_cache.setdefault(system_id, [])
-        held = {id(sl.host_f) for sl in self.slots[system_id]}
+        held = {id(sl.host_raw) for sl in self.slots[system_id]}
         for pair in cache:
             if id(pair[0]) not in held:
                 return pair
         n = len(self.pool[system_id].q)
-        pair = (torch.empty((n, 3), dtype=torch.float64, pin_memory=True),
-                torch.empty(7, dtype=torch.float64, pin_memory=True))
+        # pinned bytes laid out as the arena carves forces and E/virial:
+        # [n][3] doubles, padding to 256 bytes, 7 doubles
+        fb = (n * 24 + 255) // 256 * 256
+        raw = torch.empty(fb + 56, dtype=torch.uint8, pin_memory=True)
+        pair = (raw, raw[:n * 24].view(torch.float64).view(n, 3),
+                raw[fb:fb + 56].view(torch.float64))
         cache.append(pair)
         return pair
 
@@ -218,10 +269,9 @@ class Server:
         s.last_used = now
         req.slot = s
         req.admitted = now
-        with torch.cuda.stream(self.copy):
-            s.pos.copy_(self.inputs[req.system_id], non_blocking=True)
-            req.h2d = self._event()
-            req.h2d.record(self.copy)
+        _copy(s.pos, self.inputs[req.system_id], _H2D, self.h2d)
+        req.h2d = self._event()
+        req.h2d.record(self.h2d)
         return True
 
     def _event(self):
@@ -247,12 +297,33 @@ class Server:
             if gc_was:
                 gc.enable()
 
+    # atoms of kept forces copied out of a slot's host buffer per loop turn,
+    # so that keeping a large system's forces never stalls the loop for long
+    COPY_CHUNK = 16384
+
+    def _copy_kept(self, pending):
+        """One chunk of the oldest pending copy of kept forces; the slot is
+        released once its forces are out."""
+        r = pending[0]
+        n = r.forces.shape[0]
+        e = min(n, r.copied + self.COPY_CHUNK)
+        r.forces[r.copied:e] = r.slot.host_f.numpy()[r.copied:e]
+        r.copied = e
+        if e == n:
+            r.slot.busy = False
+            pending.pop(0)
+
     def _loop(self, reqs, waiting, staged, running, done, stall_s):
         nxt = 0
         t0 = time.perf_counter()
         last_progress = 0.0
-        while len(done) < len(reqs):
+        pending = []  # completed requests whose kept forces are still being copied
+        prev = 0.0
+        while len(done) < len(reqs) or pending:
             now = time.perf_counter() - t0
+            if now - prev > self.stats.longest_turn_s:
+                self.stats.longest_turn_s, self.stats.longest_turn_at_s = now - prev, prev
+            prev = now
             if now - last_progress > stall_s and now > (reqs[-1].arrival if reqs else 0.0):
                 raise RuntimeError(f"serving stalled: {len(done)} of {len(reqs)} requests done")
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
@@ -267,25 +338,28 @@ class Server:
                 else:
                     staged.append(r)
             waiting = still
-            # one tick: every staged request whose input is on the device
-            ready = [r for r in staged if r.h2d.query()][: self.max_batch]
+            # one tick: the staged requests in one launch, ordered after their
+            # input copies on the device (no host round trip in between)
+            ready = staged[: self.max_batch]
             if ready:
-                ids = {id(r) for r in ready}
-                staged = [r for r in staged if id(r) not in ids]
+                staged = staged[len(ready):]
                 for r in ready:
-                    self._events.append(r.h2d)  # complete: free for reuse
+                    self.compute.wait_event(r.h2d)
+                    self._events.insert(0, r.h2d)  # the wait is enqueued: reusable later
                     r.h2d = None
                 self.batch.launch([r.slot.slot for r in ready])
                 ev = self._event()
                 ev.record(self.compute)
-                self.copy.wait_event(ev)
+                self.d2h.wait_event(ev)
                 self._events.insert(0, ev)  # reused only after later events
-                with torch.cuda.stream(self.copy):
-                    for r in ready:
-                        r.slot.host_f.copy_(r.slot.forces, non_blocking=True)
-                        r.slot.host_ev.copy_(r.slot.ev, non_blocking=True)
-                        r.d2h = self._event()
-                        r.d2h.record(self.copy)
+                for r in ready:
+                    if r.slot.span is not None:
+                        _copy(r.slot.host_raw, r.slot.span, _D2H, self.d2h)
+                    else:
+                        _copy(r.slot.host_f, r.slot.forces, _D2H, self.d2h)
+                        _copy(r.slot.host_ev, r.slot.ev, _D2H, self.d2h)
+                    r.d2h = self._event()
+                    r.d2h.record(self.d2h)
                 running.extend(ready)
                 self.stats.batch_sizes.append(len(ready))
             self.stats.peak_inflight = max(self.stats.peak_inflight, len(running) + len(staged))
@@ -297,23 +371,36 @@ class Server:
                     self._events.append(r.d2h)
                     r.d2h = None
                     r.energy = float(r.slot.host_ev[0])
-                    if self._keep(r.rid):
-                        r.forces = r.slot.host_f.numpy().copy()
-                    r.slot.busy = False
                     r.slot.last_used = r.done
+                    if self._keep(r.rid):
+                        # copied out in chunks over the next loop turns; the
+                        # slot stays busy until then
+                        r.forces = np.empty(tuple(r.slot.host_f.shape), dtype=np.float64)
+                        pending.append(r)
+                    else:
+                        r.slot.busy = False
                     done.append(r)
                     last_progress = r.done
                     self.stats.latencies_s.append(r.done - r.arrival)
                 else:
                     still.append(r)
             running = still
+            if pending:
+                self._copy_kept(pending)
             if not ready and not running and not staged and nxt < len(reqs) and not waiting:
-                # idle until the next arrival
+                # idle until the next arrival: sleep only while it is far off
+                # (a sleep overshoots by tens of microseconds), then spin
                 dt = reqs[nxt].arrival - (time.perf_counter() - t0)
-                if dt > 0:
-                    time.sleep(min(dt, 0.0005))
+                if dt > 3e-4:
+                    time.sleep(min(dt - 2e-4, 5e-4))
         self.stats.wall_s = time.perf_counter() - t0
         self.stats.completed = len(done)
+        if done:
+            w = max(done, key=lambda r: r.done - r.arrival)
+            self.stats.worst_request = {"rid": w.rid, "system": w.system_id,
+                                        "atoms": int(w.slot.host_f.shape[0]),
+                                        "arrival_s": w.arrival, "admitted_s": w.admitted,
+                                        "done_s": w.done}
         return done
 
     def close(self):
