@@ -1402,35 +1402,28 @@ static __device__ void reduce_ev(const Args& a) {
 // rows of the workspace (with a (p-1)-point wrap halo in front).  Used on
 // large grids before k_interp_phi, and for the debug copy of the potential.
 // ---------------------------------------------------------------------------
-// (the plane, the twiddles, then the register transforms' scratch, 9
-// complex per transform lane, where it still fits)
-template <class P, class G>
-__host__ __device__ constexpr size_t inv_x_lds_base() {
-  return (size_t)G::K2 * (G::K1 / 2 + 2) * sizeof(cplx<typename P::real>) +
+// Row pitch (complex) of the potential rows of k_inv_x and k_interp: the
+// half spectrum X_0 .. X_{K1/2} plus one, widened where the register
+// inverse x transform uses the row itself as its transpose scratch (RX
+// lanes of 9 complex each).
+template <int K1>
+__host__ __device__ constexpr int x_row_pitch() {
+  return reg_x_ok<K1>() && (K1 / 16) * 9 > K1 / 2 + 2 ? (K1 / 16) * 9 : K1 / 2 + 2;
+}
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr size_t inv_x_lds_bytes() {
+  return (size_t)G::K2 * x_row_pitch<G::K1>() * sizeof(cplx<typename P::real>) +
          (size_t)G::K1 * sizeof(cplx<typename P::real>);
-}
-template <class P, class G>
-__host__ __device__ constexpr size_t inv_x_scratch() {
-  constexpr size_t XL = (size_t)fft_lanes(G::K1 / 2) * G::K2;  // lanes of the x transforms
-  return (XL < kPlaneThreads ? XL : kPlaneThreads) * 9 * sizeof(cplx<typename P::real>);
-}
-template <class P, class G>
-__host__ __device__ constexpr bool inv_x_reg() {
-  return reg_x_ok<G::K1>() && inv_x_lds_base<P, G>() + inv_x_scratch<P, G>() <= kMaxLds;
 }
 template <class P, class G, int ORDER>
 __host__ __device__ constexpr bool x_inv_reg();  // both interpolations alike
-template <class P, class G, int ORDER>
-__host__ __device__ constexpr size_t inv_x_lds_bytes() {
-  return inv_x_lds_base<P, G>() + (x_inv_reg<P, G, ORDER>() ? inv_x_scratch<P, G>() : 0);
-}
 
 template <class P, class G, int ORDER, bool BATCH>
 __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt) {
   const Args a = BATCH ? *bt.sys[blockIdx.y] : a_in;
   using T = typename P::real;
   constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
-  constexpr int M = K1 / 2, KH = K1 / 2 + 1, PC = KH + 1;
+  constexpr int M = K1 / 2, KH = K1 / 2 + 1, PC = x_row_pitch<K1>();
   constexpr int PP = phi_pitch_of(K1, ORDER);
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem);
@@ -1448,10 +1441,9 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
   __syncthreads();
   constexpr int TM = fft_lanes(M);
   if constexpr (x_inv_reg<P, G, ORDER>()) {
-    cplx<T>* xscr = tw + K1;  // 9 per transform lane
     for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
       const int y = task / TM, l = task - y * TM;
-      c2r_row_reg<T, K1>(pl + y * PC, l, xscr + (tid - l) * 9, tw);
+      c2r_row_reg<T, K1>(pl + y * PC, l, pl + y * PC, tw);  // the row is its scratch
     }
   } else {
     for (int task = tid; task < K2 * TM; task += kPlaneThreads) {
@@ -1480,35 +1472,18 @@ __global__ __launch_bounds__(kPlaneThreads) void k_inv_x(Args a_in, BatchArgs bt
 // interpolates those atoms from LDS, one per thread; forces go to the
 // caller's atom order.
 // ---------------------------------------------------------------------------
-// (the rows, the twiddles, the counts, then the register transforms'
-// scratch, 9 complex per transform lane, where it still fits)
-template <class P, class G, int ORDER>
-__host__ __device__ constexpr size_t interp_lds_base() {
-  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
-  constexpr size_t PC = G::K1 / 2 + 2;
-  return NROW * PC * sizeof(cplx<typename P::real>) + (size_t)G::K1 * sizeof(cplx<typename P::real>) +
-         4 * sizeof(int);
-}
-template <class P, class G, int ORDER>
-__host__ __device__ constexpr size_t interp_scratch() {
-  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
-  constexpr size_t XL = (size_t)fft_lanes(G::K1 / 2) * NROW;  // lanes of the x transforms
-  return (XL < kInterpThreads ? XL : kInterpThreads) * 9 * sizeof(cplx<typename P::real>);
-}
-template <class P, class G, int ORDER>
-__host__ __device__ constexpr bool interp_reg() {
-  return reg_x_ok<G::K1>() &&
-         interp_lds_base<P, G, ORDER>() + interp_scratch<P, G, ORDER>() <= kMaxLds;
-}
-// The register inverse x transform where both interpolations can hold its
-// scratch, so that the fused and the split interpolation stay bit-identical.
-template <class P, class G, int ORDER>
-__host__ __device__ constexpr bool x_inv_reg() {
-  return inv_x_reg<P, G>() && interp_reg<P, G, ORDER>();
-}
 template <class P, class G, int ORDER>
 __host__ __device__ constexpr size_t interp_lds_bytes() {
-  return interp_lds_base<P, G, ORDER>() + (x_inv_reg<P, G, ORDER>() ? interp_scratch<P, G, ORDER>() : 0);
+  constexpr size_t R = G::K2 / nq_of(G::K2, P::fixed), NROW = (size_t)ORDER * (R + ORDER - 1);
+  return NROW * x_row_pitch<G::K1>() * sizeof(cplx<typename P::real>) +
+         (size_t)G::K1 * sizeof(cplx<typename P::real>) + 4 * sizeof(int);
+}
+// The register inverse x transform wherever both interpolations have it, so
+// that the fused and the split interpolation stay bit-identical.
+template <class P, class G, int ORDER>
+__host__ __device__ constexpr bool x_inv_reg() {
+  return reg_x_ok<G::K1>() && interp_lds_bytes<P, G, ORDER>() <= kMaxLds &&
+         inv_x_lds_bytes<P, G, ORDER>() <= kMaxLds;
 }
 
 // Force on one atom from the potential: rows(jz, jy) points at the potential
@@ -1572,7 +1547,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   using T = typename P::real;
   using Rec = typename P::rec;
   constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3;
-  constexpr int M = K1 / 2, KH = M + 1, PC = KH + 1;
+  constexpr int M = K1 / 2, KH = M + 1, PC = x_row_pitch<K1>();
   constexpr int NQ = nq_of(K2, P::fixed), R = K2 / NQ, RR = R + ORDER - 1, NROW = ORDER * RR;
   constexpr int NT = kInterpThreads;
   static_assert(interp_lds_bytes<P, G, ORDER>() <= kMaxLds, "interpolation tile does not fit in LDS");
@@ -1624,10 +1599,9 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(Args a_in, BatchArgs 
   if (tid < total) r = rec[tid < n0 ? (size_t)b0 * cap + tid : (size_t)(b0 + 1) * cap + (tid - n0)];
   constexpr int TM = fft_lanes(M);
   if constexpr (x_inv_reg<P, G, ORDER>()) {
-    cplx<T>* xscr = reinterpret_cast<cplx<T>*>(nb + 4);  // 9 per transform lane
     for (int task = tid; task < NROW * TM; task += NT) {
       const int row = task / TM, l = task - row * TM;
-      c2r_row_reg<T, K1>(buf + row * PC, l, xscr + (tid - l) * 9, tw);
+      c2r_row_reg<T, K1>(buf + row * PC, l, buf + row * PC, tw);  // the row is its scratch
     }
   } else {
     for (int task = tid; task < NROW * TM; task += NT) {
