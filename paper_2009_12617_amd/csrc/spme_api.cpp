@@ -475,7 +475,8 @@ namespace {
 // grid, order and variants.
 bool same_group(const Args& a, const Args& b) {
   return a.precision == b.precision && a.K1 == b.K1 && a.K2 == b.K2 && a.K3 == b.K3 &&
-         a.order == b.order && a.conv_mode == b.conv_mode && a.interp_mode == b.interp_mode;
+         a.order == b.order && a.conv_mode == b.conv_mode && a.interp_mode == b.interp_mode &&
+         a.bin_chunk == b.bin_chunk;
 }
 
 // Streams a batched run may fork its grid groups onto, with the events that
@@ -565,12 +566,12 @@ int batch_run_impl(pme_plan* const* plans, int n, hipStream_t s, const Fork* for
     }
     p->state = kDirty;
   }
-  for (size_t g = 0; g < bin_bts.size(); ++g)
-    if (spme::launch_bin(bin_reps[g], s, none, &bin_bts[g]) != hipSuccess) return PME_EDEVICE;
   const int nfork = (fork != nullptr && groups.size() > 1)
                         ? (int)std::min(fork->streams.size(), groups.size())
                         : 0;
   if (nfork == 0) {
+    for (size_t g = 0; g < bin_bts.size(); ++g)
+      if (spme::launch_bin(bin_reps[g], s, none, &bin_bts[g]) != hipSuccess) return PME_EDEVICE;
     // stage by stage over the groups, all on one stream
     for (int stage = 1; stage < spme::kNumKernels; ++stage) {
       for (size_t g = 0; g < groups.size(); ++g) {
@@ -587,7 +588,9 @@ int batch_run_impl(pme_plan* const* plans, int n, hipStream_t s, const Fork* for
     }
   } else {
     // groups dealt to the fork streams, largest grids first (they take
-    // longest), each stream running its groups' stages in order
+    // longest), each stream running its groups' stages in order, binning
+    // included (a group's chain then starts without waiting for the
+    // binning of the others)
     if (hipEventRecord(fork->start, s) != hipSuccess) return PME_EDEVICE;
     for (int f = 0; f < nfork; ++f)
       if (hipStreamWaitEvent(fork->streams[f], fork->start, 0) != hipSuccess) return PME_EDEVICE;
@@ -603,7 +606,8 @@ int batch_run_impl(pme_plan* const* plans, int n, hipStream_t s, const Fork* for
       hipStream_t fs = fork->streams[k % nfork];
       const Args& a = reps[g];
       const spme::BatchArgs* bt = &bts[g];
-      if (spme::launch_spread_x(a, fs, none, bt) != hipSuccess ||
+      if (spme::launch_bin(a, fs, none, bt) != hipSuccess ||
+          spme::launch_spread_x(a, fs, none, bt) != hipSuccess ||
           spme::launch_conv(a, fs, none, bt) != hipSuccess ||
           spme::launch_interp(a, fs, none, bt) != hipSuccess)
         return PME_EDEVICE;
