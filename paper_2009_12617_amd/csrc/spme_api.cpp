@@ -847,7 +847,7 @@ struct pme_batch {
 
 namespace {
 
-constexpr int kForkStreams = 3;  // with the batch's own stream: the box's four hardware queues
+constexpr int kForkStreams = 3;  // with the batch's own stream: four hardware queues per process
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
