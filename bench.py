@@ -431,8 +431,8 @@ def bench_batched(torch, dev, Plan, BatchPool, Batch, I, reps=100):
         "step_algorithmic_bytes": int(nbytes),
         "roofline_frac": nbytes / (per.mean() * 1e-6) / 1e9 / HBM_PEAK_GBS,
         "same_as_single_steps": bool(same),
-        "launch": "pme_batch_launch in one HIP graph: one binning launch, then spreading, "
-                  "convolution and interpolation per grid group, the groups on three forked streams",
+        "launch": "pme_batch_launch in one HIP graph: binning, spreading, convolution and "
+                  "interpolation per grid group, the groups on three forked streams",
         "one_stream_pme_batch_run_us": one_stream,
         "autotune": tuned,
     }

@@ -318,10 +318,10 @@ int pme_batch_io(pme_batch *b, int slot, double **pos, double **q, double **forc
 
 /* One step of the n listed admitted slots (slots NULL: every admitted
  * system; a slot listed twice is PME_EINVAL): systems sharing precision,
- * grid, order and variants share every launch; the groups run on up to
- * three forked streams joined back into the batch's stream (so a launch can
- * be captured in a hipGraph as one fork/join).  PME_OK with nothing to
- * run. */
+ * grid, order, variants and binning chunk share every launch; the groups
+ * run, binning included, on up to three forked streams joined back into the
+ * batch's stream (so a launch can be captured in a hipGraph as one
+ * fork/join).  PME_OK with nothing to run. */
 int pme_batch_launch(pme_batch *b, const int *slots, int n);
 
 /* Occupancy: admitted systems, arena bytes in use, largest free range. */

@@ -487,11 +487,11 @@ struct Fork {
   hipEvent_t start = nullptr;
 };
 
-// One step of each bound plan: one binning launch per (precision, chunk),
-// then spreading, convolution and interpolation once per grid group.
-// Without fork streams every launch goes to s in stage order; with them, the
-// groups run concurrently on fork streams after the binning and join s at
-// the end.
+// One step of each bound plan.  Without fork streams: one binning launch per
+// (precision, chunk), then spreading, convolution and interpolation once per
+// grid group, every launch on s in stage order.  With them: each grid group
+// runs its own binning, spreading, convolution and interpolation on a fork
+// stream, the groups concurrently, joining s at the end.
 int batch_run_impl(pme_plan* const* plans, int n, hipStream_t s, const Fork* fork) {
   if (n < 0 || (n > 0 && plans == nullptr)) return PME_EINVAL;
   for (int i = 0; i < n; ++i) {
