@@ -1211,7 +1211,7 @@ __global__ __launch_bounds__(kPassThreads) void k_conv_z(Args a_in, BatchArgs bt
 
 // ---------------------------------------------------------------------------
 // k_conv_reg: the column convolution with register-resident transforms
-// (FP32 precisions; y and z pencils of 32 or 64 points).  A pencil of
+// (y and z pencils of 32 or 64 points; FP32 or FP64).  A pencil of
 // N = 8 R points is held by R lanes of one wavefront, 8 values per lane
 // (lane j holds points j + R r): a radix-8 DFT over r in registers, the
 // twiddles W_N^(j s), an R x 8 transpose through the wavefront's own LDS
@@ -1252,7 +1252,7 @@ __global__ __launch_bounds__(conv_reg_threads<G>()) void k_conv_reg(Args a_in, B
   constexpr int K1 = G::K1, K2 = G::K2, K3 = G::K3, KH = K1 / 2 + 1;
   constexpr int NT = conv_reg_threads<G>(), PB = conv_reg_pitch<G>();
   constexpr int RY = K2 / 8, EY = 8 / RY, RZ = K3 / 8, EZ = 8 / RZ;
-  static_assert(conv_reg_shape<G>() && P::fixed, "register transforms: FP32, 32 or 64 points");
+  static_assert(conv_reg_shape<G>(), "register transforms: 32 or 64 points");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);         // [z][y], pitch PB
   cplx<T>* scr0 = buf + K3 * PB;                            // transposes: 9 per lane
@@ -1801,7 +1801,7 @@ __host__ __device__ constexpr bool conv_split_ok() {
 }
 template <class P, class G>
 __host__ __device__ constexpr bool conv_reg_ok() {
-  return P::fixed && conv_reg_shape<G>() && conv_reg_lds_bytes<P, G>() <= kMaxLds;
+  return conv_reg_shape<G>() && conv_reg_lds_bytes<P, G>() <= kMaxLds;
 }
 template <class P, class G, int ORDER>
 __host__ __device__ constexpr bool interp_fused_ok() {
