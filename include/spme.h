@@ -201,8 +201,8 @@ int pme_batch_run(pme_plan *const *plans, int n, void *stream);
 #define PME_CONV_SPLIT 1   /* the same in three launches of row-chunk workgroups (forward y;
                               z, influence function, inverse z; inverse y), the half
                               spectrum in the workspace between them */
-#define PME_CONV_REG 2     /* one workgroup per x' column (FP32 precisions, y and z pencils of
-                              32 or 64 points): each pencil held in registers by a few lanes
+#define PME_CONV_REG 2     /* one workgroup per x' column (y and z pencils of 32 or 64
+                              points, every precision): each pencil held in registers by a few lanes
                               of one wavefront, radix-8 and radix-4/8 DFTs in registers with
                               one transpose through LDS between them; the forward z
                               transform, the influence function and the inverse z transform

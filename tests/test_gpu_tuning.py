@@ -6,7 +6,7 @@ binning chunk perform the same per-element arithmetic, so their forces are
 bit-identical and their energy/virial agree to summation order
 (bit-identical within one convolution variant); the register-resident
 convolution factors its transforms differently (radix 8 x 8 with its own
-twiddle order), so it agrees with them to FP32 rounding.  The autotuner's choice is
+twiddle order), so it agrees with them to the rounding of the precision.  The autotuner's choice is
 re-timed against the built-in default on the full-size workloads."""
 import ctypes
 import json
