@@ -28,10 +28,9 @@ from . import _lib
 from .plan import BatchPool
 
 # Request copies go straight to the HIP runtime the step library is linked
-# against (the process's one): torch's non-blocking copies of pinned memory
-# record a new event in its host allocator each time, and the runtime now
-# and then stalls the host for milliseconds growing the pool those events
-# draw on.
+# against (the process's one): a non-blocking torch copy of pinned memory
+# also records an event in torch's host allocator, which these copies, into
+# buffers that live as long as the server, do not need.
 _H2D, _D2H = 1, 2  # hipMemcpyKind
 
 
