@@ -624,7 +624,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner table")
     ap.add_argument("--profile-leg", default="",
                     help="for profilers: only `steps` host-launched evaluations of one leg "
-                         "(real, batched, or a workload name such as water_209715_k128_p4)")
+                         "(real, batched, or a workload name such as water_209715_k128_p4; "
+                         "a name ending in _fp64 runs that workload's plain FP64 path)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -917,6 +918,9 @@ def profile_leg(torch, dev, Plan, BatchPool, I, leg, steps):
         run = pool.launch
     else:
         named = {wl.name: wl for wl in (I.SMALL_32, I.HEADLINE_64, I.LARGE_128_P4, I.LARGE_128_P6)}
+        precision = "fp32_fixed"
+        if leg.endswith("_fp64"):  # a workload name with "_fp64": its plain FP64 path
+            leg, precision = leg[: -len("_fp64")], "fp64"
         if leg == "water_131070_k64x64x128":
             pos, q, box = stacked_water(I)
             K, order, beta = (64, 64, 128), 4, 0.34
@@ -926,7 +930,7 @@ def profile_leg(torch, dev, Plan, BatchPool, I, leg, steps):
             K, order, beta = wl.K, wl.order, wl.beta
         else:
             raise SystemExit(f"bench.py: unknown leg {leg!r}")
-        plan = Plan(K, order, beta, max_atoms=len(q), device=dev)
+        plan = Plan(K, order, beta, max_atoms=len(q), precision=precision, device=dev)
         dp, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
         run = lambda: plan.step(dp, dq, box)  # noqa: E731
     for _ in range(3):
@@ -936,7 +940,8 @@ def profile_leg(torch, dev, Plan, BatchPool, I, leg, steps):
     for _ in range(steps):
         run()
     torch.cuda.synchronize()
-    print(json.dumps({"leg": leg, "evaluations": steps,
+    print(json.dumps({"leg": leg, "precision": precision if leg not in ("real", "batched") else None,
+                      "evaluations": steps,
                       "us_per_evaluation": (time.perf_counter() - t0) / steps * 1e6, "mode": "profile"}))
 
 
