@@ -71,7 +71,7 @@ def test_batch_admission_answers_without_a_device(lib):
 def test_tuning_queries_without_a_device(lib):
     v = lib.pme_tuning_variants(64, 64, 64, 4, 1)
     assert v == 31                                   # every variant at 64^3
-    assert lib.pme_tuning_variants(64, 64, 64, 4, 0) == 15   # no register column in FP64
+    assert lib.pme_tuning_variants(64, 64, 64, 4, 0) == 31   # FP64 too (152 KB of LDS per column)
     assert lib.pme_tuning_variants(48, 48, 48, 4, 1) & 16 == 0  # 48-point pencils: no
     assert lib.pme_tuning_variants(16, 16, 16, 4, 1) == 1 | 4 | 8   # no split column passes
     assert lib.pme_tuning_variants(50, 50, 50, 4, 1) == 0
@@ -79,7 +79,7 @@ def test_tuning_queries_without_a_device(lib):
     assert lib.pme_default_tuning(64, 64, 64, 4, 1, ctypes.byref(t)) == 0
     assert t.as_dict() == {"conv": 2, "interp": 0, "bin_chunk": 1024}
     assert lib.pme_default_tuning(64, 64, 64, 4, 0, ctypes.byref(t)) == 0
-    assert t.as_dict() == {"conv": 0, "interp": 0, "bin_chunk": 1024}
+    assert t.as_dict() == {"conv": 2, "interp": 0, "bin_chunk": 1024}
     assert lib.pme_default_tuning(48, 48, 48, 4, 1, ctypes.byref(t)) == 0
     assert t.as_dict() == {"conv": 0, "interp": 0, "bin_chunk": 1024}
     assert lib.pme_default_tuning(128, 128, 128, 6, 1, ctypes.byref(t)) == 0
@@ -170,3 +170,41 @@ def test_slots_per_system_cap(srv):
     y = srv._free_slot(3)
     y.busy = True
     assert srv._free_slot(3) is None
+
+
+def test_kept_forces_copied_out_in_chunks():
+    # the serving loop copies a kept request's forces out of the slot's
+    # pinned buffer a chunk per loop turn, releasing the slot only after the
+    # last chunk; two requests queue in completion order
+    import numpy as np
+    import torch
+
+    class Slot:
+        busy = True
+
+    class Req:
+        pass
+
+    class Stub:
+        COPY_CHUNK = S.Server.COPY_CHUNK
+
+    rng = np.random.default_rng(7)
+    reqs = []
+    for n in (S.Server.COPY_CHUNK * 2 + 5, 17):
+        r = Req()
+        r.slot = Slot()
+        r.slot.host_f = torch.from_numpy(rng.standard_normal((n, 3)))
+        r.forces = np.empty((n, 3))
+        r.copied = 0
+        reqs.append(r)
+    pending = list(reqs)
+    turns = 0
+    while pending:
+        S.Server._copy_kept(Stub(), pending)
+        turns += 1
+        if reqs[0] in pending:
+            assert reqs[0].slot.busy and reqs[1].slot.busy
+    assert turns == 4  # three chunks, then the small request
+    for r in reqs:
+        assert not r.slot.busy
+        assert np.array_equal(r.forces, r.slot.host_f.numpy())
