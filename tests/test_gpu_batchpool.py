@@ -180,3 +180,30 @@ def test_pool_autotune_keeps_results(P):
         torch.cuda.synchronize()
         assert torch.equal(pool.io(s)[2], f) and torch.equal(pool.io(s)[3], e), m.index
     pool.close()
+
+
+def test_pool_mixed_binning_chunks_in_one_grid(P):
+    # systems of one grid shape with different binning chunks form separate
+    # groups (each group bins with one chunk size on its fork stream); every
+    # result equals the system's own single step with that chunk
+    mix = [m for m in I.batch_mix(n_systems=12, seed=41, lo=600, hi=20000) if m.K == 32][:4]
+    assert len(mix) >= 3
+    stream = torch.cuda.Stream()
+    pool = P.BatchPool(1 << 30, max_systems=8, stream=stream)
+    with torch.cuda.stream(stream):
+        slots = admit_all(P, pool, mix)
+    chunks = [256, 1024, 512, 1024][: len(slots)]
+    refs = []
+    for (s, m, pos, q, box), c in zip(slots, chunks):
+        pool.set_tuning(s, bin_chunk=c)
+        plan = P.Plan(m.K, 4, 0.34, max_atoms=len(q))
+        plan.set_tuning(bin_chunk=c)
+        f, e = plan.step(dev(pos), dev(q), box)
+        torch.cuda.synchronize()
+        refs.append((f.clone(), e.clone()))
+    pool.launch()
+    stream.synchronize()
+    for (s, m, *_), (fr, er) in zip(slots, refs):
+        _, _, f, e = pool.io(s)
+        assert torch.equal(f, fr) and torch.equal(e, er), m.index
+    pool.close()
