@@ -298,7 +298,10 @@ int pme_batch_destroy(pme_batch *b);
 
 /* Admit a system: PME_EBUSY when every slot is taken or no free range of
  * the arena is large enough (nothing changes then); otherwise *slot is its
- * handle.  Argument errors as for pme_create and pme_bind. */
+ * handle.  Argument errors as for pme_create and pme_bind.  The system's
+ * plan starts from pme_default_tuning, except that a grid with K1 other
+ * than 64 and 128 takes PME_INTERP_SPLIT (faster in batched launches);
+ * pme_set_tuning on pme_batch_plan(b, slot) changes it. */
 int pme_batch_admit(pme_batch *b, const pme_system_desc *s, int *slot);
 
 /* New inputs/outputs of an admitted system (as pme_bind, on the batch's

@@ -1007,6 +1007,19 @@ int pme_batch_admit(pme_batch* b, const pme_system_desc* s, int* slot) {
   }
   int rc = pme_create(&sl.plan, s->K1, s->K2, s->K3, s->order, s->beta, s->max_atoms,
                       s->precision, 0, 0.0, b->arena + off, ws_bytes, b->stream);
+  if (rc == PME_OK && s->K1 != 64 && s->K1 != 128) {
+    // In a batched launch the chip is full, so work counts more than
+    // launches: the fused interpolation transforms p (R + p - 1) / R times
+    // the grid's x rows (each tile those it reads), the split form each row
+    // once.  Where the rows have no register transform (K1 other than 64
+    // and 128) the split form is the batch's choice.
+    pme_tuning t;
+    if (pme_get_tuning(sl.plan, &t) == PME_OK && t.interp != PME_INTERP_SPLIT) {
+      t.interp = PME_INTERP_SPLIT;
+      rc = pme_set_tuning(sl.plan, &t);
+      if (rc != PME_OK) pme_destroy(sl.plan);
+    }
+  }
   if (rc == PME_OK) {
     rc = pme_bind(sl.plan, sl.pos, sl.q, s->N, s->box, sl.forces, 0, sl.ev);
     if (rc != PME_OK) pme_destroy(sl.plan);

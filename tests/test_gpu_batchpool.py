@@ -2,7 +2,8 @@
 arena by footprint, their buffers carved from it, one launch over any set of
 slots with grid groups on forked streams; every result bit-identical to the
 system's own single step, under graph replay too; retire and re-admit reuse
-arena ranges; a full arena answers PME_EBUSY.  Also: pme_bind is
+arena ranges; a full arena answers PME_EBUSY; admission takes the split
+interpolation on grids without register x transforms.  Also: pme_bind is
 stream-ordered (a rebind does not disturb a batched run enqueued before
 it)."""
 import numpy as np
@@ -26,8 +27,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
 
 
-def single(P, m, pos, q, box):
+def single(P, m, pos, q, box, tuning=None):
     plan = P.Plan(m.K, 4, 0.34, max_atoms=len(q))
+    if tuning is not None:
+        plan.set_tuning(**tuning)
     f, e = plan.step(dev(pos), dev(q), box)
     torch.cuda.synchronize()
     return f.clone(), e.clone()
@@ -56,7 +59,12 @@ def test_pool_matches_single_steps_and_graph(P):
     st = pool.stats()
     assert st["admitted"] == len(mix) and st["bytes_used"] == sum(
         P.BatchPool.footprint(m.K, 4, len(q)) for _, m, _, q, _ in slots)
-    refs = [single(P, m, pos, q, box) for _, m, pos, q, box in slots]
+    # admission's variants: the single plan's, with the split interpolation
+    # where the x rows have no register transform
+    for s, m, *_ in slots:
+        t = pool.tuning_of(s)
+        assert t["interp"] == (0 if m.K == 64 else 1), (m.K, t)
+    refs = [single(P, m, pos, q, box, pool.tuning_of(s)) for s, m, pos, q, box in slots]
     pool.launch()
     stream.synchronize()
     for (s, m, *_), (fr, er) in zip(slots, refs):
@@ -113,10 +121,10 @@ def test_pool_busy_retire_readmit(P):
         qq.copy_(dev(q_mid))
         pool.launch()
     stream.synchronize()
-    fr, er = single(P, m_mid, pos_mid, q_mid, box_mid)
+    fr, er = single(P, m_mid, pos_mid, q_mid, box_mid, pool.tuning_of(s_new))
     assert torch.equal(pool.io(s_new)[2], fr) and torch.equal(pool.io(s_new)[3], er)
     for s, mm, pos_, q_, box_ in (first[0], first[2]):
-        f2, e2 = single(P, mm, pos_, q_, box_)
+        f2, e2 = single(P, mm, pos_, q_, box_, pool.tuning_of(s))
         assert torch.equal(pool.io(s)[2], f2) and torch.equal(pool.io(s)[3], e2)
     # update: fewer atoms and a new box through the carved buffers
     s0, m0, pos0, q0, box0 = first[0]
@@ -125,7 +133,7 @@ def test_pool_busy_retire_readmit(P):
         pool.update(s0, n, box0 * 1.01)
         pool.launch([s0])
     stream.synchronize()
-    f3, e3 = single(P, m0, pos0[:n], q0[:n], box0 * 1.01)
+    f3, e3 = single(P, m0, pos0[:n], q0[:n], box0 * 1.01, pool.tuning_of(s0))
     assert torch.equal(pool.io(s0)[2][:n], f3) and torch.equal(pool.io(s0)[3], e3)
     assert pool.check(s0) == 0
     pool.close()
@@ -197,7 +205,7 @@ def test_pool_mixed_binning_chunks_in_one_grid(P):
     for (s, m, pos, q, box), c in zip(slots, chunks):
         pool.set_tuning(s, bin_chunk=c)
         plan = P.Plan(m.K, 4, 0.34, max_atoms=len(q))
-        plan.set_tuning(bin_chunk=c)
+        plan.set_tuning(**pool.tuning_of(s))
         f, e = plan.step(dev(pos), dev(q), box)
         torch.cuda.synchronize()
         refs.append((f.clone(), e.clone()))
