@@ -215,3 +215,38 @@ def test_pool_mixed_binning_chunks_in_one_grid(P):
         _, _, f, e = pool.io(s)
         assert torch.equal(f, fr) and torch.equal(e, er), m.index
     pool.close()
+
+
+def test_pool_admission_variants_match_the_oracle(P):
+    # one system of each grid group, in the variants admission picked (the
+    # split interpolation on 32^3 and 48^3), against the FP64 oracle at the
+    # FP32/fixed bars: force relative RMS, the worst component (extreme-value
+    # factor of 3N independent errors), energy and virial
+    import oracle
+    mix = I.batch_mix(n_systems=12, seed=41, lo=600, hi=20000)
+    pick = {}
+    for m in mix:
+        pick.setdefault(m.K, m)
+    assert set(pick) == {32, 48, 64}
+    stream = torch.cuda.Stream()
+    pool = P.BatchPool(1 << 30, max_systems=4, stream=stream)
+    with torch.cuda.stream(stream):
+        slots = admit_all(P, pool, [pick[k] for k in (32, 48, 64)])
+    pool.launch()
+    stream.synchronize()
+    for s, m, pos, q, box in slots:
+        assert pool.tuning_of(s)["interp"] == (0 if m.K == 64 else 1)
+        ref = oracle.spme(pos, q, box, m.K, 4, 0.34)
+        _, _, f, e = pool.io(s)
+        f, e = f.cpu().numpy(), e.cpu().numpy()
+        rms = np.sqrt(np.mean(ref["forces"] ** 2))
+        fr = np.linalg.norm(f - ref["forces"]) / np.linalg.norm(ref["forces"])
+        worst = np.abs(f - ref["forces"]).max() / rms
+        er = abs(e[0] - ref["E"]) / abs(ref["E"])
+        vr = np.abs(e[1:] - ref["virial"]).max() / abs(ref["E"])
+        print(f"K={m.K} atoms={len(q)} force {fr:.2e} worst {worst:.2e} energy {er:.2e} "
+              f"virial {vr:.2e}", flush=True)
+        assert fr <= 1e-5
+        assert worst <= 1e-5 * np.sqrt(2.0 * np.log(3.0 * len(q)))
+        assert er <= 1e-6 and vr <= 2e-6
+    pool.close()

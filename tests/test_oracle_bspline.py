@@ -91,7 +91,28 @@ def test_moduli_closed_forms(orc):
             np.testing.assert_allclose(b[1:], b[1:][::-1], rtol=1e-13)
 
 
+def test_odd_order_moduli_closed_forms(orc):
+    # For odd p the denominator sum_k M_p(k+1) exp(i k theta), theta = 2 pi m/K,
+    # is exp(i (p-2) theta/2) times a real cosine polynomial: with the integer
+    # values 1/2, 1/2 (p = 3) and 1/24, 11/24, 11/24, 1/24 (p = 5, checked
+    # against the truncated-power form), |b(m)|^2 = 1/cos^2(theta/2) and
+    # 1/((2 cos(3 theta/2) + 22 cos(theta/2))/24)^2.  Both vanish at the
+    # Nyquist index m = K/2, the only entry left to the reading below.
+    assert truncated_power_M(5, 1) == pytest.approx(1 / 24, abs=1e-15)
+    assert truncated_power_M(5, 2) == pytest.approx(11 / 24, abs=1e-15)
+    for K in (16, 32, 48):
+        m = np.arange(K)
+        th = 2 * np.pi * m / K
+        reg = m != K // 2
+        d3 = np.cos(th / 2) ** 2
+        d5 = ((2 * np.cos(1.5 * th) + 22 * np.cos(th / 2)) / 24) ** 2
+        np.testing.assert_allclose(orc.moduli(3, K)[reg], 1.0 / d3[reg], rtol=1e-12)
+        np.testing.assert_allclose(orc.moduli(5, K)[reg], 1.0 / d5[reg], rtol=1e-12)
+
+
 def test_odd_order_nyquist_is_finite(orc):
+    # reading: the vanishing Nyquist denominator of an odd order takes the
+    # mean of its two neighbours (the GPU path supports even orders only)
     b = orc.moduli(5, 32)
     assert np.all(np.isfinite(b))
     assert b[16] == pytest.approx(0.5 * (b[15] + b[17]))
