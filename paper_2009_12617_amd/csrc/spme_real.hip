@@ -13,8 +13,9 @@
 //   k_rs_scan    one workgroup: exclusive prefix sum of the counts
 //   k_rs_fill    atoms into cell order (position, charge, original index)
 //   k_rs_pairs   kRsBlocks workgroups per cell: its atoms, 2 to 8 lanes each, against
-//                the atoms of the 27 neighbour cells staged in LDS with their
-//                periodic shifts applied; pairs inside the cutoff are queued
+//                the atoms of the 27 neighbour cells that lie within the
+//                cutoff of the home atoms' bounding box, staged in LDS with
+//                their periodic shifts applied; pairs inside the cutoff are queued
 //                per wavefront and evaluated in batches of 64; then each
 //                atom's excluded partners; forces to the caller's order
 //   k_rs_reduce  energies from the per-workgroup rows, in a fixed order
@@ -39,7 +40,9 @@ constexpr int kRsMaxSplit = 8;      // most lanes sharing one home atom's candid
 constexpr int kRsBlocks = 4;        // pair workgroups per cell (home atoms dealt out in passes)
 constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (< 2^24)
 constexpr int kRsUnroll = 2;        // candidates each lane tests per step
+constexpr int kRsPer = 4;           // neighbour atoms each thread reads per staging pass
 static_assert(kRsStage % (kRsMaxSplit * kRsUnroll) == 0, "the padded stage must fit");
+static_assert(kRsPer * kRsThreads >= kRsStage, "one staging pass reads the whole stage");
 constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
 static_assert((kRsQueue & (kRsQueue - 1)) == 0 && kRsQueue >= 64 + 64 * kRsUnroll,
               "a wavefront's ring holds under 64 leftovers plus one step's hits");
@@ -242,6 +245,8 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   __shared__ double hf[kRsHome][3];
   __shared__ int queue[kRsThreads / 64][kRsQueue];
   __shared__ double wred[16 * 8];
+  __shared__ double hbox[6];                  // home pass bounding box: low x y z, high x y z
+  __shared__ int kept[kRsThreads / 64];       // staged atoms kept per wavefront
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cell = blockIdx.x, blk = blockIdx.y;
   const int cx = cell % a.nc[0], cy = (cell / a.nc[0]) % a.nc[1], cz = cell / (a.nc[0] * a.nc[1]);
@@ -299,6 +304,22 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
       home[tid] = a.rec[hb + tid];
       hf[tid][0] = hf[tid][1] = hf[tid][2] = 0.0;
     }
+    if (wave == 0) {  // the bounding box of this pass's home atoms (nh <= 64)
+      const double4 h = a.rec[hb + min(tid, nh - 1)];
+      double bx[6] = {h.x, h.y, h.z, h.x, h.y, h.z};
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bx[c] = fmin(bx[c], __shfl_xor(bx[c], d));
+          bx[3 + c] = fmax(bx[3 + c], __shfl_xor(bx[3 + c], d));
+        }
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) hbox[c] = bx[c];
+      }
+    }
     // an idle lane sits far from every atom and never finds a pair
     double4 ri = make_double4(-1e30, -1e30, -1e30, 0.0);
     int ii = -1;
@@ -307,23 +328,56 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
       ii = a.ridx[hb + slot];
     }
     for (int s0 = 0; s0 < total; s0 += kRsStage) {
-      const int sn = min(kRsStage, total - s0);
+      // kRsStage neighbour atoms (with their periodic shifts) are read per
+      // pass, kRsPer consecutive ones per thread, and only those within the
+      // cutoff of the home atoms' bounding box are staged, in their original
+      // order (a scan over the workgroup): no partner of a home atom inside
+      // the cutoff is dropped (the box test is a lower bound of every
+      // home-candidate distance, with a margin for its rounding)
+      const int sr = min(kRsStage, total - s0);
+      __syncthreads();
+      double4 cand[kRsPer];
+      unsigned keep = 0u;
+      const int tb = tid * kRsPer;
+      if (tb < sr) {
+        const double lim = a.rc2 * (1.0 + 1e-12) + 1e-12;
+        int k = 0;
+#pragma unroll
+        for (int j = 0; j < kRsPer; ++j) {
+          const int g = s0 + tb + j;
+          if (tb + j < sr) {
+            while (nb_pre[k + 1] <= g) ++k;
+            const double4 r = a.rec[nb_start[k] + (g - nb_pre[k])];
+            cand[j] = make_double4(r.x + nb_shift[k][0], r.y + nb_shift[k][1], r.z + nb_shift[k][2], r.w);
+            const double dx = fmax(fmax(hbox[0] - cand[j].x, cand[j].x - hbox[3]), 0.0);
+            const double dy = fmax(fmax(hbox[1] - cand[j].y, cand[j].y - hbox[4]), 0.0);
+            const double dz = fmax(fmax(hbox[2] - cand[j].z, cand[j].z - hbox[5]), 0.0);
+            if (dx * dx + dy * dy + dz * dz <= lim) keep |= 1u << j;
+          }
+        }
+      }
+      const int c = __popc(keep);
+      int inc = c;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+      }
+      if (lane == 63) kept[wave] = inc;
+      __syncthreads();
+      int sn = 0, o = inc - c;
+#pragma unroll
+      for (int w = 0; w < kRsThreads / 64; ++w) {
+        if (w < wave) o += kept[w];
+        sn += kept[w];
+      }
+#pragma unroll
+      for (int j = 0; j < kRsPer; ++j)
+        if (keep & (1u << j)) stage[o++] = cand[j];
       // padded to whole steps with atoms far away (never inside the cutoff);
       // kRsStage is a multiple of every step S * kRsUnroll
       const int snp = (sn + S * kRsUnroll - 1) / (S * kRsUnroll) * (S * kRsUnroll);
-      __syncthreads();
-      for (int t = tid; t < snp; t += kRsThreads) {
-        if (t >= sn) {
-          stage[t] = make_double4(1e30, 1e30, 1e30, 0.0);
-          continue;
-        }
-        const int g = s0 + t;
-        int k = 0;
-        while (nb_pre[k + 1] <= g) ++k;
-        const int src = nb_start[k] + (g - nb_pre[k]);
-        const double4 r = a.rec[src];
-        stage[t] = make_double4(r.x + nb_shift[k][0], r.y + nb_shift[k][1], r.z + nb_shift[k][2], r.w);
-      }
+      for (int t = sn + tid; t < snp; t += kRsThreads) stage[t] = make_double4(1e30, 1e30, 1e30, 0.0);
       __syncthreads();
       if (wave * 64 >= S * nh) continue;  // no active lane in this wavefront
       // ring of queued pairs: head qh, length qn (uniform over the wavefront)
