@@ -8,10 +8,10 @@
 // least three cells of edge >= rcut per axis (so the 27 neighbour cells of
 // a cell are distinct and minimum-image pairs within rcut are found once):
 //   k_rs_zero    clear the cell counts
-//   k_rs_count   wrap each atom into the cell, count atoms per cell; sum q^2
+//   k_rs_count   wrap each atom into its cell, count atoms per (cell, octant); sum q^2
 //                per workgroup (self term)
 //   k_rs_scan    one workgroup: exclusive prefix sum of the counts
-//   k_rs_fill    atoms into cell order (position, charge, original index)
+//   k_rs_fill    atoms into (cell, octant) order (position, charge, original index)
 //   k_rs_pairs   kRsBlocks workgroups per cell: its atoms, 2 to 8 lanes each, against
 //                the atoms of the 27 neighbour cells that lie within the
 //                cutoff of the home atoms' bounding box, staged in LDS with
@@ -37,7 +37,7 @@ namespace {
 constexpr int kRsThreads = 128;     // threads of a pair workgroup (two wavefronts)
 constexpr int kRsHome = kRsThreads / 2;  // most home atoms per pass (two lanes each)
 constexpr int kRsMaxSplit = 8;      // most lanes sharing one home atom's candidates
-constexpr int kRsBlocks = 4;        // pair workgroups per cell (home atoms dealt out in passes)
+constexpr int kRsBlocks = 2;        // pair workgroups per cell (each a half of its atoms, in passes)
 constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (< 2^24)
 constexpr int kRsUnroll = 2;        // candidates each lane tests per step
 constexpr int kRsPer = 4;           // neighbour atoms each thread reads per staging pass
@@ -52,6 +52,11 @@ constexpr int kRsChebShort = 24;    // terms enough for beta rcut <= kRsShortRan
 constexpr double kRsShortRange = 3.2;  // 24 terms: <= 1.3e-14 relative up to here
 constexpr double kRsMaxBetaRcut = 6.0;  // series error <= 2e-14 relative up to here
 constexpr int kRsScanThreads = 1024;
+// Atoms are ordered by cell and, inside a cell, by octant (x half fastest),
+// so that the contiguous share of a cell's atoms each pair workgroup takes
+// is compact in space (its bounding box, which bounds the candidates staged
+// for it, is then smaller than the cell).
+constexpr int kRsOct = 8;
 
 struct RsArgs {
   int N, nc[3], ncell, n_count_blocks;
@@ -69,9 +74,9 @@ struct RsArgs {
   int accumulate;
   double* energies;
   // workspace
-  unsigned* count;      // [ncell]
-  unsigned* start;      // [ncell + 1]
-  unsigned* cursor;     // [ncell]
+  unsigned* count;      // [ncell * kRsOct]: per (cell, octant)
+  unsigned* start;      // [ncell * kRsOct + 1]
+  unsigned* cursor;     // [ncell * kRsOct]
   double4* rec;         // [N] wrapped position and charge, in cell order
   int* ridx;            // [N] original index, in cell order
   double* rows;         // [nrow][2] pair and exclusion energies; then [n_count_blocks] q^2 sums
@@ -85,19 +90,22 @@ __device__ __forceinline__ double wrap(double x, double L, double invL) {
 }
 
 __device__ __forceinline__ int cell_of(const RsArgs& a, double x, double y, double z) {
-  int c[3];
+  // (cell, octant): cell index times kRsOct plus the octant bits x | y << 1 | z << 2
+  int c[3], o = 0;
   const double w[3] = {x, y, z};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    c[d] = (int)(w[d] * a.cell_inv[d]);
+    const double u = w[d] * a.cell_inv[d];
+    c[d] = (int)u;
     if (c[d] >= a.nc[d]) c[d] = a.nc[d] - 1;
     if (c[d] < 0) c[d] = 0;
+    o |= (u - c[d] >= 0.5 ? 1 : 0) << d;
   }
-  return (c[2] * a.nc[1] + c[1]) * a.nc[0] + c[0];
+  return ((c[2] * a.nc[1] + c[1]) * a.nc[0] + c[0]) * kRsOct + o;
 }
 
 __global__ __launch_bounds__(256) void k_rs_zero(RsArgs a) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x)
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell * kRsOct; c += gridDim.x * blockDim.x)
     a.count[c] = 0u;
 }
 
@@ -155,9 +163,10 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(RsArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) carry = 0u;
   __syncthreads();
-  for (int c0 = 0; c0 < a.ncell; c0 += kRsScanThreads) {
+  const int nsub = a.ncell * kRsOct;
+  for (int c0 = 0; c0 < nsub; c0 += kRsScanThreads) {
     const int c = c0 + tid;
-    const unsigned v = c < a.ncell ? a.count[c] : 0u;
+    const unsigned v = c < nsub ? a.count[c] : 0u;
     unsigned x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(RsArgs a) {
     __syncthreads();
     unsigned before = carry;
     for (int w = 0; w < wave; ++w) before += wsum[w];
-    if (c < a.ncell) {
+    if (c < nsub) {
       a.start[c] = before + x - v;
       a.cursor[c] = before + x - v;
     }
@@ -176,7 +185,7 @@ __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(RsArgs a) {
     if (tid == kRsScanThreads - 1) carry = before + x;
     __syncthreads();
   }
-  if (tid == 0) a.start[a.ncell] = carry;
+  if (tid == 0) a.start[nsub] = carry;
 }
 
 __global__ __launch_bounds__(256) void k_rs_fill(RsArgs a) {
@@ -271,8 +280,8 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
       nb_shift[tid][d] = sh;
     }
     const int nbc = (n3[2] * a.nc[1] + n3[1]) * a.nc[0] + n3[0];
-    nb_start[tid] = (int)a.start[nbc];
-    nb_pre[tid + 1] = (int)(a.start[nbc + 1] - a.start[nbc]);
+    nb_start[tid] = (int)a.start[nbc * kRsOct];
+    nb_pre[tid + 1] = (int)(a.start[(nbc + 1) * kRsOct] - a.start[nbc * kRsOct]);
   }
   __syncthreads();
   if (tid == 0) {
@@ -281,12 +290,13 @@ __global__ __launch_bounds__(kRsThreads, 3) void k_rs_pairs(RsArgs a) {
   }
   __syncthreads();
   const int total = nb_pre[27];
-  const int h0 = (int)a.start[cell], h1 = (int)a.start[cell + 1];
+  const int h0 = (int)a.start[cell * kRsOct], h1 = (int)a.start[(cell + 1) * kRsOct];
   const double two_over_sqrtpi = 1.12837916709551257390;
   double e_pair = 0.0, e_excl = 0.0;
   int* wq = queue[wave];
-  // Home atoms of the cell dealt evenly over its kRsBlocks workgroups, in
-  // passes of at most kRsHome.  S lanes share a home atom (S = 2, 4 or 8,
+  // Home atoms of the cell (in octant order) dealt in contiguous chunks over
+  // its kRsBlocks workgroups -- a half each for cells of up to 2 kRsHome
+  // atoms -- in passes of at most kRsHome.  S lanes share a home atom (S = 2, 4 or 8,
   // the most that fit the workgroup: lane L takes home L mod nh and every
   // S-th candidate from L / nh), so a sparsely filled pass still spreads its
   // candidate tests over the whole workgroup.  Each lane tests its
@@ -487,9 +497,10 @@ RsLayout rs_layout(int max_atoms, int max_cells) {
   const int nblk = (max_atoms + kRsCountThreads - 1) / kRsCountThreads;
   RsLayout L{};
   size_t o = 0;
-  L.count = o;   o = align256(o + (size_t)max_cells * sizeof(unsigned));
-  L.start = o;   o = align256(o + ((size_t)max_cells + 1) * sizeof(unsigned));
-  L.cursor = o;  o = align256(o + (size_t)max_cells * sizeof(unsigned));
+  const size_t nsub = (size_t)max_cells * kRsOct;
+  L.count = o;   o = align256(o + nsub * sizeof(unsigned));
+  L.start = o;   o = align256(o + (nsub + 1) * sizeof(unsigned));
+  L.cursor = o;  o = align256(o + nsub * sizeof(unsigned));
   L.rec = o;     o = align256(o + (size_t)max_atoms * sizeof(double4));
   L.ridx = o;    o = align256(o + (size_t)max_atoms * sizeof(int));
   L.rows = o;    o = align256(o + (2 * (size_t)max_cells * kRsBlocks + nblk) * sizeof(double));
@@ -603,7 +614,7 @@ int pme_real(const double* pos, const double* q, int N, const double box[9], dou
   a.rows = reinterpret_cast<double*>(ws + W.rows);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nb = (N + 255) / 256;
-  k_rs_zero<<<dim3((a.ncell + 255) / 256), dim3(256), 0, s>>>(a);
+  k_rs_zero<<<dim3((a.ncell * kRsOct + 255) / 256), dim3(256), 0, s>>>(a);
   if (N > 0) {
     k_rs_count<<<dim3(a.n_count_blocks), dim3(kRsCountThreads), 0, s>>>(a);
   }
