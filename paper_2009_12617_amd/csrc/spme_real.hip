@@ -38,12 +38,12 @@ constexpr int kRsThreads = 128;     // threads of a pair workgroup (two wavefron
 constexpr int kRsHome = kRsThreads / 2;  // most home atoms per pass (two lanes each)
 constexpr int kRsMaxSplit = 8;      // most lanes sharing one home atom's candidates
 constexpr int kRsBlocks = 2;        // pair workgroups per cell (each a half of its atoms, in passes)
-constexpr int kRsStage = 448;       // neighbour atoms staged in LDS per pass (< 2^24)
-constexpr int kRsUnroll = 2;        // candidates each lane tests per step
+constexpr int kRsStage = 512;       // neighbour atoms staged in LDS per pass (< 2^24)
+constexpr int kRsUnroll = 4;        // candidates each lane tests per step
 constexpr int kRsPer = 4;           // neighbour atoms each thread reads per staging pass
 static_assert(kRsStage % (kRsMaxSplit * kRsUnroll) == 0, "the padded stage must fit");
 static_assert(kRsPer * kRsThreads >= kRsStage, "one staging pass reads the whole stage");
-constexpr int kRsQueue = 256;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
+constexpr int kRsQueue = 512;       // ring of queued pairs per wavefront (>= 64 + 64 kRsUnroll, 2^n)
 static_assert((kRsQueue & (kRsQueue - 1)) == 0 && kRsQueue >= 64 + 64 * kRsUnroll,
               "a wavefront's ring holds under 64 leftovers plus one step's hits");
 constexpr int kRsCountThreads = 256;
