@@ -52,6 +52,7 @@ constexpr int kRsChebShort = 24;    // terms enough for beta rcut <= kRsShortRan
 constexpr double kRsShortRange = 3.2;  // 24 terms: <= 1.3e-14 relative up to here
 constexpr double kRsMaxBetaRcut = 6.0;  // series error <= 2e-14 relative up to here
 constexpr int kRsScanThreads = 1024;
+constexpr int kRsScanPre = 8;       // chunks of counts the scan loads at once
 // Atoms are ordered by cell and, inside a cell, by octant (x half fastest),
 // so that the contiguous share of a cell's atoms each pair workgroup takes
 // is compact in space (its bounding box, which bounds the candidates staged
@@ -158,32 +159,45 @@ __global__ __launch_bounds__(kRsCountThreads) void k_rs_count(RsArgs a) {
 
 // Exclusive prefix sum of the counts by one workgroup, in chunks of its size.
 __global__ __launch_bounds__(kRsScanThreads) void k_rs_scan(RsArgs a) {
+  // the counts of up to kRsScanPre chunks of kRsScanThreads are loaded at
+  // once, then scanned chunk by chunk from registers
   __shared__ unsigned wsum[kRsScanThreads / 64];
   __shared__ unsigned carry;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) carry = 0u;
   __syncthreads();
   const int nsub = a.ncell * kRsOct;
-  for (int c0 = 0; c0 < nsub; c0 += kRsScanThreads) {
-    const int c = c0 + tid;
-    const unsigned v = c < nsub ? a.count[c] : 0u;
-    unsigned x = v;
+  for (int s0 = 0; s0 < nsub; s0 += kRsScanThreads * kRsScanPre) {
+    unsigned pv[kRsScanPre];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const unsigned y = __shfl_up(x, d, 64);
-      if (lane >= d) x += y;
+    for (int i = 0; i < kRsScanPre; ++i) {
+      const int c = s0 + i * kRsScanThreads + tid;
+      pv[i] = c < nsub ? a.count[c] : 0u;
     }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    unsigned before = carry;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    if (c < nsub) {
-      a.start[c] = before + x - v;
-      a.cursor[c] = before + x - v;
+#pragma unroll
+    for (int i = 0; i < kRsScanPre; ++i) {
+      const int c0 = s0 + i * kRsScanThreads;
+      if (c0 >= nsub) break;  // uniform
+      const int c = c0 + tid;
+      const unsigned v = pv[i];
+      unsigned x = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const unsigned y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      if (lane == 63) wsum[wave] = x;
+      __syncthreads();
+      unsigned before = carry;
+      for (int w = 0; w < wave; ++w) before += wsum[w];
+      if (c < nsub) {
+        a.start[c] = before + x - v;
+        a.cursor[c] = before + x - v;
+      }
+      __syncthreads();
+      if (tid == kRsScanThreads - 1) carry = before + x;
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == kRsScanThreads - 1) carry = before + x;
-    __syncthreads();
   }
   if (tid == 0) a.start[nsub] = carry;
 }
